@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle to the paper and to mathematics (no GPU).
+
+Every oracle function is checked against something other than itself: values
+printed in the paper (tests/golden/paper_examples.json), exhaustive brute force
+on tiny inputs, library routines (numpy, Python integers and floats), closed
+forms and invariants (ring morphism, field axioms, Lagrange, Frobenius).
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0809_0063_amd import inputs
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+
+
+# --- worked examples ----------------------------------------------------------------
+
+def test_kronecker_example():
+    g = GOLDEN["kronecker_example"]
+    a_eval, b_eval = O.dqt_int(g["a"], g["q"]), O.dqt_int(g["b"], g["q"])
+    assert (a_eval, b_eval) == (g["a_eval"], g["b_eval"])
+    assert a_eval * b_eval == g["product_eval"]
+    assert O.radix_digits(a_eval * b_eval, g["q"], 3) == g["digits"]
+    assert [d % g["p"] for d in g["digits"]] == g["result"]
+    got = O.polymul(np.array([g["a"]], np.uint8), np.array([g["b"]], np.uint8), g["p"])
+    assert got.tolist() == [g["result"]]
+
+
+def test_redq_example_p_divides_q():
+    g = GOLDEN["redq_p_divides_q"]
+    r = O.dqt_int(g["a"], g["q"]) * O.dqt_int(g["b"], g["q"])
+    assert r == g["r"]
+    s, u, mu = O.redq_steps(r, g["p"], g["q"], 5)
+    assert s == g["s"]
+    assert u == g["result"] and mu == g["result"]
+    assert O.polymul(np.array([g["a"]], np.uint8) % 5, np.array([g["b"]], np.uint8) % 5, 5).tolist() == [g["result"]]
+
+
+def test_redq_example_full():
+    g = GOLDEN["redq_full"]
+    r = O.dqt_int(g["R"], g["q"])
+    assert r == g["r"]
+    s, u, mu = O.redq_steps(r, g["p"], g["q"], 4)
+    assert s == g["s"] and u == g["u"] and mu == g["mu"]
+    assert mu == [c % g["p"] for c in g["R"]]
+    assert O.correct_direct(g["u"], g["q"], g["p"]) == g["mu"]
+    e = GOLDEN["q_matrix_entry"]
+    assert O.q_matrix(4, e["q"], e["p"])[0][1] == e["value"]
+
+
+def test_redq_theorem_random():
+    """Theorem thm:REDQ: 0 <= u_i < p and mu_i = digit_i mod p, for random words and bases."""
+    g = np.random.default_rng(1)
+    for _ in range(3000):
+        p = int(g.choice([2, 3, 5, 7, 11, 13, 23, 101, 251]))
+        q = int(g.integers(p + 1, 5000))
+        nres = int(g.integers(1, 8))
+        digits = [int(x) for x in g.integers(0, q, size=nres - 1)] + [int(g.integers(0, 10 ** 6))]
+        r = sum(d * q ** i for i, d in enumerate(digits))
+        s, u, mu = O.redq_steps(r, p, q, nres)
+        assert s == r // p
+        assert all(0 <= x < p for x in u)
+        assert mu == [d % p for d in digits]
+
+
+def test_floor_lemma():
+    """Lemma lem:flfl: floor(floor(r/b)/a) = floor(r/(ab)) = floor(floor(r/a)/b)."""
+    g = np.random.default_rng(2)
+    for _ in range(2000):
+        r = int(g.integers(0, 2 ** 62))
+        a, b = int(g.integers(1, 10 ** 6)), int(g.integers(1, 10 ** 6))
+        assert (r // b) // a == r // (a * b) == (r // a) // b
+
+
+# --- correction tables (time-memory trade-off) ---------------------------------------
+
+def test_tmto_example_exhaustive():
+    g = GOLDEN["tmto"]
+    k, j = g["residues"], g["table_window"]
+    for p, q in [(3, 64), (3, 128), (5, 64), (7, 2 ** 7)]:
+        for u in itertools.product(range(p), repeat=k) if p == 3 else [
+                list(np.random.default_rng(p).integers(0, p, size=k)) for _ in range(500)]:
+            mu, acc = O.correct_by_tables(list(u), q, p, j)
+            assert mu == O.correct_direct(list(u), q, p)
+            assert acc == g["accesses"]
+
+
+def test_tmto_access_count_reading():
+    """The access count is ceil((k-1)/(j-1)); the printed floor undercounts (k=8, j=4)."""
+    for k in range(2, 12):
+        for j in range(2, k + 1):
+            u = [1] * k
+            _, acc = O.correct_by_tables(u, 64, 3, j)
+            assert acc == -(-(k - 1) // (j - 1))
+    assert (8 - 1) // (4 - 1) == 2 and -(-(8 - 1) // (4 - 1)) == 3
+
+
+# --- FDIV / AFDIV -----------------------------------------------------------------
+
+def _bound(row, beta):
+    b = row["bound"]
+    if b is None:
+        return None
+    den = Fraction(b["den_const"])
+    if b["den_exp_plus_beta"] is not None:
+        den += Fraction(2) ** (b["den_exp_plus_beta"] - beta)
+    return Fraction(2) ** (beta + b["num_exp"]) / den
+
+
+@pytest.mark.parametrize("beta", [5, 6, 7])
+def test_tab_fdiv_exhaustive(beta):
+    """Table tab:fdiv, every case, every p and r < 2^beta: range, bound on r, lost bits."""
+    for row in GOLDEN["tab_fdiv"]["rows"]:
+        lo, hi = row["range"]
+        bound = _bound(row, beta)
+        seen = set()
+        for p in range(1, 2 ** beta):
+            invp = O.round_beta(Fraction(1, p), beta, row["o1"])
+            for r in range(0, 2 ** beta):
+                x = O.round_beta(r * invp, beta, row["o2"])
+                d = x.numerator // x.denominator - r // p
+                seen.add(d)
+                assert lo <= d <= hi, (row["case"], p, r)
+                if bound is not None and r < bound:
+                    assert d <= 0, (row["case"], p, r)
+                if r < 2 ** (beta - row["lost_bits"]) and row["case"] in (1, 2, 3, 4, 5, 7):
+                    assert d <= 0
+        # the printed range is attained in both directions (optimality claim)
+        assert seen == set(range(lo, hi + 1)), (row["case"], seen)
+
+
+def test_round_beta_matches_ieee_double():
+    """The exact rounding model agrees with the machine's binary64 round-to-nearest."""
+    g = np.random.default_rng(3)
+    for _ in range(3000):
+        p = int(g.integers(1, 2 ** 20))
+        r = int(g.integers(0, 2 ** 53))
+        invp = O.round_beta(Fraction(1, p), 53, O.NEAREST)
+        assert Fraction(1.0 / p) == invp
+        x = O.round_beta(r * invp, 53, O.NEAREST)
+        assert Fraction(float(r) * (1.0 / p)) == x
+        assert O.fdiv(r, p, 53, O.NEAREST, O.NEAREST) == math.floor(float(r) * (1.0 / p))
+
+
+def test_case2_family_needs_correction():
+    """Case 2 is not tight: the family of section 4.3 overshoots near 3/8 of 2^beta; AFDIV fixes it."""
+    beta = 53
+    n = (beta - 1) // 2
+    p = 2 ** n - 1
+    r = (3 * 2 ** (n - 2) + 3) * p - 1
+    assert r < 2 ** beta and abs(r / 2 ** beta - GOLDEN["case2_family"]["ratio"]) < 1e-6
+    assert O.fdiv(r, p, beta, O.UP, O.NEAREST) == r // p + 1
+    assert r >= Fraction(2 ** beta) / (3 + Fraction(2) ** (1 - beta))
+    assert O.afdiv(r, p, beta, O.NEAREST) == r // p
+    # and with the machine's own binary64 arithmetic
+    invp_up = O.round_beta(Fraction(1, p), beta, O.UP)
+    assert math.floor(float(r) * float(invp_up)) == r // p + 1
+
+
+@pytest.mark.parametrize("beta", [5, 6, 7])
+def test_afdiv_exact_small_beta(beta):
+    for mode in (O.UP, O.NEAREST, O.DOWN):
+        for p in range(1, 2 ** beta):
+            for r in range(0, 2 ** beta):
+                assert O.afdiv(r, p, beta, mode) == r // p
+
+
+def test_afdiv_random_beta53_near_bound():
+    g = np.random.default_rng(4)
+    B = Fraction(2 ** 53) / (3 + Fraction(2) ** (-52))
+    for _ in range(3000):
+        p = int(g.integers(2, 256))
+        r = int(B) + int(g.integers(-2 ** 20, 2 ** 20))
+        assert O.afdiv(r, p, 53, O.NEAREST) == r // p
+
+
+def test_floor_div_matches_python():
+    g = np.random.default_rng(5)
+    r = g.integers(0, 2 ** 63, size=10000, dtype=np.uint64)
+    for p in (2, 3, 7, 255):
+        assert (O.floor_div(r, p) == np.array([int(x) // p for x in r], dtype=np.uint64)).all()
+
+
+# --- polynomial products --------------------------------------------------------
+
+@pytest.mark.parametrize("p,k", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3), (3, 4)])
+def test_polymul_all_pairs_ring_morphism(p, k):
+    """All pairs of degree < k: digits of DQT(a)*DQT(b) at a large q, mod p (ring morphism)."""
+    elems = np.array(list(itertools.product(range(p), repeat=k)), dtype=np.uint8)
+    a = np.repeat(elems, len(elems), axis=0)
+    b = np.tile(elems, (len(elems), 1))
+    got = O.polymul(a, b, p)
+    q = 1000  # > k (p-1)^2: digits never carry
+    for t in range(len(a)):
+        r = O.dqt_int(a[t], q) * O.dqt_int(b[t], q)
+        assert [d % p for d in O.radix_digits(r, q, 2 * k - 1)] == got[t].tolist()
+
+
+def test_polymul_numpy_library():
+    g = np.random.default_rng(6)
+    for p in (2, 3, 5, 7, 11, 251):
+        for ka, kb in [(1, 1), (4, 4), (7, 3), (16, 16), (3, 9)]:
+            a = g.integers(0, p, size=(50, ka), dtype=np.uint8)
+            b = g.integers(0, p, size=(50, kb), dtype=np.uint8)
+            got = O.polymul(a, b, p)
+            for t in range(50):
+                ref = np.polymul(a[t][::-1].astype(np.int64), b[t][::-1].astype(np.int64))[::-1] % p
+                ref = np.concatenate([ref, np.zeros(ka + kb - 1 - len(ref), np.int64)])
+                assert (got[t] == ref).all()
+
+
+def test_dqt_eval_and_radix_mod():
+    g = np.random.default_rng(7)
+    c = g.integers(0, 3, size=(500, 4), dtype=np.uint8)
+    w = O.dqt_eval(c, 6)
+    wr = O.dqt_eval(c, 6, reverse=True)
+    for t in range(500):
+        assert int(w[t]) == O.dqt_int(c[t], 64)
+        assert int(wr[t]) == O.dqt_int(c[t][::-1], 64)
+    r = g.integers(0, 2 ** 53, size=2000, dtype=np.uint64)
+    for p, logq, nres in [(3, 6, 7), (3, 5, 9), (7, 7, 5), (2, 11, 4), (251, 7, 7)]:
+        got = O.radix_mod(r, p, logq, nres)
+        for t in range(0, 2000, 7):
+            _, _, mu = O.redq_steps(int(r[t]), p, 2 ** logq, nres)
+            assert got[t].tolist() == mu
+        # library shifts
+        sh = np.stack([(r >> np.uint64(logq * i)) & np.uint64(2 ** logq - 1) for i in range(nres - 1)]
+                      + [r >> np.uint64(logq * (nres - 1))], axis=1) % np.uint64(p)
+        assert (got == sh.astype(np.uint8)).all()
+
+
+# --- F_p matrix product -------------------------------------------------------
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_fgemm_2x2_exhaustive(p):
+    mats = np.array(list(itertools.product(range(p), repeat=4)), dtype=np.uint8).reshape(-1, 2, 2)
+    for A in mats:
+        Cs = [O.fgemm(A, B, p) for B in mats]
+        ref = [(A.astype(np.int64) @ B.astype(np.int64)) % p for B in mats]
+        assert all((c == r).all() for c, r in zip(Cs, ref))
+
+
+def test_fgemm_numpy_and_invariants():
+    g = np.random.default_rng(8)
+    for p in (2, 3, 5, 7, 11, 251):
+        A = g.integers(0, p, size=(37, 53), dtype=np.uint8)
+        B = g.integers(0, p, size=(53, 29), dtype=np.uint8)
+        C = O.fgemm(A, B, p)
+        assert (C == (A.astype(np.int64) @ B.astype(np.int64)) % p).all()
+        assert (O.fgemm(B.T, A.T, p) == C.T).all()
+        D = g.integers(0, p, size=(29, 11), dtype=np.uint8)
+        assert (O.fgemm(C, D, p) == O.fgemm(A, O.fgemm(B, D, p), p)).all()
+        I = np.eye(53, dtype=np.uint8)
+        assert (O.fgemm(A, I, p) == A).all()
+        perm = g.permutation(53)
+        P = I[perm]
+        assert (O.fgemm(P, B, p) == B[perm]).all()
+        rows = g.integers(0, 37, size=100)
+        cols = g.integers(0, 29, size=100)
+        assert (O.fgemm_entries(A, B, p, rows, cols) == C[rows, cols]).all()
+
+
+def test_fgemm_worst_case():
+    for p in (2, 3, 7, 251):
+        A = inputs.worst_case((8, 300), p)
+        B = inputs.worst_case((300, 5), p)
+        assert (O.fgemm(A, B, p) == (300 * (p - 1) ** 2) % p).all()
+
+
+# --- GF(p^k) ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("p,k", [(2, 3), (3, 2), (3, 3)])
+def test_is_irreducible_counts(p, k):
+    """Number of monic irreducibles of degree k over F_p (Gauss): (1/k) sum_{d|k} mobius(d) p^(k/d)."""
+    def mobius(n):
+        res, m, f = 1, n, 2
+        while f * f <= m:
+            if m % f == 0:
+                m //= f
+                if m % f == 0:
+                    return 0
+                res = -res
+            f += 1
+        return -res if m > 1 else res
+    expected = sum(mobius(d) * p ** (k // d) for d in range(1, k + 1) if k % d == 0) // k
+    count = sum(O.is_irreducible(list(c) + [1], p) for c in itertools.product(range(p), repeat=k))
+    assert count == expected
+
+
+@pytest.mark.parametrize("p,k", [(3, 5), (7, 3)])
+def test_gf_full_table_field_laws(p, k):
+    """Full multiplication table of GF(p^k): commutativity, unit, Lagrange, Frobenius, inverses."""
+    P = inputs.irreducible(p, k)
+    assert O.is_irreducible(P, p)
+    elems = np.array(list(O.all_elements(p, k)), dtype=np.uint8)
+    n = len(elems)
+    a = np.repeat(elems, n, axis=0)
+    b = np.tile(elems, (n, 1))
+    tab = O.gf_mul(a, b, p, P).reshape(n, n, k)
+    # the table is commutative, 1 is the unit, 0 absorbs
+    assert (tab == tab.transpose(1, 0, 2)).all()
+    assert (tab[1] == elems).all()
+    assert (tab[0] == 0).all()
+    # index of an element in the table
+    idx = lambda e: int(sum(int(c) * p ** i for i, c in enumerate(e)))
+    # every nonzero row is a permutation of the elements (no zero divisors)
+    for i in range(1, n):
+        assert len({idx(e) for e in tab[i]}) == n
+    # Lagrange a^(p^k - 1) = 1 and Frobenius a^(p^k) = a, by repeated squaring through the table
+    one = idx([1] + [0] * (k - 1))
+    def power(i, e):
+        res, base = one, i
+        while e:
+            if e & 1:
+                res = idx(tab[res, base])
+            base = idx(tab[base, base])
+            e >>= 1
+        return res
+    for i in range(1, n):
+        assert power(i, n - 1) == one
+    for i in range(n):
+        assert power(i, n) == i
+    # the table agrees with the pure-Python product on a sample, and with the distributive law
+    g = np.random.default_rng(9)
+    for _ in range(300):
+        x, y, z = (int(v) for v in g.integers(0, n, size=3))
+        assert tab[x, y].tolist() == O.gf_mul_py(elems[x].tolist(), elems[y].tolist(), p, P)
+        yz = (elems[y].astype(int) + elems[z]) % p
+        lhs = tab[x, idx(yz)].astype(int)
+        rhs = (tab[x, y].astype(int) + tab[x, z]) % p
+        assert (lhs == rhs).all()
+        assert idx(tab[idx(tab[x, y]), z]) == idx(tab[x, idx(tab[y, z])])
+
+
+@pytest.mark.parametrize("p,k", [(3, 5), (7, 3)])
+def test_gf_inverse_check(p, k):
+    """a.b.b^-1 = a on a sample, with b^-1 by brute force and by extended Euclid."""
+    P = inputs.irreducible(p, k)
+    a, b = inputs.gf_pairs(300, k, p)
+    prod = O.gf_mul(a, b, p, P)
+    for t in range(300):
+        if not b[t].any():
+            continue
+        inv = O.gf_inverse_bruteforce(b[t].tolist(), p, P)
+        assert inv == O.gf_inverse_euclid(b[t].tolist(), p, P)
+        back = O.gf_mul(prod[t:t + 1], np.array([inv], np.uint8), p, P)
+        assert (back[0] == a[t]).all()
+
+
+@pytest.mark.parametrize("p,k,logq", [(3, 5, 5), (7, 3, 7), (2, 4, 4), (5, 2, 6)])
+def test_fgdp_two_table_reduction(p, k, logq):
+    """Theorem thm:fgdp: L from (u_0..u_{k-1}), H from (u_{k-1}..u_{2k-2}), R = H + L in the field."""
+    P = inputs.irreducible(p, k)
+    a, b = inputs.gf_pairs(2000, k, p, seed=77)
+    ref = O.gf_mul(a, b, p, P)
+    q = 2 ** logq
+    for t in range(2000):
+        r = O.dqt_int(a[t], q) * O.dqt_int(b[t], q)
+        _, u, _ = O.redq_steps(r, p, q, 2 * k - 1)
+        assert O.fgdp_reduce(u, q, p, P) == ref[t].tolist()
+
+
+# --- bounds ------------------------------------------------------------------------
+
+def test_comprange_table():
+    """Table tab:comprange, modulo 3 with beta = 53: smallest Q = 2^t with n (p-1)^2 < Q."""
+    g = GOLDEN["tab_comprange"]
+    p, beta = g["p"], g["beta"]
+    prev_max = 1
+    for col in g["columns"]:
+        if col["garbled"]:
+            prev_max = col["dim_max"]
+            continue
+        t = col["log2Q"]
+        # interior of the dimension range: the printed Q is the smallest that works
+        for n in range(prev_max + 1, col["dim_max"]):
+            tmin = min(s for s in range(1, 40) if O.cmm_bounds_ok(p, n, s, 0, beta))
+            assert tmin <= t
+        n_in = col["dim_max"] - 1
+        assert min(s for s in range(1, 40) if O.cmm_bounds_ok(p, n_in, s, 0, beta)) == t
+        # the range top needs one more bit under the strict eq:lower (reading of the table)
+        assert n_in * (p - 1) ** 2 < 2 ** t and not (col["dim_max"] * (p - 1) ** 2 < 2 ** t)
+        assert O.compression_factor(t, beta) == col["compression"]
+        assert col["compression"] - 1 == col["degree"]
+        # eq:upper holds for d = e - 1
+        assert O.cmm_bounds_ok(p, n_in, t, col["degree"], beta)
+        prev_max = col["dim_max"]
+
+
+def test_dqt_bounds_worked_cases():
+    # (X+1)(X+2) over F_3, q = 100 is not a power of two; the bound q > n k (p-1)^2 reads 100 > 8
+    assert 100 > 1 * 2 * (3 - 1) ** 2
+    # degree-3 products over F_3 in one word: q = 2^6, 7 digits of 6 bits in 53 bits
+    assert O.dqt_bounds_ok(3, 4, 1, 6, 53) and not O.dqt_bounds_ok(3, 4, 1, 4, 53)
+    assert O.dqt_bounds_ok(3, 4, 3, 6, 53) and not O.dqt_bounds_ok(3, 4, 4, 6, 53)
+    # GF(3^5) and GF(7^3) products
+    assert O.dqt_bounds_ok(3, 5, 1, 5, 53) and O.dqt_bounds_ok(7, 3, 1, 7, 53)
+    assert not O.dqt_bounds_ok(7, 3, 1, 6, 53)

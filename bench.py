@@ -1,0 +1,197 @@
+"""Benchmark of the packed DQT + REDQ hot path on one MI355X.
+
+Workload (one step): C = A.B mod 3 with m = n = k = 1024, uniform uint8 entries
+in [0, 3): DQT packing of the rows of A and the columns of B (reversed
+Kronecker pairs, four entries per 32-bit word), the packed multiply-accumulate
+(middle product, delayed reduction, one v_dot2_u32_u16 per four F_p
+multiply-adds), middle-digit extraction and one reduction per output, uint8
+store.  Inputs are resident in HBM before the timed region.
+
+Printed: one JSON line.  `value` is F_p Gop/s (2 m n k per step) of the
+packed path; `roofline` is the packed multiply kernel against the VALU issue
+rate; `cpu_baseline` is the CPU oracle on a bounded sample; `extra` holds the
+other measured paths (plain per-entry, dot4 and INT8 matrix-core comparators,
+one-word polynomial products and GF(p^k) products against HBM).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "F_p GEMM Gop/s + polymul/s, packed DQT+REDQ vs plain modular; p99 latency"
+PEAK_LANE_OPS = 256 * 64 * 2.4e9          # VALU lane-instructions per second (256 CUs, wave64, 2.4 GHz)
+PEAK_HBM = 8.0e12                          # bytes per second
+MNK = 1024
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the comparator measurements")
+    return ap.parse_args()
+
+
+def timed_loop(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps   # seconds per call
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
+              "the multi-GPU layout is described in DESIGN.md and not run here", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_0809_0063_amd import dqt as D
+    from paper_0809_0063_amd import inputs
+
+    dev = torch.device("cuda:0")
+    p = 3
+    A, B = inputs.gemm_pair(MNK, MNK, MNK, p)
+    dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    dC = torch.empty((MNK, MNK), dtype=torch.uint8, device=dev)
+    plan = D.GemmPlan(algo=D.GEMM_CMM)
+    ws = torch.empty(D.fgemm_workspace_size(p, MNK, MNK, MNK, plan), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # warmup
+    for _ in range(args.warmup):
+        D.fgemm_pack(dA, dB, p, plan=plan, workspace=ws)
+        D.fgemm_compute(dC, p, MNK, plan=plan, workspace=ws)
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps; events around the packed multiply kernel of every step
+    n_ev = args.steps
+    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
+    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(args.steps):
+        D.fgemm_pack(dA, dB, p, plan=plan, workspace=ws)
+        ev_a[i].record(stream)
+        D.fgemm_compute(dC, p, MNK, plan=plan, workspace=ws)
+        ev_b[i].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_s = t_start.elapsed_time(t_end) / 1e3
+    step_s = total_s / args.steps
+    kern_s = sum(a.elapsed_time(b) for a, b in zip(ev_a, ev_b)) / 1e3 / n_ev
+    fp_ops = 2.0 * MNK ** 3
+    value = fp_ops / step_s / 1e9
+
+    # correctness of the timed output against a cheap property (full parity is in the tests):
+    # row 0 of C equals row 0 of A times B mod 3 computed with integer numpy on the host
+    row0 = (A[:1].astype(np.int64) @ B.astype(np.int64)) % p
+    assert (dC[:1].cpu().numpy() == row0).all(), "bench output mismatch"
+
+    # roofline of the packed multiply kernel: algorithmic dot2 lane-instructions per launch
+    lane_ops = MNK * MNK * (MNK // 4)
+    achieved = lane_ops / kern_s
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved / 1e12, 3),
+        "peak": round(PEAK_LANE_OPS / 1e12, 3),
+        "unit": "Tlane-op/s",
+        "frac": round(achieved / PEAK_LANE_OPS, 4),
+        "traffic": None,
+        "kernel": "k_gemm_words<DOT2> (packed multiply-accumulate + epilogue)",
+        "kernel_us": round(kern_s * 1e6, 3),
+        "fp_top_s": round(fp_ops / kern_s / 1e12, 2),
+    }
+
+    extra = {}
+    if not args.no_extra:
+        for name, algo in (("plain_mad", D.GEMM_PLAIN), ("plain_dot4", D.GEMM_DOT4), ("mfma_int8", D.GEMM_MFMA),
+                           ("cmm_redq_epilogue", None)):
+            pl = D.GemmPlan(algo=algo) if algo is not None else D.GemmPlan(algo=D.GEMM_CMM, epilogue=D.EPI_REDQ)
+            w2 = torch.empty(max(1, D.fgemm_workspace_size(p, MNK, MNK, MNK, pl)), dtype=torch.uint8, device=dev)
+            s = timed_loop(lambda: D.fgemm(dA, dB, p, plan=pl, out=dC, workspace=w2), 100, 10, torch)
+            extra["fgemm_" + name] = {"gop_s": round(fp_ops / s / 1e9, 1), "us_per_call": round(s * 1e6, 2)}
+            assert (dC[:1].cpu().numpy() == row0).all()
+        # one-word polynomial products: degree 3 over F_3, q = 2^6, 2^26 products (beyond the MALL)
+        n = 1 << 26
+        a, b = inputs.polymul_pairs(n, 4, 3)
+        da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+        out = torch.empty((n, 7), dtype=torch.uint8, device=dev)
+        for name, fn in (("packed", lambda: D.polymul_u8(da, db, 3, out=out, log2q=6)),
+                         ("plain", lambda: D.polymul_plain_u8(da, db, 3, out=out))):
+            s = timed_loop(fn, 10, 2, torch)
+            extra["polymul_deg3_f3_" + name] = {"polymul_s": round(n / s, 1), "GB_s": round(15 * n / s / 1e9, 1),
+                                                "hbm_frac": round(15 * n / s / PEAK_HBM, 4)}
+        a65, b65 = inputs.polymul_pairs(65536, 4, 3)
+        d65a, d65b = torch.from_numpy(a65).to(dev), torch.from_numpy(b65).to(dev)
+        o65 = torch.empty((65536, 7), dtype=torch.uint8, device=dev)
+        s = timed_loop(lambda: D.polymul_u8(d65a, d65b, 3, out=o65, log2q=6), 200, 20, torch)
+        extra["polymul_65536_packed"] = {"us_per_call": round(s * 1e6, 2), "polymul_s": round(65536 / s, 1)}
+        del da, db, out
+        for (pp, k) in ((3, 5), (7, 3)):
+            P = inputs.irreducible(pp, k)
+            x, y = inputs.gf_pairs(n, k, pp)
+            dx, dy = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+            oz = torch.empty((n, k), dtype=torch.uint8, device=dev)
+            for name, fn in (("packed", lambda: D.gf_mul_u8(dx, dy, pp, P, out=oz)),
+                             ("plain", lambda: D.gf_mul_plain_u8(dx, dy, pp, P, out=oz))):
+                s = timed_loop(fn, 10, 2, torch)
+                extra[f"gf_{pp}^{k}_{name}"] = {"mul_s": round(n / s, 1), "GB_s": round(3 * k * n / s / 1e9, 1),
+                                               "hbm_frac": round(3 * k * n / s / PEAK_HBM, 4)}
+            del dx, dy, oz
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        rows = 64
+        t0 = time.perf_counter()
+        Cs = O.fgemm(A[:rows], B, p)
+        dt = time.perf_counter() - t0
+        assert (Cs[:1] == row0).all()
+        cpu = {"value": round(2.0 * rows * MNK * MNK / dt / 1e9, 3), "unit": "Gop/s",
+               "cores": O.max_threads(), "kind": "oracle",
+               "sample": f"rows 0..{rows - 1} of the 1024^3 mod-3 product ({rows}x1024x1024), reduce after every op"}
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "F_p matrix product C = A.B mod 3, m = n = k = 1024, uint8 entries, packed DQT (CMM) + REDC",
+                   "p": p, "m": MNK, "n": MNK, "k": MNK},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,288 @@
+/*
+ * dqt.h -- C ABI of libdqt, the MI355X (gfx950) packed-DQT / REDQ library.
+ *
+ * Method: Dumas, Fousse, Salvy, "Simultaneous Modular Reduction and Kronecker
+ * Substitution for Small Finite Fields".  Polynomials over F_p are packed into
+ * machine words by evaluation at q = 2^log2q (the DQT map, equation eq:dqt),
+ * multiplied and accumulated as integers while every q-adic digit stays below
+ * q (the a priori bounds eq:bounds / eq:lower / eq:upper), and recovered with
+ * REDQ (section 3): one floating-point floor for the whole word (section 4,
+ * algorithm AFDIV), field-parallel integer operations, and a correction read
+ * from tables held in LDS.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a dqt_status; none aborts, throws or prints.
+ * - Residues are uint8 values in [0, p), 2 <= p <= 255.  Inputs with an entry
+ *   >= p give unspecified (but memory-safe) results.
+ * - Coefficient i of a polynomial is the coefficient of X^i (low degree first).
+ * - Pointers named d_* are device pointers (HIP global memory) owned by the
+ *   caller; the library allocates no device memory and keeps no pointer after
+ *   the call returns.  `stream` is a hipStream_t (NULL = the null stream);
+ *   all device work is enqueued asynchronously on it.
+ * - Argument and bound checks run on the host, synchronously, before anything
+ *   is enqueued.  On an error nothing is enqueued.  DQT_E_DEVICE reports a HIP
+ *   runtime error; dqt_last_error() gives its text (thread-local).
+ * - Calls on distinct streams with distinct output buffers may run
+ *   concurrently.
+ */
+#ifndef DQT_H
+#define DQT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dqt_status {
+    DQT_OK = 0,
+    DQT_E_INVALID = -1,     /* null pointer, p outside [2,255], zero or overflowing sizes */
+    DQT_E_BOUND = -2,       /* parameters violate the paper's a priori bounds */
+    DQT_E_UNSUPPORTED = -3, /* valid, but outside what the kernels implement */
+    DQT_E_DEVICE = -4,      /* HIP runtime error (see dqt_last_error) */
+    DQT_E_WORKSPACE = -5    /* workspace null or smaller than required */
+} dqt_status;
+
+/* Text of a status code (static storage). */
+const char *dqt_status_str(dqt_status s);
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char *dqt_last_error(void);
+/* Library version string. */
+const char *dqt_version(void);
+
+/*
+ * q-adic packing parameters (section 2.3, theorem eq:bounds).
+ *   p        the prime.
+ *   log2q    q = 2^log2q, the evaluation point.
+ *   k_coeffs coefficients per packed operand (polynomials of degree < k_coeffs).
+ *   nres     digits of a packed result, 2*k_coeffs - 1 for a product (REDQ_nres).
+ *   n_accum  number of products summed into one result word before REDQ
+ *            (the n of eq:bounds); 1 for a single product.
+ * Every packed word is a uint64 holding nres fields of log2q bits.
+ */
+typedef struct dqt_qadic {
+    uint32_t p;
+    uint32_t log2q;
+    uint32_t k_coeffs;
+    uint32_t nres;
+    uint64_t n_accum;
+} dqt_qadic;
+
+/*
+ * Host-only check of a parameter set.  DQT_OK iff
+ *   q > n_accum * k_coeffs * (p-1)^2     (eq:bounds, digits never carry),
+ *   nres * log2q <= 53                   (eq:bounds with beta = 53: the word
+ *                                         is exact in binary64, so REDQ's
+ *                                         single division is one FP64 floor),
+ *   log2q <= 32, 1 <= k_coeffs, 1 <= nres <= 32.
+ * Returns DQT_E_INVALID for null or malformed input, DQT_E_BOUND otherwise.
+ */
+dqt_status dqt_qadic_check(const dqt_qadic *a);
+
+/*
+ * Host-only: the smallest log2q satisfying dqt_qadic_check for (p, k_coeffs,
+ * n_accum) with nres = 2*k_coeffs - 1.  Writes *out on success; DQT_E_BOUND
+ * when no q fits in 53 bits.
+ */
+dqt_status dqt_qadic_choose(uint32_t p, uint32_t k_coeffs, uint64_t n_accum, dqt_qadic *out);
+
+/*
+ * DQT map (equation eq:dqt; section 2.1 with q = 2^log2q a shift).
+ * d_coeffs: uint8 [count][a->k_coeffs]; d_words: uint64 [count].
+ * reverse = 0: word = sum_i c_i q^i.  reverse != 0: word = sum_i c_i q^(k-1-i)
+ * (the reversed row packing of the compressed matrix product, section 7.1).
+ * count == 0 is a no-op.
+ */
+dqt_status dqt_pack(const uint8_t *d_coeffs, uint64_t count, const dqt_qadic *a, int reverse,
+                    uint64_t *d_words, void *stream);
+
+/*
+ * Packed product (equation eq:mult): d_r[t] = d_a[t] * d_b[t] as integers,
+ * i.e. the Kronecker product of two packed polynomials, left unreduced.
+ * Requires dqt_qadic_check(a) == DQT_OK with n_accum >= 1 and
+ * nres == 2*k_coeffs - 1.  Word layout as dqt_pack.
+ */
+dqt_status dqt_polymul(const uint64_t *d_a, const uint64_t *d_b, uint64_t count, const dqt_qadic *a,
+                       uint64_t *d_r, void *stream);
+
+/*
+ * REDQ (algorithm REDQ, section 3.2, with the binary-case compression of
+ * section 3.3, the tabulated correction of section 3.5 and the FP64 floor of
+ * algorithm AFDIV, section 4.6).
+ * d_r: uint64 [count] packed words r = sum_{i<nres} m_i q^i whose lower
+ * digits m_0..m_{nres-2} are < q (guaranteed by eq:bounds when the words
+ * come from products; the caller's guarantee otherwise).  Checked here:
+ * nres * log2q <= 53 (so r < 2^53 and the division is one binary64 floor,
+ * DQT_E_BOUND otherwise) and log2q >= ceil(log2 p) (DQT_E_UNSUPPORTED
+ * otherwise); n_accum and the first part of eq:bounds are not used.
+ * modulus == NULL: d_out uint8 [count][nres], d_out[t][i] = m_i mod p.
+ * modulus != NULL (GF(p^k) reduction of algorithm FGDP, lines 3-6, theorem
+ * thm:fgdp): host pointer to k_coeffs+1 coefficients of a monic polynomial P
+ * (modulus[k_coeffs] == 1), nres must be 2*k_coeffs-1, k_coeffs <= 6, and
+ * d_out is uint8 [count][k_coeffs] = (sum_i m_i X^i mod p) mod P.
+ */
+dqt_status redq_unpack(const uint64_t *d_r, uint64_t count, const dqt_qadic *a, const uint8_t *modulus,
+                       uint8_t *d_out, void *stream);
+
+/*
+ * Fused one-word polynomial product: pack + product + REDQ + store, in one
+ * kernel.  d_a, d_b: uint8 [count][k]; d_out: uint8 [count][2k-1], the
+ * product mod p (zeros included).  log2q = 0 takes the smallest q allowed by
+ * eq:bounds (dqt_qadic_choose(p, k, 1)); a given log2q must satisfy
+ * dqt_qadic_check with n_accum = 1 (DQT_E_BOUND otherwise).
+ * DQT_E_UNSUPPORTED if no q fits in one 53-bit word (k too large for p) or
+ * k > 9.
+ */
+dqt_status dqt_polymul_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t k, uint32_t p,
+                          uint32_t log2q, uint8_t *d_out, void *stream);
+
+/*
+ * Fused GF(p^k) product (section 6, algorithm FGDP lines 3-6 on single
+ * products): d_a, d_b, d_out uint8 [count][k], modulus a host pointer to the
+ * k+1 coefficients of a monic P (not checked for irreducibility: the result
+ * is the product in F_p[X]/(P)).  2 <= k <= 6, k*ceil(log2 p) <= 12 (the two
+ * tables of 2^(k ceil(log2 p)) entries live in LDS).  log2q as for
+ * dqt_polymul_u8.
+ */
+dqt_status dqt_gf_mul_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t k, uint32_t p,
+                         uint32_t log2q, const uint8_t *modulus, uint8_t *d_out, void *stream);
+
+/*
+ * Plain per-entry comparators (the paper's "delayed" baseline, section 5.1):
+ * one coefficient per machine multiply-add, integer accumulation, one
+ * reduction (REDC) per output coefficient.  Same layouts and results as the
+ * packed entry points.  dqt_polymul_plain_u8 accepts any k <= 64.
+ */
+dqt_status dqt_polymul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t k, uint32_t p,
+                                uint8_t *d_out, void *stream);
+dqt_status dqt_gf_mul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t k, uint32_t p,
+                               const uint8_t *modulus, uint8_t *d_out, void *stream);
+
+/*
+ * Long polynomial products by the FQT (section 5.2): P = sum_i P_i Y^i with
+ * Y = X^(d+1) and each block P_i of d+1 coefficients packed in one word; block
+ * products are summed in packed form (delayed, at most the n_q of section 5.3
+ * per word) and each output block is recovered by one REDQ_{2d+1}; the d
+ * overlapping coefficients of consecutive blocks are added mod p.
+ * d_a: uint8 [count][na], d_b: uint8 [count][nb], d_out: uint8 [count][na+nb-1].
+ * block = d+1 coefficients per word (0 = choose).  na, nb <= 64.
+ */
+dqt_status dqt_polymul_fqt_u8(const uint8_t *d_a, uint32_t na, const uint8_t *d_b, uint32_t nb, uint64_t count,
+                              uint32_t p, uint32_t block, uint8_t *d_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * F_p matrix product C = A.B mod p (section 7).
+ * A: uint8 m x kdim, row-major, leading dimension lda >= kdim.
+ * B: uint8 kdim x n, row-major, ldb >= n.  C: uint8 m x n, ldc >= n.
+ * m, n, kdim may be 0 (no-op) and need not be multiples of any tile.
+ * ------------------------------------------------------------------------ */
+
+typedef enum dqt_gemm_algo {
+    DQT_GEMM_AUTO = 0,      /* CMM when the packing bounds allow it, else PLAIN */
+    DQT_GEMM_CMM = 1,       /* compressed (middle product, section 7.1) on packed words */
+    DQT_GEMM_PLAIN = 2,     /* one entry per multiply-add, delayed REDC */
+    DQT_GEMM_DOT4 = 3,      /* plain, four u8 entries per hardware dot instruction */
+    DQT_GEMM_MFMA = 4,      /* plain, INT8 matrix cores, exact int32 accumulation */
+    DQT_GEMM_RIGHT = 5      /* right-compressed (section 7.4): A times row-packed B, REDQ per word */
+} dqt_gemm_algo;
+
+typedef enum dqt_gemm_epilogue {
+    DQT_EPI_REDC = 0,       /* one reduction per output (section 7.2) */
+    DQT_EPI_REDQ = 1        /* middle digits gathered e per word and reduced by one REDQ_e */
+} dqt_gemm_epilogue;
+
+typedef struct dqt_gemm_plan {
+    uint32_t algo;          /* dqt_gemm_algo */
+    uint32_t log2Q;         /* 0 = smallest allowed by eq:lower for the interval */
+    uint32_t interval;      /* delayed-reduction interval in k (0 = whole kdim); multiple of 4 */
+    uint32_t tile_rows;     /* rows per wave (CMM/PLAIN: 8, 16 or 32; 0 = default) */
+    uint32_t ksplit;        /* waves splitting kdim inside a workgroup (1, 2, 4, 8; 0 = default) */
+    uint32_t epilogue;      /* dqt_gemm_epilogue */
+} dqt_gemm_plan;
+
+/*
+ * Bytes of device workspace dqt_fgemm needs for (m, n, kdim, plan); 0 when
+ * none.  plan == NULL means the default plan for (p, kdim).
+ */
+size_t dqt_fgemm_workspace_size(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const dqt_gemm_plan *plan);
+
+/*
+ * F_p matrix product.  plan == NULL: DQT_GEMM_AUTO with defaults.
+ * CMM bounds (eq:lower with the interval in place of kdim): interval*(p-1)^2
+ * < Q, and (p-1)(Q+1) < 2^16 so that a Kronecker pair fits a 16-bit lane of
+ * the packed word.  d_work: device workspace of at least
+ * dqt_fgemm_workspace_size(...) bytes (packed operands); its contents on
+ * entry are ignored.
+ */
+dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t *d_A, uint64_t lda,
+                     const uint8_t *d_B, uint64_t ldb, uint8_t *d_C, uint64_t ldc, const dqt_gemm_plan *plan,
+                     void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * The two phases of dqt_fgemm on their own (section 7.1: compression,
+ * multiplication and extraction; compressed matrices are often reused).
+ * dqt_fgemm_pack writes the packed operands of (p, m, n, kdim, plan) into
+ * d_work; either d_A or d_B may be NULL to keep the packed copy already in the
+ * workspace.  dqt_fgemm_compute multiplies the packed operands in d_work and
+ * writes C; it must be given the same (p, m, n, kdim, plan) as the pack call
+ * that filled d_work.  dqt_fgemm is the two calls in sequence.
+ */
+dqt_status dqt_fgemm_pack(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t *d_A, uint64_t lda,
+                          const uint8_t *d_B, uint64_t ldb, const dqt_gemm_plan *plan, void *d_work,
+                          size_t work_bytes, void *stream);
+dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t *d_C, uint64_t ldc,
+                             const dqt_gemm_plan *plan, const void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * Batched F_p matrix products in one persistent launch.
+ *
+ * Each descriptor names its own device operands (row-major uint8, as for
+ * dqt_fgemm) and its packing choices: algo (DQT_GEMM_AUTO, _CMM, _PLAIN or
+ * _DOT4), interval and log2Q (0 = smallest allowed), epilogue.  These are the
+ * knobs the tuner picks per (size, p) bucket.
+ *
+ * dqt_fgemm_batched_prepare builds the device-resident plan in d_work
+ * (descriptors, packed-operand slices, the work-item list sorted by
+ * decreasing cost) with one host-to-device copy on `stream`, waits for it,
+ * and returns a host handle.  dqt_fgemm_batched_run enqueues the batch:
+ * one packing launch over all products, then one persistent launch whose
+ * workgroups take (product, tile) items from an atomic counter until none is
+ * left.  run reads only d_work and may be called again (or captured in a
+ * graph and replayed) as long as the operands and d_work stay valid; calls
+ * that share a d_work must not overlap.  dqt_fgemm_batched = prepare + run +
+ * free.
+ */
+typedef struct dqt_gemm_desc {
+    const uint8_t *A;
+    const uint8_t *B;
+    uint8_t *C;
+    uint32_t m, n, kdim;
+    uint32_t lda, ldb, ldc;
+    uint32_t p;
+    uint32_t algo;          /* DQT_GEMM_AUTO, DQT_GEMM_CMM, DQT_GEMM_PLAIN or DQT_GEMM_DOT4 */
+    uint32_t interval;      /* delayed-reduction interval in k (0 = largest allowed) */
+    uint32_t log2Q;         /* 0 = smallest allowed */
+    uint32_t epilogue;      /* dqt_gemm_epilogue */
+} dqt_gemm_desc;
+
+typedef struct dqt_batch_opts {
+    uint32_t tile_rows;     /* 8 or 16 (0 = 16) */
+    uint32_t ksplit;        /* 2 or 4 waves per workgroup (0 = 4) */
+} dqt_batch_opts;
+
+typedef struct dqt_batch dqt_batch;   /* opaque host handle */
+
+size_t dqt_fgemm_batched_workspace_size(const dqt_gemm_desc *descs, uint32_t count, const dqt_batch_opts *opts);
+dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc *descs, uint32_t count, const dqt_batch_opts *opts,
+                                     void *d_work, size_t work_bytes, void *stream, dqt_batch **out);
+dqt_status dqt_fgemm_batched_run(const dqt_batch *batch, void *stream);
+void dqt_batch_free(dqt_batch *batch);
+dqt_status dqt_fgemm_batched(const dqt_gemm_desc *descs, uint32_t count, const dqt_batch_opts *opts,
+                             void *d_work, size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DQT_H */

@@ -1,0 +1,674 @@
+// F_p matrix products C = A.B mod p (section 7 of the paper).
+//
+// Packed path (compressed matrix multiplication, section 7.1, "CMM"): k is cut
+// into groups of four; a group of a row of A becomes one 32-bit word of two
+// 16-bit lanes, each lane the reversed Kronecker pair a_(2l) Q + a_(2l+1); the
+// same group of a column of B becomes b_(2l) + b_(2l+1) Q.  One
+// v_dot2_u32_u16 of the two words adds the two lane products into a 32-bit
+// accumulator whose digit of weight Q (the middle product) collects four
+// multiply-adds of the dot product.  Digits never carry while the number of
+// accumulated k (the delayed-reduction interval) times (p-1)^2 stays below Q
+// (eq:lower); the accumulator wraps modulo 2^32 above digit 1, which leaves
+// digits 0 and 1 exact.  After the interval the middle digit is extracted and
+// added to a plain accumulator.  One reduction per output ends the product
+// (REDC, section 7.2), or the middle digits of several outputs are gathered
+// into one word and reduced by one REDQ (section 3).
+//
+// Comparators in the same kernel structure: one entry per word and one
+// v_mad_u32_u24 per multiply-add ("plain", the paper's delayed baseline), and
+// four u8 entries per word with v_dot4_u32_u8.  A separate kernel uses the
+// INT8 matrix cores (exact int32 accumulation while k (p-1)^2 < 2^31).
+//
+// Layout on the device (workspace, written by the pack kernel each call):
+//   CA: [KW][m_pad] uint32, k-major, so the words of 16 consecutive rows at one
+//       k-group are one 64-byte scalar load (rows are uniform across a wave).
+//   CB: [KW][n_pad] uint32, k-major, column words contiguous (coalesced).
+// Each wave owns TM rows (uniform, held in SGPRs) and 64*TN columns (one per
+// lane and per j); S waves of a workgroup split k and add their partial sums
+// through LDS before the epilogue.
+
+#include <string.h>
+
+#include "dqt_internal.h"
+
+namespace dqt {
+
+enum GemmOp { OP_DOT2 = 0, OP_DOT4 = 1, OP_MAD = 2 };
+
+struct GemmArgs {
+    const uint32_t* CA;
+    const uint32_t* CB;
+    uint8_t* C;
+    uint32_t m, n, ldc;
+    uint32_t m_pad, n_pad;
+    uint32_t KW;          // k-groups (words) along k
+    uint32_t kw_split;    // k-groups per wave
+    uint32_t lw;          // delayed-reduction interval in k-groups (0 = whole range)
+    uint32_t nrb, ncb;    // row blocks, column blocks
+    uint32_t b;           // log2 Q (packed path)
+    uint32_t p, pmagic;
+    uint32_t epi;         // 0 REDC, 1 REDQ
+    uint32_t epi_e;       // outputs per REDQ word
+    RedqArgs ra;          // REDQ_{epi_e} parameters (q = Q)
+};
+
+// x mod p for any 32-bit x: quotient from the rounded-up reciprocal, one fix.
+__device__ __forceinline__ uint32_t mod_u32(uint32_t x, uint32_t p, uint32_t pmagic) {
+    const uint32_t qt = __umulhi(x, pmagic);
+    const int32_t r = (int32_t)(x - qt * p);
+    return (uint32_t)(r < 0 ? r + (int32_t)p : r);
+}
+
+template <int OP>
+__device__ __forceinline__ uint32_t mac(uint32_t a, uint32_t b, uint32_t acc) {
+    if (OP == OP_DOT2) {
+        typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+        return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b), acc, false);
+    } else if (OP == OP_DOT4) {
+        return __builtin_amdgcn_udot4(a, b, acc, false);
+    } else {
+        return __umul24(a, b) + acc;
+    }
+}
+
+// Logical tile of a workgroup: on a launch whose size is a multiple of 8,
+// workgroup i runs on XCD i mod 8; consecutive logical tiles on one XCD share
+// a column block so that the XCD's L2 keeps one slice of CB.
+__device__ __forceinline__ void tile_of(uint32_t bid, uint32_t nblk, uint32_t nrb, uint32_t* rb, uint32_t* cb) {
+    uint32_t logical = bid;
+    if ((nblk & 7u) == 0) logical = (bid & 7u) * (nblk >> 3) + (bid >> 3);
+    *rb = logical % nrb;
+    *cb = logical / nrb;
+}
+
+template <int OP, int TM, int TN, int S>
+__global__ __launch_bounds__(64 * S) void k_gemm_words(GemmArgs g) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t rb, cb;
+    tile_of(blockIdx.x, gridDim.x, g.nrb, &rb, &cb);
+    const uint32_t row0 = rb * TM;
+    const uint32_t col0 = cb * 64u * TN;
+
+    uint32_t acc[TM][TN], wide[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = wide[i][j] = 0;
+
+    const uint32_t kw0 = wave * g.kw_split;
+    const uint32_t kw1 = min(g.KW, kw0 + g.kw_split);
+    const uint32_t* __restrict__ pa = g.CA + row0;
+    const uint32_t* __restrict__ pb = g.CB + col0 + lane;
+    // delayed-reduction interval in k-groups (the whole range when none is needed)
+    const uint32_t step = (OP == OP_DOT2 && g.lw) ? g.lw : (kw1 > kw0 ? kw1 - kw0 : 1u);
+    const uint32_t mask = (1u << g.b) - 1u;
+
+    for (uint32_t kc = kw0; kc < kw1; kc += step) {
+        const uint32_t ke = min(kw1, kc + step);
+#pragma unroll 4
+        for (uint32_t kw = kc; kw < ke; ++kw) {
+            uint32_t av[TM], bv[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) av[i] = pa[(size_t)kw * g.m_pad + i];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bv[j] = pb[(size_t)kw * g.n_pad + 64 * j];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = mac<OP>(av[i], bv[j], acc[i][j]);
+        }
+        if (OP == OP_DOT2 && ke < kw1) {
+            // end of a delayed-reduction interval: move the middle digit out
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    wide[i][j] += (acc[i][j] >> g.b) & mask;
+                    acc[i][j] = 0;
+                }
+        }
+    }
+    // value of each output for this wave's k range
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = (OP == OP_DOT2) ? wide[i][j] + ((acc[i][j] >> g.b) & mask) : acc[i][j];
+
+    // split-k: add the S partial sums through LDS; wave w finishes rows i = w, w+S, ...
+    if (S > 1) {
+        __shared__ uint32_t red[S][TM][TN][64];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) red[wave][i][j][lane] = acc[i][j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            if ((uint32_t)i % S != wave) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                uint32_t s = 0;
+#pragma unroll
+                for (int w = 0; w < S; ++w) s += red[w][i][j][lane];
+                acc[i][j] = s;
+            }
+        }
+    }
+
+    // epilogue: reduce mod p and store bytes
+    if (g.epi == 0) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            if (S > 1 && (uint32_t)i % S != wave) continue;
+            const uint32_t row = row0 + i;
+            if (row >= g.m) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const uint32_t col = col0 + lane + 64 * j;
+                if (col < g.n) g.C[(size_t)row * g.ldc + col] = (uint8_t)mod_u32(acc[i][j], g.p, g.pmagic);
+            }
+        }
+    } else {
+        // REDQ_e: middle digits (each < Q) of up to e outputs of this lane
+        // packed into one word at q = Q, one REDQ for all of them.
+        const RedqArgs& ra = g.ra;
+        uint64_t word = 0;
+        uint32_t nin = 0;
+        uint32_t rows[8], cols[8];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            if (S > 1 && (uint32_t)i % S != wave) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                word |= (uint64_t)acc[i][j] << (ra.b * nin);
+                rows[nin] = row0 + i;
+                cols[nin] = col0 + lane + 64 * j;
+                ++nin;
+                const bool last = (i == TM - 1 || (S > 1 && i + S > TM - 1)) && j == TN - 1;
+                if (nin == g.epi_e || last) {
+                    const uint64_t U = redq_compress(word, ra);
+                    for (uint32_t t = 0; t < nin; ++t) {
+                        const uint32_t ut = field(U, t, ra);
+                        uint32_t mu = ut;
+                        if (ra.c && t + 1 < nin) mu = correct_arith(ut, field(U, t + 1, ra), ra);
+                        if (rows[t] < g.m && cols[t] < g.n) g.C[(size_t)rows[t] * g.ldc + cols[t]] = (uint8_t)mu;
+                    }
+                    word = 0;
+                    nin = 0;
+                }
+            }
+        }
+    }
+}
+
+// Pack A (rows, reversed pairs) and B (columns) into the word layouts.
+// Grid: blocks [0, nba) pack A, blocks [nba, ...) pack B; 256 threads, one word each.
+struct PackArgs {
+    const uint8_t* A;
+    const uint8_t* B;
+    uint32_t* CA;
+    uint32_t* CB;
+    uint32_t m, n, kdim, lda, ldb;
+    uint32_t m_pad, n_pad, KW;
+    uint32_t b;       // log2 Q
+    uint32_t op;      // GemmOp
+    uint32_t nba;     // blocks for A
+};
+
+__global__ __launch_bounds__(256) void k_gemm_pack(PackArgs a) {
+    const uint32_t epw = a.op == OP_MAD ? 1u : 4u;  // entries per word
+    if (blockIdx.x < a.nba) {
+        // CA[kw][row]: thread index = kw * m_pad + row (rows fastest: coalesced stores)
+        const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+        if (t >= (uint64_t)a.KW * a.m_pad) return;
+        const uint32_t kw = (uint32_t)(t / a.m_pad), row = (uint32_t)(t % a.m_pad);
+        uint32_t e[4] = {0, 0, 0, 0};
+        if (row < a.m)
+            for (uint32_t i = 0; i < epw; ++i) {
+                const uint32_t k = kw * epw + i;
+                if (k < a.kdim) e[i] = a.A[(size_t)row * a.lda + k];
+            }
+        uint32_t w;
+        if (a.op == OP_DOT2)
+            w = ((e[0] << a.b) | e[1]) | (((e[2] << a.b) | e[3]) << 16);
+        else if (a.op == OP_DOT4)
+            w = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+        else
+            w = e[0];
+        a.CA[t] = w;
+    } else {
+        const uint64_t t = (uint64_t)(blockIdx.x - a.nba) * 256 + threadIdx.x;
+        if (t >= (uint64_t)a.KW * a.n_pad) return;
+        const uint32_t kw = (uint32_t)(t / a.n_pad), col = (uint32_t)(t % a.n_pad);
+        uint32_t e[4] = {0, 0, 0, 0};
+        if (col < a.n)
+            for (uint32_t i = 0; i < epw; ++i) {
+                const uint32_t k = kw * epw + i;
+                if (k < a.kdim) e[i] = a.B[(size_t)k * a.ldb + col];
+            }
+        uint32_t w;
+        if (a.op == OP_DOT2)
+            w = (e[0] | (e[1] << a.b)) | ((e[2] | (e[3] << a.b)) << 16);
+        else if (a.op == OP_DOT4)
+            w = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+        else
+            w = e[0];
+        a.CB[t] = w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// INT8 matrix-core comparator
+// ---------------------------------------------------------------------------
+// A8: [m_pad][k_pad] int8 (row-major, zero padded), BT8: [n_pad][k_pad] int8
+// (B transposed).  A wave computes a 32x32 block as 2x2 tiles of
+// v_mfma_i32_16x16x64_i8.  Lane l supplies row (or column) l%16 and the 16
+// consecutive k of slot l/16 for both operands, so the slots of A and B pair
+// up on the same k; lane l receives rows 4(l/16)..4(l/16)+3 of column l%16.
+
+struct MfmaArgs {
+    const uint8_t* A8;
+    const uint8_t* BT8;
+    uint8_t* C;
+    uint32_t m, n, ldc, k_pad, m_pad, n_pad;
+    uint32_t nrb;      // 64-row blocks
+    uint32_t p, pmagic;
+};
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_gemm_mfma(MfmaArgs g) {
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    uint32_t rb, cb;
+    tile_of(blockIdx.x, gridDim.x, g.nrb, &rb, &cb);
+    const uint32_t row0 = rb * 64 + (wave & 1) * 32;
+    const uint32_t col0 = cb * 64 + (wave >> 1) * 32;
+    const uint32_t r = lane & 15u, slot = lane >> 4;
+    v4i acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (v4i){0, 0, 0, 0};
+    const uint8_t* pa0 = g.A8 + (size_t)(row0 + r) * g.k_pad + slot * 16;
+    const uint8_t* pa1 = pa0 + (size_t)16 * g.k_pad;
+    const uint8_t* pb0 = g.BT8 + (size_t)(col0 + r) * g.k_pad + slot * 16;
+    const uint8_t* pb1 = pb0 + (size_t)16 * g.k_pad;
+    for (uint32_t k = 0; k < g.k_pad; k += 64) {
+        const v4i a0 = *reinterpret_cast<const v4i*>(pa0 + k);
+        const v4i a1 = *reinterpret_cast<const v4i*>(pa1 + k);
+        const v4i b0 = *reinterpret_cast<const v4i*>(pb0 + k);
+        const v4i b1 = *reinterpret_cast<const v4i*>(pb1 + k);
+        acc[0][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t row = row0 + 16 * i + 4 * slot + t;
+                const uint32_t col = col0 + 16 * j + r;
+                if (row < g.m && col < g.n)
+                    g.C[(size_t)row * g.ldc + col] = (uint8_t)mod_u32((uint32_t)acc[i][j][t], g.p, g.pmagic);
+            }
+}
+
+struct MfmaPackArgs {
+    const uint8_t* A;
+    const uint8_t* B;
+    uint8_t* A8;
+    uint8_t* BT8;
+    uint32_t m, n, kdim, lda, ldb, k_pad, m_pad, n_pad;
+    uint32_t nba;
+};
+
+// A8[row][k] = A[row][k] (zero padded); BT8[col][k] = B[k][col] (zero padded).
+__global__ __launch_bounds__(256) void k_mfma_pack(MfmaPackArgs a) {
+    if (blockIdx.x < a.nba) {
+        const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+        if (t >= (uint64_t)a.m_pad * a.k_pad) return;
+        const uint32_t row = (uint32_t)(t / a.k_pad), k = (uint32_t)(t % a.k_pad);
+        a.A8[t] = (row < a.m && k < a.kdim) ? a.A[(size_t)row * a.lda + k] : 0;
+    } else {
+        const uint64_t t = (uint64_t)(blockIdx.x - a.nba) * 256 + threadIdx.x;
+        if (t >= (uint64_t)a.n_pad * a.k_pad) return;
+        // consecutive threads walk columns (coalesced reads of B), writes are strided
+        const uint32_t k = (uint32_t)(t / a.n_pad), col = (uint32_t)(t % a.n_pad);
+        a.BT8[(size_t)col * a.k_pad + k] = (col < a.n && k < a.kdim) ? a.B[(size_t)k * a.ldb + col] : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host planning
+// ---------------------------------------------------------------------------
+
+struct GemmPlanResolved {
+    uint32_t algo;
+    uint32_t op;
+    uint32_t b;         // log2 Q (packed)
+    uint32_t lw;        // interval in k-groups (0 = none)
+    uint32_t tm, tn, s;
+    uint32_t epi;
+    uint32_t KW, m_pad, n_pad, k_pad;
+    size_t ws_bytes;
+};
+
+static uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+// Largest interval (in k) and its Q for the packed path: L (p-1)^2 < Q and
+// (p-1)(Q+1) < 2^16 so that a Kronecker pair fits one 16-bit lane, 2 log2 Q <= 32.
+// Returns false when not even four multiply-adds fit.
+bool cmm_params(uint32_t p, uint64_t kdim, uint32_t want_interval, uint32_t want_b, uint32_t* b_out,
+                uint32_t* interval_out) {
+    const uint64_t e2 = (uint64_t)(p - 1) * (p - 1);
+    uint32_t bmax = 0;
+    for (uint32_t b = 1; b <= 16; ++b)
+        if ((uint64_t)(p - 1) * ((1ull << b) + 1) < 65536ull) bmax = b;
+    if (want_b) {
+        if (want_b > bmax) return false;
+        bmax = want_b;
+    }
+    if (e2 == 0) {  // p = 2 with (p-1)^2 = 1 handled by the general formula below
+    }
+    // interval L (multiple of 4) with L * (p-1)^2 < 2^bmax
+    uint64_t lmax = e2 ? ((1ull << bmax) - 1) / e2 : kdim;
+    lmax = lmax / 4 * 4;
+    if (lmax < 4) return false;
+    uint64_t L = kdim <= lmax ? round_up(kdim ? kdim : 4, 4) : lmax;
+    if (want_interval) {
+        if (want_interval % 4 || want_interval > lmax) return false;
+        L = want_interval < round_up(kdim, 4) ? want_interval : round_up(kdim, 4);
+    }
+    // smallest Q for that interval: L (p-1)^2 < Q (strict, eq:lower)
+    uint32_t b = 1;
+    while (b < bmax && !((1ull << b) > L * e2)) ++b;
+    if (!((1ull << b) > L * e2)) return false;
+    if (want_b) b = want_b;
+    *b_out = b;
+    *interval_out = (uint32_t)L;
+    return true;
+}
+
+static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const dqt_gemm_plan* plan,
+                               GemmPlanResolved* r) {
+    memset(r, 0, sizeof(*r));
+    dqt_gemm_plan pl;
+    memset(&pl, 0, sizeof(pl));
+    if (plan) pl = *plan;
+    if (p < 2 || p > 255) return DQT_E_INVALID;
+    if (m > 0x7FFFFFFFull || n > 0x7FFFFFFFull || kdim > 0x7FFFFFFFull) return DQT_E_INVALID;
+    uint32_t algo = pl.algo;
+    uint32_t b = 0, interval = 0;
+    const bool cmm_ok = cmm_params(p, kdim, pl.interval, pl.log2Q, &b, &interval);
+    if (algo == DQT_GEMM_AUTO) algo = cmm_ok ? DQT_GEMM_CMM : DQT_GEMM_PLAIN;
+    r->algo = algo;
+    r->epi = pl.epilogue;
+    if (r->epi > 1) return DQT_E_INVALID;
+    switch (algo) {
+        case DQT_GEMM_CMM:
+            if (!cmm_ok) return (pl.interval || pl.log2Q) ? DQT_E_BOUND : DQT_E_UNSUPPORTED;
+            r->op = OP_DOT2;
+            r->b = b;
+            r->lw = interval >= round_up(kdim, 4) ? 0 : interval / 4;
+            break;
+        case DQT_GEMM_PLAIN:
+            r->op = OP_MAD;
+            if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 32)) return DQT_E_UNSUPPORTED;
+            if (r->epi) return DQT_E_UNSUPPORTED;
+            break;
+        case DQT_GEMM_DOT4:
+            r->op = OP_DOT4;
+            if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 32)) return DQT_E_UNSUPPORTED;
+            if (r->epi) return DQT_E_UNSUPPORTED;
+            break;
+        case DQT_GEMM_MFMA:
+            if (p > 128) return DQT_E_UNSUPPORTED;  // entries must be valid int8
+            if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 31)) return DQT_E_UNSUPPORTED;
+            if (r->epi) return DQT_E_UNSUPPORTED;
+            r->k_pad = (uint32_t)round_up(kdim ? kdim : 64, 64);
+            r->m_pad = (uint32_t)round_up(m ? m : 64, 64);
+            r->n_pad = (uint32_t)round_up(n ? n : 64, 64);
+            r->ws_bytes = (size_t)r->k_pad * (r->m_pad + r->n_pad);
+            return DQT_OK;
+        default:
+            return DQT_E_UNSUPPORTED;
+    }
+    r->tm = pl.tile_rows ? pl.tile_rows : 16;
+    if (r->tm != 8 && r->tm != 16 && r->tm != 32) return DQT_E_INVALID;
+    r->tn = 2;
+    const uint32_t epw = r->op == OP_MAD ? 1 : 4;
+    r->KW = (uint32_t)((kdim + epw - 1) / epw);
+    if (pl.ksplit) {
+        r->s = pl.ksplit;
+    } else {
+        // enough waves to fill the chip: aim at >= 8 waves per CU
+        const uint64_t tiles = ((m + r->tm - 1) / r->tm) * ((n + 64 * r->tn - 1) / (64 * r->tn));
+        r->s = 1;
+        while (r->s < 8 && tiles * r->s < 2048 && (uint64_t)r->KW / (r->s * 2) >= 16) r->s *= 2;
+    }
+    if (r->s != 1 && r->s != 2 && r->s != 4 && r->s != 8) return DQT_E_INVALID;
+    // split-k boundaries must fall on interval boundaries of the packed path
+    r->m_pad = (uint32_t)round_up(m ? m : 1, r->tm);
+    r->n_pad = (uint32_t)round_up(n ? n : 1, 64 * r->tn);
+    r->ws_bytes = (size_t)r->KW * (r->m_pad + r->n_pad) * sizeof(uint32_t);
+    if (r->epi == 1 && r->op != OP_DOT2) return DQT_E_UNSUPPORTED;
+    return DQT_OK;
+}
+
+template <int OP, int TM, int S>
+static void launch_words(const GemmArgs& g, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_words<OP, TM, 2, S>), dim3(grid), dim3(64 * S), 0, s, g);
+}
+
+template <int OP, int TM>
+static void launch_words_s(const GemmArgs& g, unsigned grid, uint32_t S_, hipStream_t s) {
+    switch (S_) {
+        case 1: launch_words<OP, TM, 1>(g, grid, s); break;
+        case 2: launch_words<OP, TM, 2>(g, grid, s); break;
+        case 4: launch_words<OP, TM, 4>(g, grid, s); break;
+        default: launch_words<OP, TM, 8>(g, grid, s); break;
+    }
+}
+
+template <int OP>
+static void launch_words_tm(const GemmArgs& g, unsigned grid, uint32_t tm, uint32_t S_, hipStream_t s) {
+    switch (tm) {
+        case 8: launch_words_s<OP, 8>(g, grid, S_, s); break;
+        case 16: launch_words_s<OP, 16>(g, grid, S_, s); break;
+        default: launch_words_s<OP, 32>(g, grid, S_, s); break;
+    }
+}
+
+// Packing step: operands to the word layout of the plan's kernel (either
+// operand may be skipped by passing NULL, to reuse a packed one).
+dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A, uint64_t lda, const uint8_t* B,
+                              uint64_t ldb, const GemmPlanResolved& r, void* work, hipStream_t s) {
+    if (r.algo == DQT_GEMM_MFMA) {
+        MfmaPackArgs pa;
+        pa.A = A;
+        pa.B = B;
+        pa.A8 = reinterpret_cast<uint8_t*>(work);
+        pa.BT8 = pa.A8 + (size_t)r.m_pad * r.k_pad;
+        pa.m = (uint32_t)m;
+        pa.n = (uint32_t)n;
+        pa.kdim = (uint32_t)kdim;
+        pa.lda = (uint32_t)lda;
+        pa.ldb = (uint32_t)ldb;
+        pa.k_pad = r.k_pad;
+        pa.m_pad = r.m_pad;
+        pa.n_pad = r.n_pad;
+        const uint32_t nba = A ? (uint32_t)(((uint64_t)r.m_pad * r.k_pad + 255) / 256) : 0;
+        const uint32_t nbb = B ? (uint32_t)(((uint64_t)r.n_pad * r.k_pad + 255) / 256) : 0;
+        pa.nba = nba;
+        if (nba + nbb == 0) return DQT_OK;
+        hipLaunchKernelGGL(k_mfma_pack, dim3(nba + nbb), dim3(256), 0, s, pa);
+        DQT_LAUNCH_CHECK("fgemm(mfma pack)");
+        return DQT_OK;
+    }
+    uint32_t* CA = reinterpret_cast<uint32_t*>(work);
+    uint32_t* CB = CA + (size_t)r.KW * r.m_pad;
+    PackArgs pa;
+    pa.A = A;
+    pa.B = B;
+    pa.CA = CA;
+    pa.CB = CB;
+    pa.m = (uint32_t)m;
+    pa.n = (uint32_t)n;
+    pa.kdim = (uint32_t)kdim;
+    pa.lda = (uint32_t)lda;
+    pa.ldb = (uint32_t)ldb;
+    pa.m_pad = r.m_pad;
+    pa.n_pad = r.n_pad;
+    pa.KW = r.KW;
+    pa.b = r.b;
+    pa.op = r.op;
+    const uint32_t nba = A ? (uint32_t)(((uint64_t)r.KW * r.m_pad + 255) / 256) : 0;
+    const uint32_t nbb = B ? (uint32_t)(((uint64_t)r.KW * r.n_pad + 255) / 256) : 0;
+    pa.nba = nba;
+    if (nba + nbb == 0) return DQT_OK;
+    hipLaunchKernelGGL(k_gemm_pack, dim3(nba + nbb), dim3(256), 0, s, pa);
+    DQT_LAUNCH_CHECK("fgemm(pack)");
+    return DQT_OK;
+}
+
+// Multiplication and extraction on packed operands.
+dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* C, uint64_t ldc,
+                                 const GemmPlanResolved& r, const void* work, hipStream_t s) {
+    const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
+    if (r.algo == DQT_GEMM_MFMA) {
+        MfmaArgs g;
+        g.A8 = reinterpret_cast<const uint8_t*>(work);
+        g.BT8 = g.A8 + (size_t)r.m_pad * r.k_pad;
+        g.C = C;
+        g.m = (uint32_t)m;
+        g.n = (uint32_t)n;
+        g.ldc = (uint32_t)ldc;
+        g.k_pad = r.k_pad;
+        g.m_pad = r.m_pad;
+        g.n_pad = r.n_pad;
+        g.nrb = r.m_pad / 64;
+        g.p = p;
+        g.pmagic = pmagic;
+        const unsigned grid = (r.m_pad / 64) * (r.n_pad / 64);
+        hipLaunchKernelGGL(k_gemm_mfma, dim3(grid), dim3(256), 0, s, g);
+        DQT_LAUNCH_CHECK("fgemm(mfma)");
+        return DQT_OK;
+    }
+    GemmArgs g;
+    memset(&g, 0, sizeof(g));
+    g.CA = reinterpret_cast<const uint32_t*>(work);
+    g.CB = g.CA + (size_t)r.KW * r.m_pad;
+    g.C = C;
+    g.m = (uint32_t)m;
+    g.n = (uint32_t)n;
+    g.ldc = (uint32_t)ldc;
+    g.m_pad = r.m_pad;
+    g.n_pad = r.n_pad;
+    g.KW = r.KW;
+    // split-k boundaries on interval boundaries (packed path)
+    uint32_t ks = (r.KW + r.s - 1) / r.s;
+    if (r.lw) ks = (uint32_t)round_up(ks, r.lw);
+    g.kw_split = ks;
+    g.lw = r.lw;
+    g.nrb = r.m_pad / r.tm;
+    g.ncb = r.n_pad / (64 * r.tn);
+    g.b = r.b ? r.b : 1;
+    g.p = p;
+    g.pmagic = pmagic;
+    g.epi = r.epi;
+    if (r.epi == 1) {
+        // The gathered values are whole dot products (all intervals and all
+        // k-splits added), at most kdim (p-1)^2: they are the digits of the
+        // REDQ word, so its q is the smallest power of two above that bound,
+        // and e = floor(53 / log2 q) of them share one word (section 7.6.1).
+        const uint64_t maxdot = (uint64_t)kdim * (p - 1) * (p - 1);
+        uint32_t be = residue_bits(p);
+        while (be < 32 && (1ull << be) <= maxdot) ++be;
+        uint32_t e = 53 / be;
+        if (e > 8) e = 8;
+        if (e < 1) return DQT_E_UNSUPPORTED;
+        g.epi_e = e;
+        DQT_TRY(make_redq_args(p, be, e, e * be, &g.ra));
+    }
+    const unsigned grid = g.nrb * g.ncb;
+    switch (r.op) {
+        case OP_DOT2: launch_words_tm<OP_DOT2>(g, grid, r.tm, r.s, s); break;
+        case OP_DOT4: launch_words_tm<OP_DOT4>(g, grid, r.tm, r.s, s); break;
+        default: launch_words_tm<OP_MAD>(g, grid, r.tm, r.s, s); break;
+    }
+    DQT_LAUNCH_CHECK("fgemm");
+    return DQT_OK;
+}
+
+dqt_status fgemm_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A, uint64_t lda,
+                         const uint8_t* B, uint64_t ldb, uint8_t* C, uint64_t ldc, const GemmPlanResolved& r,
+                         void* work, hipStream_t s) {
+    DQT_TRY(fgemm_pack_enqueue(m, n, kdim, A, lda, B, ldb, r, work, s));
+    return fgemm_compute_enqueue(p, m, n, kdim, C, ldc, r, work, s);
+}
+
+dqt_status fgemm_resolve(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const dqt_gemm_plan* plan,
+                         GemmPlanResolved* r) {
+    return resolve_plan(p, m, n, kdim, plan, r);
+}
+
+}  // namespace dqt
+
+using namespace dqt;
+
+extern "C" size_t dqt_fgemm_workspace_size(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim,
+                                           const dqt_gemm_plan* plan) {
+    GemmPlanResolved r;
+    if (resolve_plan(p, m, n, kdim, plan, &r) != DQT_OK) return 0;
+    return r.ws_bytes;
+}
+
+static dqt_status fgemm_common_checks(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const dqt_gemm_plan* plan,
+                                      size_t work_bytes, const void* d_work, GemmPlanResolved* r) {
+    DQT_TRY(resolve_plan(p, m, n, kdim, plan, r));
+    if (r->ws_bytes && (!d_work || work_bytes < r->ws_bytes)) return DQT_E_WORKSPACE;
+    return DQT_OK;
+}
+
+extern "C" dqt_status dqt_fgemm_pack(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* d_A,
+                                     uint64_t lda, const uint8_t* d_B, uint64_t ldb, const dqt_gemm_plan* plan,
+                                     void* d_work, size_t work_bytes, void* stream) {
+    GemmPlanResolved r;
+    DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
+    if (m == 0 || n == 0) return DQT_OK;
+    if (!d_A && !d_B) return DQT_E_INVALID;
+    if ((d_A && lda < kdim) || (d_B && ldb < n) || lda > 0xFFFFFFFFull || ldb > 0xFFFFFFFFull) return DQT_E_INVALID;
+    DQT_TRY(fgemm_common_checks(p, m, n, kdim, plan, work_bytes, d_work, &r));
+    DQT_TRY(ensure_device_ready());
+    return fgemm_pack_enqueue(m, n, kdim, d_A, lda, d_B, ldb, r, d_work, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* d_C, uint64_t ldc,
+                                        const dqt_gemm_plan* plan, const void* d_work, size_t work_bytes,
+                                        void* stream) {
+    GemmPlanResolved r;
+    DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
+    if (m == 0 || n == 0) return DQT_OK;
+    if (!d_C || ldc < n || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
+    DQT_TRY(fgemm_common_checks(p, m, n, kdim, plan, work_bytes, d_work, &r));
+    DQT_TRY(ensure_device_ready());
+    return fgemm_compute_enqueue(p, m, n, kdim, d_C, ldc, r, d_work, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* d_A, uint64_t lda,
+                                const uint8_t* d_B, uint64_t ldb, uint8_t* d_C, uint64_t ldc,
+                                const dqt_gemm_plan* plan, void* d_work, size_t work_bytes, void* stream) {
+    GemmPlanResolved r;
+    DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
+    if (m == 0 || n == 0) return DQT_OK;
+    if (!d_A || !d_B || !d_C) return DQT_E_INVALID;
+    if (lda < kdim || ldb < n || ldc < n) return DQT_E_INVALID;
+    if (lda > 0xFFFFFFFFull || ldb > 0xFFFFFFFFull || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
+    if (r.ws_bytes && (!d_work || work_bytes < r.ws_bytes)) return DQT_E_WORKSPACE;
+    DQT_TRY(ensure_device_ready());
+    return fgemm_enqueue(p, m, n, kdim, d_A, lda, d_B, ldb, d_C, ldc, r, d_work, reinterpret_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,37 @@
+// Host-side internals shared by the libdqt translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dqt.h"
+#include "dqt_device.h"
+
+namespace dqt {
+
+// Record a message for dqt_last_error() (thread-local).
+void set_error(const char* msg);
+// Map a HIP error to DQT_E_DEVICE (recording its text), hipSuccess to DQT_OK.
+dqt_status hip_status(hipError_t e, const char* what);
+// One-time per-device set-up and self-check (rounding mode of binary64 is
+// round-to-nearest, as algorithm AFDIV's choice of invp assumes).
+dqt_status ensure_device_ready();
+// Compute units of the current device (cached per device).
+int device_cus();
+// REDQ_nres parameters for (p, b = log2 q, nres) on words below 2^word_bits.
+// DQT_E_BOUND if nres*b > 53 or word_bits > 53.
+dqt_status make_redq_args(uint32_t p, uint32_t b, uint32_t nres, uint32_t word_bits, RedqArgs* out);
+// ceil(log2 p) for p >= 2.
+uint32_t residue_bits(uint32_t p);
+// Grid size for a streaming kernel over `items` work items of `per_block` each.
+unsigned stream_grid(uint64_t items, unsigned per_block, unsigned waves_per_cu = 8);
+
+}  // namespace dqt
+
+#define DQT_TRY(expr)                         \
+    do {                                      \
+        dqt_status s_ = (expr);               \
+        if (s_ != DQT_OK) return s_;          \
+    } while (0)
+
+#define DQT_LAUNCH_CHECK(what) DQT_TRY(::dqt::hip_status(hipGetLastError(), what))

@@ -1,0 +1,370 @@
+"""Python binding of libdqt (ctypes): argument marshalling only.
+
+Every function forwards torch device tensors (as raw device pointers) and the
+current HIP stream to the C ABI declared in include/dqt.h; every step of the
+path runs in the library's HIP kernels.  There is no CPU fallback: if the
+library is missing or the device is not a GPU the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdqt.so")
+
+DQT_OK, DQT_E_INVALID, DQT_E_BOUND, DQT_E_UNSUPPORTED, DQT_E_DEVICE, DQT_E_WORKSPACE = 0, -1, -2, -3, -4, -5
+
+GEMM_AUTO, GEMM_CMM, GEMM_PLAIN, GEMM_DOT4, GEMM_MFMA, GEMM_RIGHT = 0, 1, 2, 3, 4, 5
+EPI_REDC, EPI_REDQ = 0, 1
+
+
+class DQTError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {_status_str(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+class _Qadic(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint32), ("log2q", ctypes.c_uint32), ("k_coeffs", ctypes.c_uint32),
+                ("nres", ctypes.c_uint32), ("n_accum", ctypes.c_uint64)]
+
+
+class _GemmPlan(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_uint32), ("log2Q", ctypes.c_uint32), ("interval", ctypes.c_uint32),
+                ("tile_rows", ctypes.c_uint32), ("ksplit", ctypes.c_uint32), ("epilogue", ctypes.c_uint32)]
+
+
+class _GemmDesc(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("m", ctypes.c_uint32), ("n", ctypes.c_uint32), ("kdim", ctypes.c_uint32),
+                ("lda", ctypes.c_uint32), ("ldb", ctypes.c_uint32), ("ldc", ctypes.c_uint32),
+                ("p", ctypes.c_uint32), ("algo", ctypes.c_uint32)]
+
+
+@dataclass(frozen=True)
+class Qadic:
+    """q-adic packing parameters (p, q = 2^log2q, k coefficients, nres digits, n accumulated products)."""
+    p: int
+    log2q: int
+    k_coeffs: int
+    nres: int
+    n_accum: int = 1
+
+    def _c(self) -> _Qadic:
+        return _Qadic(self.p, self.log2q, self.k_coeffs, self.nres, self.n_accum)
+
+
+@dataclass(frozen=True)
+class GemmPlan:
+    algo: int = GEMM_AUTO
+    log2Q: int = 0
+    interval: int = 0
+    tile_rows: int = 0
+    ksplit: int = 0
+    epilogue: int = EPI_REDC
+
+    def _c(self) -> _GemmPlan:
+        return _GemmPlan(self.algo, self.log2Q, self.interval, self.tile_rows, self.ksplit, self.epilogue)
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdqt.so not found at {LIB_PATH}; build it with "
+                          f"`python -m paper_0809_0063_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    V, U32, U64, I, SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+    QP = ctypes.POINTER(_Qadic)
+    sigs = {
+        "dqt_qadic_check": [QP],
+        "dqt_qadic_choose": [U32, U32, U64, QP],
+        "dqt_pack": [V, U64, QP, I, V, V],
+        "dqt_polymul": [V, V, U64, QP, V, V],
+        "redq_unpack": [V, U64, QP, V, V, V],
+        "dqt_polymul_u8": [V, V, U64, U32, U32, U32, V, V],
+        "dqt_gf_mul_u8": [V, V, U64, U32, U32, U32, V, V, V],
+        "dqt_polymul_plain_u8": [V, V, U64, U32, U32, V, V],
+        "dqt_gf_mul_plain_u8": [V, V, U64, U32, U32, V, V, V],
+        "dqt_polymul_fqt_u8": [V, U32, V, U32, U64, U32, U32, V, V],
+        "dqt_fgemm": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
+        "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, V, SZ, V],
+        "dqt_fgemm_pack": [U32, U64, U64, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
+        "dqt_fgemm_compute": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
+    }
+    for name, args in sigs.items():
+        if not hasattr(lib, name):
+            continue  # reported by the ABI export test
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    if hasattr(lib, "dqt_fgemm_workspace_size"):
+        lib.dqt_fgemm_workspace_size.argtypes = [U32, U64, U64, U64, ctypes.POINTER(_GemmPlan)]
+        lib.dqt_fgemm_workspace_size.restype = SZ
+    if hasattr(lib, "dqt_fgemm_batched_workspace_size"):
+        lib.dqt_fgemm_batched_workspace_size.argtypes = [ctypes.POINTER(_GemmDesc), U32]
+        lib.dqt_fgemm_batched_workspace_size.restype = SZ
+    for name in ("dqt_status_str",):
+        getattr(lib, name).argtypes = [ctypes.c_int]
+        getattr(lib, name).restype = ctypes.c_char_p
+    lib.dqt_last_error.argtypes = []
+    lib.dqt_last_error.restype = ctypes.c_char_p
+    lib.dqt_version.argtypes = []
+    lib.dqt_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def lib():
+    """The loaded ctypes library (raises ImportError if it was not built)."""
+    return _load()
+
+
+def _status_str(s: int) -> str:
+    try:
+        return _load().dqt_status_str(s).decode()
+    except Exception:
+        return "status"
+
+
+def _check(status: int, where: str):
+    if status != DQT_OK:
+        detail = _load().dqt_last_error().decode() if status == DQT_E_DEVICE else ""
+        raise DQTError(status, where, detail)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_modulus(modulus: Sequence[int]):
+    arr = (ctypes.c_uint8 * len(modulus))(*[int(x) for x in modulus])
+    return arr
+
+
+def version() -> str:
+    return _load().dqt_version().decode()
+
+
+# --- parameters --------------------------------------------------------------
+
+def qadic_check(q: Qadic) -> int:
+    """Status of dqt_qadic_check (0 = the parameters satisfy eq:bounds with beta = 53)."""
+    c = q._c()
+    return _load().dqt_qadic_check(ctypes.byref(c))
+
+
+def qadic_choose(p: int, k_coeffs: int, n_accum: int = 1) -> Qadic:
+    c = _Qadic()
+    _check(_load().dqt_qadic_choose(p, k_coeffs, n_accum, ctypes.byref(c)), "dqt_qadic_choose")
+    return Qadic(c.p, c.log2q, c.k_coeffs, c.nres, c.n_accum)
+
+
+# --- one-word path -------------------------------------------------------------
+
+def pack(coeffs: torch.Tensor, q: Qadic, reverse: bool = False, out: Optional[torch.Tensor] = None, stream=None):
+    """DQT words (int64 bit patterns) of coeffs uint8 [N, k]."""
+    n = coeffs.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=coeffs.device)
+    c = q._c()
+    _check(_load().dqt_pack(_dev(coeffs, "coeffs", torch.uint8), n, ctypes.byref(c), int(reverse),
+                            _dev(out, "out", torch.int64), _stream(stream)), "dqt_pack")
+    return out
+
+
+def polymul_words(a: torch.Tensor, b: torch.Tensor, q: Qadic, out: Optional[torch.Tensor] = None, stream=None):
+    n = a.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=a.device)
+    c = q._c()
+    _check(_load().dqt_polymul(_dev(a, "a", torch.int64), _dev(b, "b", torch.int64), n, ctypes.byref(c),
+                               _dev(out, "out", torch.int64), _stream(stream)), "dqt_polymul")
+    return out
+
+
+def redq_unpack(r: torch.Tensor, q: Qadic, modulus: Optional[Sequence[int]] = None,
+                out: Optional[torch.Tensor] = None, stream=None):
+    """REDQ of packed words r (int64 [N]) -> uint8 [N, nres] (or [N, k] with a GF modulus)."""
+    n = r.shape[0]
+    width = q.nres if modulus is None else q.k_coeffs
+    if out is None:
+        out = torch.empty((n, width), dtype=torch.uint8, device=r.device)
+    c = q._c()
+    mod = _host_modulus(modulus) if modulus is not None else None
+    _check(_load().redq_unpack(_dev(r, "r", torch.int64), n, ctypes.byref(c),
+                               ctypes.cast(mod, ctypes.c_void_p) if mod is not None else None,
+                               _dev(out, "out", torch.uint8), _stream(stream)), "redq_unpack")
+    return out
+
+
+def _u8_pair(a, b):
+    if a.dim() != 2 or b.dim() != 2 or a.shape[0] != b.shape[0]:
+        raise ValueError("a and b must be [N, k] with the same N")
+
+
+def polymul_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Tensor] = None, stream=None,
+               log2q: int = 0):
+    """Packed fused product: uint8 [N, k] x uint8 [N, k] -> uint8 [N, 2k-1] over F_p (q = 2^log2q, 0 = smallest)."""
+    _u8_pair(a, b)
+    n, k = a.shape
+    if b.shape[1] != k:
+        raise ValueError("a and b must have the same k")
+    if out is None:
+        out = torch.empty((n, 2 * k - 1), dtype=torch.uint8, device=a.device)
+    _check(_load().dqt_polymul_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), n, k, p, log2q,
+                                  _dev(out, "out", torch.uint8), _stream(stream)), "dqt_polymul_u8")
+    return out
+
+
+def polymul_plain_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Tensor] = None, stream=None):
+    _u8_pair(a, b)
+    n, k = a.shape
+    if out is None:
+        out = torch.empty((n, 2 * k - 1), dtype=torch.uint8, device=a.device)
+    _check(_load().dqt_polymul_plain_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), n, k, p,
+                                        _dev(out, "out", torch.uint8), _stream(stream)), "dqt_polymul_plain_u8")
+    return out
+
+
+def polymul_fqt_u8(a: torch.Tensor, b: torch.Tensor, p: int, block: int = 0, out: Optional[torch.Tensor] = None,
+                   stream=None):
+    """Long products by blocks (FQT): uint8 [N, na] x uint8 [N, nb] -> uint8 [N, na+nb-1]."""
+    _u8_pair(a, b)
+    n, na = a.shape
+    nb = b.shape[1]
+    if out is None:
+        out = torch.empty((n, na + nb - 1), dtype=torch.uint8, device=a.device)
+    _check(_load().dqt_polymul_fqt_u8(_dev(a, "a", torch.uint8), na, _dev(b, "b", torch.uint8), nb, n, p, block,
+                                      _dev(out, "out", torch.uint8), _stream(stream)), "dqt_polymul_fqt_u8")
+    return out
+
+
+def gf_mul_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
+              out: Optional[torch.Tensor] = None, stream=None, log2q: int = 0):
+    """Packed GF(p^k) products: uint8 [N, k] each, modulus = k+1 monic coefficients (low first)."""
+    _u8_pair(a, b)
+    n, k = a.shape
+    if out is None:
+        out = torch.empty((n, k), dtype=torch.uint8, device=a.device)
+    mod = _host_modulus(modulus)
+    _check(_load().dqt_gf_mul_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), n, k, p, log2q,
+                                 ctypes.cast(mod, ctypes.c_void_p), _dev(out, "out", torch.uint8), _stream(stream)),
+           "dqt_gf_mul_u8")
+    return out
+
+
+def gf_mul_plain_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
+                    out: Optional[torch.Tensor] = None, stream=None):
+    _u8_pair(a, b)
+    n, k = a.shape
+    if out is None:
+        out = torch.empty((n, k), dtype=torch.uint8, device=a.device)
+    mod = _host_modulus(modulus)
+    _check(_load().dqt_gf_mul_plain_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), n, k, p,
+                                       ctypes.cast(mod, ctypes.c_void_p), _dev(out, "out", torch.uint8),
+                                       _stream(stream)), "dqt_gf_mul_plain_u8")
+    return out
+
+
+# --- matrix products -----------------------------------------------------------
+
+def fgemm_workspace_size(p: int, m: int, n: int, kdim: int, plan: Optional[GemmPlan] = None) -> int:
+    pc = plan._c() if plan is not None else None
+    return int(_load().dqt_fgemm_workspace_size(p, m, n, kdim, ctypes.byref(pc) if pc is not None else None))
+
+
+def fgemm(A: torch.Tensor, B: torch.Tensor, p: int, plan: Optional[GemmPlan] = None,
+          out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None, stream=None):
+    """C = A.B mod p for uint8 A [m, k], B [k, n] (row-major, contiguous)."""
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("A [m,k] and B [k,n] required")
+    m, kdim = A.shape
+    n = B.shape[1]
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+    ws = fgemm_workspace_size(p, m, n, kdim, plan)
+    if ws and (workspace is None or workspace.numel() * workspace.element_size() < ws):
+        workspace = torch.empty(ws, dtype=torch.uint8, device=A.device)
+    pc = plan._c() if plan is not None else None
+    wptr = _dev(workspace, "workspace") if ws else None
+    wbytes = workspace.numel() * workspace.element_size() if ws else 0
+    _check(_load().dqt_fgemm(p, m, n, kdim, _dev(A, "A", torch.uint8), kdim, _dev(B, "B", torch.uint8), n,
+                             _dev(out, "C", torch.uint8), n, ctypes.byref(pc) if pc is not None else None,
+                             wptr, wbytes, _stream(stream)), "dqt_fgemm")
+    return out
+
+
+def fgemm_pack(A: Optional[torch.Tensor], B: Optional[torch.Tensor], p: int, plan: Optional[GemmPlan] = None,
+               workspace: Optional[torch.Tensor] = None, shape=None, stream=None):
+    """Packing phase of fgemm into `workspace` (A or B may be None to keep a packed copy)."""
+    if shape is None:
+        m, kdim = A.shape
+        n = B.shape[1]
+    else:
+        m, n, kdim = shape
+    pc = plan._c() if plan is not None else None
+    _check(_load().dqt_fgemm_pack(p, m, n, kdim, _dev(A, "A", torch.uint8) if A is not None else None, kdim,
+                                  _dev(B, "B", torch.uint8) if B is not None else None, n,
+                                  ctypes.byref(pc) if pc is not None else None, _dev(workspace, "workspace"),
+                                  workspace.numel() * workspace.element_size(), _stream(stream)), "dqt_fgemm_pack")
+
+
+def fgemm_compute(C: torch.Tensor, p: int, kdim: int, plan: Optional[GemmPlan] = None,
+                  workspace: Optional[torch.Tensor] = None, stream=None):
+    """Multiplication phase of fgemm on the packed operands in `workspace`; writes C [m, n]."""
+    m, n = C.shape
+    pc = plan._c() if plan is not None else None
+    _check(_load().dqt_fgemm_compute(p, m, n, kdim, _dev(C, "C", torch.uint8), n,
+                                     ctypes.byref(pc) if pc is not None else None, _dev(workspace, "workspace"),
+                                     workspace.numel() * workspace.element_size(), _stream(stream)),
+           "dqt_fgemm_compute")
+    return C
+
+
+def make_descs(items):
+    """ctypes descriptor array from (A, B, C, p, algo) tuples of square/rectangular uint8 device tensors."""
+    arr = (_GemmDesc * len(items))()
+    for i, (A, B, C, p, algo) in enumerate(items):
+        m, kdim = A.shape
+        n = B.shape[1]
+        arr[i] = _GemmDesc(A.data_ptr(), B.data_ptr(), C.data_ptr(), m, n, kdim, kdim, n, n, p, algo)
+    return arr
+
+
+def fgemm_batched_workspace_size(descs) -> int:
+    return int(_load().dqt_fgemm_batched_workspace_size(descs, len(descs)))
+
+
+def fgemm_batched(descs, workspace: torch.Tensor, stream=None):
+    """Run every descriptor (from make_descs) in one persistent launch."""
+    ws = fgemm_batched_workspace_size(descs)
+    if workspace.numel() * workspace.element_size() < ws:
+        raise ValueError(f"workspace needs {ws} bytes")
+    _check(_load().dqt_fgemm_batched(descs, len(descs), _dev(workspace, "workspace"),
+                                     workspace.numel() * workspace.element_size(), _stream(stream)),
+           "dqt_fgemm_batched")

@@ -1,0 +1,106 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol, and
+its host-only logic (a priori bounds, plans, argument checks) is right."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dqt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:dqt_status|size_t|const char\s*\*|char\s*\*|void)\s*\*?\s*(\w+)\s*\(",
+                       text, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_0809_0063_amd import build, dqt
+    build.ensure_built()
+    return dqt
+
+
+def test_header_parses():
+    names = declared_functions()
+    for must in ("dqt_pack", "dqt_polymul", "redq_unpack", "dqt_fgemm", "dqt_qadic_check", "dqt_qadic_choose",
+                 "dqt_fgemm_batched", "dqt_polymul_u8", "dqt_gf_mul_u8"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(D):
+    lib = D.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(D):
+    lib = D.lib()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.dqt_status_str(s)
+    assert b"gfx950" in lib.dqt_version()
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 11, 13, 31, 127, 251])
+def test_qadic_choose_matches_eq_bounds(D, p):
+    for k in range(1, 10):
+        for n in (1, 2, 3, 7, 100):
+            want = None
+            for b in range(1, 33):
+                if O.dqt_bounds_ok(p, k, n, b, 53):
+                    want = b
+                    break
+            if want is None:
+                with pytest.raises(D.DQTError) as e:
+                    D.qadic_choose(p, k, n)
+                assert e.value.status == D.DQT_E_BOUND
+            else:
+                q = D.qadic_choose(p, k, n)
+                assert (q.log2q, q.nres, q.k_coeffs, q.n_accum) == (want, 2 * k - 1, k, n)
+
+
+def test_qadic_check_grid(D):
+    for p in (2, 3, 5, 7, 251):
+        for k in (1, 2, 4, 7):
+            for n in (1, 3, 1000):
+                for b in range(1, 33):
+                    st = D.qadic_check(D.Qadic(p, b, k, 2 * k - 1, n))
+                    assert (st == 0) == O.dqt_bounds_ok(p, k, n, b, 53), (p, k, n, b)
+    # the degree-3 polynomials over F_3 at q = 2^6 admit up to 3 accumulated products
+    assert D.qadic_check(D.Qadic(3, 6, 4, 7, 3)) == 0
+    assert D.qadic_check(D.Qadic(3, 6, 4, 7, 4)) == D.DQT_E_BOUND
+    assert D.qadic_check(D.Qadic(1, 6, 4, 7, 1)) == D.DQT_E_INVALID
+
+
+def test_argument_errors_before_any_device_call(D):
+    lib = D.lib()
+    # p out of range, k too large for one word, bounds violated: refused on the host
+    assert lib.dqt_polymul_u8(None, None, 10, 4, 1, 0, None, None) == D.DQT_E_INVALID
+    assert lib.dqt_polymul_u8(None, None, 10, 10, 251, 0, None, None) == D.DQT_E_UNSUPPORTED
+    assert lib.dqt_polymul_u8(None, None, 10, 4, 3, 4, None, None) == D.DQT_E_BOUND
+    assert lib.dqt_polymul_u8(None, None, 0, 4, 3, 6, None, None) == D.DQT_OK   # empty: no-op
+    mod_bad = (ctypes.c_uint8 * 6)(1, 2, 0, 0, 0, 2)  # not monic
+    assert lib.dqt_gf_mul_u8(None, None, 10, 5, 3, 0, mod_bad, None, None) == D.DQT_E_INVALID
+    assert lib.dqt_gf_mul_u8(None, None, 10, 5, 3, 0, None, None, None) == D.DQT_E_INVALID
+    q = D.Qadic(3, 13, 1, 5, 1)._c()  # 5 * 13 > 53
+    assert lib.redq_unpack(None, 10, ctypes.byref(q), None, None, None) == D.DQT_E_BOUND
+    assert lib.dqt_fgemm(300, 4, 4, 4, None, 4, None, 4, None, 4, None, None, 0, None) == D.DQT_E_INVALID
+    assert lib.dqt_fgemm(3, 0, 4, 4, None, 4, None, 4, None, 4, None, None, 0, None) == D.DQT_OK
+    assert lib.dqt_polymul_fqt_u8(None, 0, None, 4, 10, 3, 0, None, None) == D.DQT_E_INVALID
+
+
+def test_fgemm_workspace_sizes(D):
+    # packed path: words of four entries for the rows of A and the columns of B
+    ws = D.fgemm_workspace_size(3, 1024, 1024, 1024)
+    assert ws == 256 * (1024 + 1024) * 4
+    assert D.fgemm_workspace_size(3, 1024, 1024, 1024, D.GemmPlan(algo=D.GEMM_PLAIN)) == 1024 * 2048 * 4
+    assert D.fgemm_workspace_size(3, 100, 100, 100, D.GemmPlan(algo=D.GEMM_MFMA)) == 128 * (128 + 128)
+    # packing bounds: a Kronecker pair must fit a 16-bit lane, the interval must fit Q
+    assert D.fgemm_workspace_size(251, 64, 64, 64, D.GemmPlan(algo=D.GEMM_CMM)) == 0
+    assert D.fgemm_workspace_size(3, 64, 64, 64, D.GemmPlan(algo=D.GEMM_CMM, interval=8192)) == 0

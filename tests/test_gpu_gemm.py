@@ -1,0 +1,117 @@
+"""GPU parity: F_p matrix products (packed CMM, plain, dot4, INT8 matrix cores) vs the oracle, bit-exact."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0809_0063_amd import inputs
+from tests.gpu_util import device, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dqt():
+    device()
+    from paper_0809_0063_amd import dqt as D
+    return D
+
+
+def _all_algos(D):
+    return [D.GemmPlan(algo=D.GEMM_CMM), D.GemmPlan(algo=D.GEMM_CMM, epilogue=D.EPI_REDQ),
+            D.GemmPlan(algo=D.GEMM_PLAIN), D.GemmPlan(algo=D.GEMM_DOT4), D.GemmPlan(algo=D.GEMM_MFMA)]
+
+
+def test_fgemm_1024_p3(dqt):
+    """C = A.B mod 3 with m = n = k = 1024 (uniform entries) and the all-2 worst case."""
+    A, B = inputs.gemm_pair(1024, 1024, 1024, 3)
+    ref = O.fgemm(A, B, 3)
+    dA, dB = to_dev(A), to_dev(B)
+    for plan in [None] + _all_algos(dqt):
+        got = to_host(dqt.fgemm(dA, dB, 3, plan=plan))
+        assert (got == ref).all(), plan
+    W = to_dev(inputs.worst_case((1024, 1024), 3))
+    for plan in [None] + _all_algos(dqt):
+        got = to_host(dqt.fgemm(W, W, 3, plan=plan))
+        assert (got == (1024 * 4) % 3).all(), plan
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 11, 13])
+def test_fgemm_bound_edges_worst_case(dqt, p):
+    """All entries p-1 at inner dimensions around the interval limits (digits at their maximum)."""
+    for k in (1, 3, 4, 5, 63, 64, 65, 227, 228, 229, 511, 512, 513, 1020, 1021, 2047, 2048, 2049, 4095, 4096, 4097):
+        A = to_dev(inputs.worst_case((33, k), p))
+        B = to_dev(inputs.worst_case((k, 65), p))
+        want = (k * (p - 1) ** 2) % p
+        for plan in [None, dqt.GemmPlan(algo=dqt.GEMM_PLAIN), dqt.GemmPlan(algo=dqt.GEMM_CMM, epilogue=dqt.EPI_REDQ)]:
+            got = to_host(dqt.fgemm(A, B, p, plan=plan))
+            assert (got == want).all(), (p, k, plan)
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 11])
+def test_fgemm_ragged_shapes(dqt, p):
+    g = np.random.default_rng(p)
+    for _ in range(12):
+        m, n, k = (int(x) for x in g.integers(1, 300, size=3))
+        A, B = inputs.gemm_pair(m, n, k, p, seed=int(g.integers(1 << 30)))
+        ref = O.fgemm(A, B, p)
+        dA, dB = to_dev(A), to_dev(B)
+        for plan in [None] + _all_algos(dqt):
+            got = to_host(dqt.fgemm(dA, dB, p, plan=plan))
+            assert (got == ref).all(), (m, n, k, plan)
+
+
+def test_fgemm_plans(dqt):
+    """Every tile/split/interval choice gives the same bytes."""
+    p = 5
+    A, B = inputs.gemm_pair(200, 300, 1000, p, seed=11)
+    ref = O.fgemm(A, B, p)
+    dA, dB = to_dev(A), to_dev(B)
+    for tm in (8, 16, 32):
+        for ks in (1, 2, 4, 8):
+            if tm == 32 and ks == 8:
+                continue
+            for interval in (0, 4, 64, 500, 508):
+                for epi in (dqt.EPI_REDC, dqt.EPI_REDQ):
+                    plan = dqt.GemmPlan(algo=dqt.GEMM_CMM, interval=interval, tile_rows=tm, ksplit=ks, epilogue=epi)
+                    got = to_host(dqt.fgemm(dA, dB, p, plan=plan))
+                    assert (got == ref).all(), plan
+            for algo in (dqt.GEMM_PLAIN, dqt.GEMM_DOT4):
+                got = to_host(dqt.fgemm(dA, dB, p, plan=dqt.GemmPlan(algo=algo, tile_rows=tm, ksplit=ks)))
+                assert (got == ref).all(), (algo, tm, ks)
+
+
+def test_fgemm_large_prime_routes_plain(dqt):
+    for p in (31, 127, 251):
+        A, B = inputs.gemm_pair(70, 90, 300, p, seed=p)
+        ref = O.fgemm(A, B, p)
+        got = to_host(dqt.fgemm(to_dev(A), to_dev(B), p))
+        assert (got == ref).all()
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.fgemm(to_dev(A), to_dev(B), 251, plan=dqt.GemmPlan(algo=dqt.GEMM_CMM))
+    assert e.value.status in (dqt.DQT_E_UNSUPPORTED, dqt.DQT_E_BOUND)
+
+
+def test_fgemm_identity_permutation(dqt):
+    p = 7
+    g = np.random.default_rng(3)
+    A = inputs.uniform_residues((129, 129), p, 5)
+    I = np.eye(129, dtype=np.uint8)
+    P = I[g.permutation(129)]
+    dA = to_dev(A)
+    assert (to_host(dqt.fgemm(dA, to_dev(I), p)) == A).all()
+    assert (to_host(dqt.fgemm(to_dev(P), dA, p)) == (P.astype(np.int64) @ A) % p).all()
+
+
+def test_fgemm_workspace_errors(dqt):
+    import torch
+    A = torch.zeros((64, 64), dtype=torch.uint8, device=device())
+    ws = dqt.fgemm_workspace_size(3, 64, 64, 64)
+    assert ws > 0
+    small = torch.zeros(ws - 1, dtype=torch.uint8, device=device())
+    C = torch.zeros((64, 64), dtype=torch.uint8, device=device())
+    from paper_0809_0063_amd.dqt import _load, _stream
+    import ctypes
+    st = _load().dqt_fgemm(3, 64, 64, 64, ctypes.c_void_p(A.data_ptr()), 64, ctypes.c_void_p(A.data_ptr()), 64,
+                           ctypes.c_void_p(C.data_ptr()), 64, None, ctypes.c_void_p(small.data_ptr()), ws - 1,
+                           _stream(None))
+    assert st == dqt.DQT_E_WORKSPACE

@@ -1,0 +1,206 @@
+"""GPU parity: one-word polynomial products, REDQ unpack, GF(p^k) products (bit-exact vs the oracle).
+
+All calls go through the C ABI (paper_0809_0063_amd.dqt).  Inputs come from the
+seeded generator; expected values from the CPU oracle only.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_0809_0063_amd import inputs
+from tests.gpu_util import device, to_dev, to_host, unaligned_like, unaligned_empty
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dqt():
+    device()
+    from paper_0809_0063_amd import dqt as D
+    return D
+
+
+def test_small_polymul_workload(dqt):
+    """65,536 products of degree-3 polynomials over F_3 (q = 2^6, one 64-bit word)."""
+    a, b = inputs.polymul_pairs(65536, 4, 3)
+    ref = O.polymul(a, b, 3)
+    got = to_host(dqt.polymul_u8(to_dev(a), to_dev(b), 3, log2q=6))
+    assert got.shape == (65536, 7)
+    assert (got == ref).all()
+    # every admissible q gives the same bytes (q > 16 and 7 log2 q <= 53)
+    for lq in (5, 7):
+        assert (to_host(dqt.polymul_u8(to_dev(a), to_dev(b), 3, log2q=lq)) == ref).all()
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.polymul_u8(to_dev(a), to_dev(b), 3, log2q=4)
+    assert e.value.status == dqt.DQT_E_BOUND
+    plain = to_host(dqt.polymul_plain_u8(to_dev(a), to_dev(b), 3))
+    assert (plain == ref).all()
+
+
+@pytest.mark.parametrize("p,k", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3), (3, 4)])
+def test_polymul_all_pairs(dqt, p, k):
+    elems = np.array(list(itertools.product(range(p), repeat=k)), dtype=np.uint8)
+    a = np.repeat(elems, len(elems), axis=0)
+    b = np.tile(elems, (len(elems), 1))
+    ref = O.polymul(a, b, p)
+    assert (to_host(dqt.polymul_u8(to_dev(a), to_dev(b), p)) == ref).all()
+    assert (to_host(dqt.polymul_plain_u8(to_dev(a), to_dev(b), p)) == ref).all()
+
+
+def _supported_pairs():
+    out = []
+    for p in (2, 3, 5, 7, 11, 13, 17, 31, 61, 127, 251):
+        for k in range(1, 10):
+            if O.dqt_bounds_ok(p, k, 1, max(1, (k * (p - 1) ** 2).bit_length()), 53):
+                out.append((p, k))
+    return out
+
+
+@pytest.mark.parametrize("p,k", _supported_pairs())
+def test_polymul_fields_and_degrees(dqt, p, k):
+    q = dqt.qadic_choose(p, k, 1)
+    assert O.dqt_bounds_ok(p, k, 1, q.log2q, 53) and not O.dqt_bounds_ok(p, k, 1, q.log2q - 1, 53)
+    for count in (1, 3, 4, 5, 1023, 4097):
+        a, b = inputs.polymul_pairs(count, k, p, seed=count * 31 + p)
+        ref = O.polymul(a, b, p)
+        assert (to_host(dqt.polymul_u8(to_dev(a), to_dev(b), p)) == ref).all(), (p, k, count)
+        assert (to_host(dqt.polymul_plain_u8(to_dev(a), to_dev(b), p)) == ref).all(), (p, k, count)
+    w = inputs.worst_case((257, k), p)
+    assert (to_host(dqt.polymul_u8(to_dev(w), to_dev(w), p)) == O.polymul(w, w, p)).all()
+
+
+def test_polymul_unsupported_degree(dqt):
+    # degree 9 over F_251 cannot fit one 53-bit word
+    a = torch.zeros((4, 10), dtype=torch.uint8, device=device())
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.polymul_u8(a, a, 251)
+    assert e.value.status == dqt.DQT_E_UNSUPPORTED
+
+
+def test_polymul_empty_and_unaligned(dqt):
+    z = torch.zeros((0, 4), dtype=torch.uint8, device=device())
+    assert dqt.polymul_u8(z, z, 3).shape == (0, 7)
+    a, b = inputs.polymul_pairs(1001, 4, 3, seed=5)
+    ref = O.polymul(a, b, 3)
+    out = unaligned_empty((1001, 7), 3)
+    dqt.polymul_u8(unaligned_like(a, 1), unaligned_like(b, 2), 3, out=out)
+    assert (to_host(out) == ref).all()
+
+
+def test_unfused_composition_matches(dqt):
+    """pack -> packed product -> REDQ gives the same bytes as the fused kernel."""
+    for p, k in [(3, 4), (2, 5), (5, 3), (7, 3), (11, 2), (3, 5)]:
+        a, b = inputs.polymul_pairs(3000, k, p, seed=k + 100 * p)
+        q = dqt.qadic_choose(p, k, 1)
+        wa, wb = dqt.pack(to_dev(a), q), dqt.pack(to_dev(b), q)
+        assert (to_host(wa).view(np.uint64) == O.dqt_eval(a, q.log2q)).all()
+        assert (to_host(dqt.pack(to_dev(a), q, reverse=True)).view(np.uint64) == O.dqt_eval(a, q.log2q, True)).all()
+        r = dqt.polymul_words(wa, wb, q)
+        got = to_host(dqt.redq_unpack(r, q))
+        assert (got == O.polymul(a, b, p)).all()
+        assert (got == to_host(dqt.polymul_u8(to_dev(a), to_dev(b), p))).all()
+
+
+@pytest.mark.parametrize("p,b,nres", [(3, 6, 7), (3, 13, 4), (2, 11, 4), (5, 7, 7), (7, 7, 7), (11, 9, 5),
+                                      (13, 10, 5), (31, 11, 4), (251, 17, 3), (3, 4, 13), (3, 13, 1),
+                                      (7, 3, 17), (5, 26, 2), (3, 5, 10), (3, 8, 6)])
+def test_redq_unpack_words(dqt, p, b, nres):
+    """REDQ of arbitrary words with digits < q (top digit free) vs radix conversion + mod p."""
+    g = np.random.default_rng(p * 1000 + b * 10 + nres)
+    n = 20000
+    top_bits = 53 - b * (nres - 1)
+    low = g.integers(0, 2 ** b, size=(n, nres - 1), dtype=np.uint64)
+    top = g.integers(0, 2 ** min(top_bits, 62), size=n, dtype=np.uint64)
+    r = top << np.uint64(b * (nres - 1))
+    for i in range(nres - 1):
+        r |= low[:, i] << np.uint64(b * i)
+    # words right at the top of the range exercise the one-sided AFDIV test
+    r[:8] = np.uint64(2 ** 53 - 1) - np.arange(8, dtype=np.uint64)
+    for i in range(8):
+        digits = [(int(r[i]) >> (b * j)) & (2 ** b - 1) for j in range(nres - 1)]
+        assert all(d < 2 ** b for d in digits)
+    rt = torch.from_numpy(r.view(np.int64)).to(device())
+    got = to_host(dqt.redq_unpack(rt, dqt.Qadic(p, b, 1, nres, 1)))
+    assert (got == O.radix_mod(r, p, b, nres)).all()
+
+
+@pytest.mark.parametrize("p,k", [(3, 5), (7, 3)])
+def test_gf_full_tables(dqt, p, k):
+    """Every product of GF(3^5) (59,049) and GF(7^3) (117,649) with the seeded irreducible modulus."""
+    P = inputs.irreducible(p, k)
+    elems = np.array(list(O.all_elements(p, k)), dtype=np.uint8)
+    a = np.repeat(elems, len(elems), axis=0)
+    b = np.tile(elems, (len(elems), 1))
+    ref = O.gf_mul(a, b, p, P)
+    assert (to_host(dqt.gf_mul_u8(to_dev(a), to_dev(b), p, P)) == ref).all()
+    assert (to_host(dqt.gf_mul_plain_u8(to_dev(a), to_dev(b), p, P)) == ref).all()
+    q = dqt.qadic_choose(p, k, 1)
+    r = dqt.polymul_words(dqt.pack(to_dev(a), q), dqt.pack(to_dev(b), q), q)
+    assert (to_host(dqt.redq_unpack(r, q, modulus=P)) == ref).all()
+
+
+@pytest.mark.parametrize("p,k", [(3, 5), (7, 3)])
+def test_gf_workload_and_inverse(dqt, p, k):
+    """2^24 products per field as in the GF(p^k) workload; a.b.b^-1 = a on 4,096 elements."""
+    P = inputs.irreducible(p, k)
+    n = 1 << 24
+    a, b = inputs.gf_pairs(n, k, p)
+    ref = O.gf_mul(a, b, p, P)
+    da, db = to_dev(a), to_dev(b)
+    got = dqt.gf_mul_u8(da, db, p, P)
+    assert (to_host(got) == ref).all()
+    # inverse check: b^-1 from the oracle's full table
+    elems = np.array(list(O.all_elements(p, k)), dtype=np.uint8)
+    m = len(elems)
+    tab = O.gf_mul(np.repeat(elems, m, axis=0), np.tile(elems, (m, 1)), p, P).reshape(m, m, k)
+    one = np.zeros(k, np.uint8)
+    one[0] = 1
+    inv = {}
+    for i in range(1, m):
+        j = int(np.nonzero((tab[i] == one).all(axis=1))[0][0])
+        inv[i] = elems[j]
+    weights = p ** np.arange(k)
+    idx = (b[:4096].astype(np.int64) * weights).sum(axis=1)
+    sel = np.nonzero(idx)[0]
+    binv = np.stack([inv[int(i)] for i in idx[sel]])
+    back = dqt.gf_mul_u8(got[:4096][sel].contiguous(), to_dev(binv), p, P)
+    assert (to_host(back) == a[:4096][sel]).all()
+
+
+def test_gf_ragged_and_unaligned(dqt):
+    for p, k in [(3, 5), (7, 3), (2, 6), (5, 4), (3, 2), (13, 3), (2, 2)]:
+        P = inputs.irreducible(p, k)
+        for count in (1, 2, 3, 5, 4099):
+            a, b = inputs.gf_pairs(count, k, p, seed=count)
+            ref = O.gf_mul(a, b, p, P)
+            assert (to_host(dqt.gf_mul_u8(to_dev(a), to_dev(b), p, P)) == ref).all(), (p, k, count)
+            assert (to_host(dqt.gf_mul_plain_u8(to_dev(a), to_dev(b), p, P)) == ref).all(), (p, k, count)
+            out = unaligned_empty((count, k), 1)
+            dqt.gf_mul_u8(unaligned_like(a, 3), unaligned_like(b, 2), p, P, out=out)
+            assert (to_host(out) == ref).all(), (p, k, count)
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 11])
+def test_fqt_long_products(dqt, p):
+    """Block (FQT) products for degrees 2..15 and unequal lengths, every admissible block size."""
+    for na, nb in [(3, 3), (5, 5), (8, 8), (11, 11), (16, 16), (5, 13), (16, 2), (1, 9), (32, 32), (20, 7)]:
+        for count in (1, 7, 1000):
+            a, b = inputs.polymul_pairs(count, na, p, seed=na * 100 + nb + count, kb=nb)
+            ref = O.polymul(a, b, p)
+            got = to_host(dqt.polymul_fqt_u8(to_dev(a), to_dev(b), p))
+            assert (got == ref).all(), (p, na, nb, count)
+        a, b = inputs.polymul_pairs(300, na, p, seed=na + nb, kb=nb)
+        ref = O.polymul(a, b, p)
+        for block in range(2, 7):
+            try:
+                got = to_host(dqt.polymul_fqt_u8(to_dev(a), to_dev(b), p, block=block))
+            except dqt.DQTError as e:
+                assert e.status in (dqt.DQT_E_BOUND, dqt.DQT_E_UNSUPPORTED)
+                continue
+            assert (got == ref).all(), (p, na, nb, block)
+        w = inputs.worst_case((64, na), p)
+        wb = inputs.worst_case((64, nb), p)
+        assert (to_host(dqt.polymul_fqt_u8(to_dev(w), to_dev(wb), p)) == O.polymul(w, wb, p)).all()

@@ -236,6 +236,16 @@ dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, 
                              const dqt_gemm_plan *plan, const void *d_work, size_t work_bytes, void *stream);
 
 /*
+ * dqt_fgemm_compute, with the multiply kernel's own start and end recorded
+ * into two caller-created hipEvent_t (either may be NULL): the elapsed time
+ * between them is that kernel's execution, without the launch gaps around
+ * it (measurement).  Not for DQT_GEMM_MFMA (DQT_E_UNSUPPORTED).
+ */
+dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t *d_C, uint64_t ldc,
+                                   const dqt_gemm_plan *plan, const void *d_work, size_t work_bytes,
+                                   void *start_event, void *stop_event, void *stream);
+
+/*
  * Batched F_p matrix products in one persistent launch.
  *
  * Each descriptor names its own device operands (row-major uint8, as for

@@ -130,6 +130,8 @@ dqt_status make_redq_args(uint32_t p, uint32_t b, uint32_t nres, uint32_t word_b
     a.w = residue_bits(p);
     if (a.w == 0) a.w = 1;
     a.invp = inverse_rounded_up(p);
+    a.invp52 = ldexp(a.invp, 52);
+    a.small = (word_bits <= 51) ? 1u : 0u;
     a.c = (uint32_t)(((b >= 32) ? 0 : ((1ull << b) % p)) % p);
     if (b >= 32) a.c = (uint32_t)((1ull << 32) % p);
     // Words are < 2^word_bits.  AFDIV's single test is needed only if they can
@@ -315,18 +317,19 @@ __device__ __forceinline__ uint64_t gf_add_bytes(uint64_t h, uint64_t l, uint32_
     return s - (uint64_t)p * ge;
 }
 
-template <int K>
+template <int K, int B = 0, int W = 0, bool SMALL = false>
 __device__ __forceinline__ uint64_t gf_reduce_word(uint64_t r, const RedqArgs& ra, const uint64_t* tl, const uint64_t* th,
                                                    uint64_t ones) {
-    const uint64_t U = redq_compress(r, ra);
-    const uint32_t wm = (1u << ra.w) - 1u;
+    const uint64_t U = redq_compress_t<(B ? 2 * K - 1 : 0), B, W, SMALL>(r, ra);
+    const uint32_t b = B ? B : ra.b, w = W ? W : ra.w;
+    const uint32_t wm = (1u << w) - 1u;
     const uint32_t xl = (uint32_t)U;
-    const uint32_t xh = (uint32_t)(U >> (ra.b * (K - 1)));
+    const uint32_t xh = (uint32_t)(U >> (b * (K - 1)));
     uint32_t il = 0, ih = 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        il |= ((xl >> (ra.b * j)) & wm) << (ra.w * j);
-        ih |= ((xh >> (ra.b * j)) & wm) << (ra.w * j);
+        il |= ((xl >> (b * j)) & wm) << (w * j);
+        ih |= ((xh >> (b * j)) & wm) << (w * j);
     }
     return gf_add_bytes(th[ih], tl[il], ra.p, ones);
 }
@@ -364,8 +367,11 @@ __device__ __forceinline__ uint64_t packed_mul(uint64_t x, uint64_t y) {
 }
 
 // DQT of K coefficient bytes starting at compile-time byte position BASE.
-template <int K, int BASE, int MODE>
-__device__ __forceinline__ uint64_t pack_bytes(const uint32_t* w, uint32_t b) {
+template <int K, int BASE, int MODE, int B = 0, int W = 0>
+__device__ __forceinline__ uint64_t pack_bytes(const uint32_t* w, uint32_t b_rt) {
+    const uint32_t b = B ? B : b_rt;
+    if (K == 4 && (BASE & 3) == 0 && B && W && pack4_by_multiply<(B ? B : 1), (W ? W : 1)>())
+        return pack4_multiply<(B ? B : 1), (W ? W : 1)>(w[BASE >> 2]);
     if (MODE == MUL64) {
         uint64_t v = 0;
 #pragma unroll
@@ -378,15 +384,15 @@ __device__ __forceinline__ uint64_t pack_bytes(const uint32_t* w, uint32_t b) {
     return v;
 }
 
-template <int K, int MODE, int T>
+template <int K, int MODE, int T, int B = 0, int W = 0, bool SMALL = false>
 __device__ __forceinline__ void polymul_one(const uint32_t* a, const uint32_t* bw, uint32_t* o, const RedqArgs& ra,
                                             const uint16_t* tab) {
     constexpr int NR = 2 * K - 1;
-    const uint64_t x = pack_bytes<K, T * K, MODE>(a, ra.b);
-    const uint64_t y = pack_bytes<K, T * K, MODE>(bw, ra.b);
+    const uint64_t x = pack_bytes<K, T * K, MODE, B, W>(a, ra.b);
+    const uint64_t y = pack_bytes<K, T * K, MODE, B, W>(bw, ra.b);
     const uint64_t r = packed_mul<MODE>(x, y);
-    const uint64_t U = redq_compress(r, ra);
-    redq_correct<NR>(U, ra, tab, [&](int i, uint32_t v) { put_byte(o, T * NR + i, v); });
+    const uint64_t U = redq_compress_t<(B ? NR : 0), B, W, SMALL>(r, ra);
+    redq_correct<NR, B, W>(U, ra, tab, [&](int i, uint32_t v) { put_byte(o, T * NR + i, v); });
 }
 
 // Scalar path for the last count % 4 products (byte loads and stores).
@@ -405,7 +411,7 @@ __device__ void polymul_tail(const uint8_t* A, const uint8_t* B, uint8_t* OUT, u
     for (int i = 0; i < NR; ++i) OUT[t * NR + i] = (uint8_t)((o[i >> 2] >> (8 * (i & 3))) & 0xFF);
 }
 
-template <int K, int MODE>
+template <int K, int MODE, int QB = 0, int QW = 0, bool SMALL = false>
 __global__ __launch_bounds__(256) void k_polymul_fused(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                        uint8_t* __restrict__ OUT, uint64_t count, RedqArgs ra) {
     constexpr int NR = 2 * K - 1;
@@ -425,10 +431,10 @@ __global__ __launch_bounds__(256) void k_polymul_fused(const uint8_t* __restrict
         }
 #pragma unroll
         for (int i = 0; i < NR; ++i) o[i] = 0;
-        polymul_one<K, MODE, 0>(a, b, o, ra, tab);
-        polymul_one<K, MODE, 1>(a, b, o, ra, tab);
-        polymul_one<K, MODE, 2>(a, b, o, ra, tab);
-        polymul_one<K, MODE, 3>(a, b, o, ra, tab);
+        polymul_one<K, MODE, 0, QB, QW, SMALL>(a, b, o, ra, tab);
+        polymul_one<K, MODE, 1, QB, QW, SMALL>(a, b, o, ra, tab);
+        polymul_one<K, MODE, 2, QB, QW, SMALL>(a, b, o, ra, tab);
+        polymul_one<K, MODE, 3, QB, QW, SMALL>(a, b, o, ra, tab);
 #pragma unroll
         for (int i = 0; i < NR; ++i) __builtin_nontemporal_store(o[i], O32 + g * NR + i);
     }
@@ -446,17 +452,17 @@ __global__ __launch_bounds__(256) void k_polymul_fused_bytes(const uint8_t* __re
         polymul_tail<K, MODE>(A, B, OUT, t, ra, tab);
 }
 
-template <int K, int MODE, int T>
+template <int K, int MODE, int T, int B = 0, int W = 0, bool SMALL = false>
 __device__ __forceinline__ void gf_one(const uint32_t* a, const uint32_t* bw, uint32_t* o, const RedqArgs& ra,
                                        const uint64_t* tl, const uint64_t* th, uint64_t ones) {
-    const uint64_t x = pack_bytes<K, T * K, MODE>(a, ra.b);
-    const uint64_t y = pack_bytes<K, T * K, MODE>(bw, ra.b);
-    const uint64_t v = gf_reduce_word<K>(packed_mul<MODE>(x, y), ra, tl, th, ones);
+    const uint64_t x = pack_bytes<K, T * K, MODE, B, W>(a, ra.b);
+    const uint64_t y = pack_bytes<K, T * K, MODE, B, W>(bw, ra.b);
+    const uint64_t v = gf_reduce_word<K, B, W, SMALL>(packed_mul<MODE>(x, y), ra, tl, th, ones);
 #pragma unroll
     for (int i = 0; i < K; ++i) put_byte(o, T * K + i, (uint32_t)(v >> (8 * i)) & 0xFFu);
 }
 
-template <int K, int MODE>
+template <int K, int MODE, int QB = 0, int QW = 0, bool SMALL = false>
 __global__ __launch_bounds__(256) void k_gf_mul_fused(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                       uint8_t* __restrict__ OUT, uint64_t count, RedqArgs ra, GfArgs ga) {
     extern __shared__ uint64_t gf_smem[];
@@ -478,10 +484,10 @@ __global__ __launch_bounds__(256) void k_gf_mul_fused(const uint8_t* __restrict_
             b[i] = __builtin_nontemporal_load(B32 + g * K + i);
             o[i] = 0;
         }
-        gf_one<K, MODE, 0>(a, b, o, ra, tl, th, ones);
-        gf_one<K, MODE, 1>(a, b, o, ra, tl, th, ones);
-        gf_one<K, MODE, 2>(a, b, o, ra, tl, th, ones);
-        gf_one<K, MODE, 3>(a, b, o, ra, tl, th, ones);
+        gf_one<K, MODE, 0, QB, QW, SMALL>(a, b, o, ra, tl, th, ones);
+        gf_one<K, MODE, 1, QB, QW, SMALL>(a, b, o, ra, tl, th, ones);
+        gf_one<K, MODE, 2, QB, QW, SMALL>(a, b, o, ra, tl, th, ones);
+        gf_one<K, MODE, 3, QB, QW, SMALL>(a, b, o, ra, tl, th, ones);
 #pragma unroll
         for (int i = 0; i < K; ++i) __builtin_nontemporal_store(o[i], O32 + g * K + i);
     }
@@ -772,6 +778,15 @@ static dqt_status launch_polymul_fused(const uint8_t* A, const uint8_t* B, uint6
         return DQT_OK;
     }
     const unsigned grid = stream_grid((count + 3) / 4, 256);
+    // compile-time q and residue width for the degree-3 products over F_3 at q = 2^6
+    if constexpr (K == 4) {
+        if (ra.b == 6 && ra.w == 2 && ra.small && mul_mode(K, ra.b, ra.w) == MUL24) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fused<K, MUL24, 6, 2, true>), dim3(grid), dim3(256), 0, s, A, B,
+                               out, count, ra);
+            DQT_LAUNCH_CHECK("dqt_polymul_u8");
+            return DQT_OK;
+        }
+    }
     switch (mul_mode(K, ra.b, ra.w)) {
         case MUL24:
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fused<K, MUL24>), dim3(grid), dim3(256), 0, s, A, B, out, count, ra);
@@ -835,6 +850,23 @@ static dqt_status launch_gf_fused(const uint8_t* A, const uint8_t* B, uint64_t c
         return DQT_OK;
     }
     const unsigned grid = stream_grid((count + 3) / 4, 256, 4);
+    // compile-time q and residue width for GF(3^5) at q = 2^5 and GF(7^3) at q = 2^7
+    if constexpr (K == 5) {
+        if (ra.b == 5 && ra.w == 2 && ra.small && mul_mode(K, ra.b, ra.w) == MUL24) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_fused<K, MUL24, 5, 2, true>), dim3(grid), dim3(256), smem, s, A, B,
+                               out, count, ra, ga);
+            DQT_LAUNCH_CHECK("dqt_gf_mul_u8");
+            return DQT_OK;
+        }
+    }
+    if constexpr (K == 3) {
+        if (ra.b == 7 && ra.w == 3 && ra.small && mul_mode(K, ra.b, ra.w) == MUL24) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_fused<K, MUL24, 7, 3, true>), dim3(grid), dim3(256), smem, s, A, B,
+                               out, count, ra, ga);
+            DQT_LAUNCH_CHECK("dqt_gf_mul_u8");
+            return DQT_OK;
+        }
+    }
     if (mul_mode(K, ra.b, ra.w) == MUL24)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_fused<K, MUL24>), dim3(grid), dim3(256), smem, s, A, B, out, count, ra, ga);
     else

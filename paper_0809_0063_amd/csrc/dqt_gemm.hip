@@ -29,47 +29,12 @@
 
 #include <string.h>
 
+#include <hip/hip_ext.h>
+
+#include "dqt_gemm_tile.h"
 #include "dqt_internal.h"
 
 namespace dqt {
-
-enum GemmOp { OP_DOT2 = 0, OP_DOT4 = 1, OP_MAD = 2 };
-
-struct GemmArgs {
-    const uint32_t* CA;
-    const uint32_t* CB;
-    uint8_t* C;
-    uint32_t m, n, ldc;
-    uint32_t m_pad, n_pad;
-    uint32_t KW;          // k-groups (words) along k
-    uint32_t kw_split;    // k-groups per wave
-    uint32_t lw;          // delayed-reduction interval in k-groups (0 = whole range)
-    uint32_t nrb, ncb;    // row blocks, column blocks
-    uint32_t b;           // log2 Q (packed path)
-    uint32_t p, pmagic;
-    uint32_t epi;         // 0 REDC, 1 REDQ
-    uint32_t epi_e;       // outputs per REDQ word
-    RedqArgs ra;          // REDQ_{epi_e} parameters (q = Q)
-};
-
-// x mod p for any 32-bit x: quotient from the rounded-up reciprocal, one fix.
-__device__ __forceinline__ uint32_t mod_u32(uint32_t x, uint32_t p, uint32_t pmagic) {
-    const uint32_t qt = __umulhi(x, pmagic);
-    const int32_t r = (int32_t)(x - qt * p);
-    return (uint32_t)(r < 0 ? r + (int32_t)p : r);
-}
-
-template <int OP>
-__device__ __forceinline__ uint32_t mac(uint32_t a, uint32_t b, uint32_t acc) {
-    if (OP == OP_DOT2) {
-        typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-        return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b), acc, false);
-    } else if (OP == OP_DOT4) {
-        return __builtin_amdgcn_udot4(a, b, acc, false);
-    } else {
-        return __umul24(a, b) + acc;
-    }
-}
 
 // Logical tile of a workgroup: on a launch whose size is a multiple of 8,
 // workgroup i runs on XCD i mod 8; consecutive logical tiles on one XCD share
@@ -81,180 +46,96 @@ __device__ __forceinline__ void tile_of(uint32_t bid, uint32_t nblk, uint32_t nr
     *cb = logical / nrb;
 }
 
-template <int OP, int TM, int TN, int S>
+template <int OP, int TM, int TN, int S, bool FLUSH, int EPI>
 __global__ __launch_bounds__(64 * S) void k_gemm_words(GemmArgs g) {
+    __shared__ uint32_t red[TileSmem<TM, TN, S>::words];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t rb, cb;
     tile_of(blockIdx.x, gridDim.x, g.nrb, &rb, &cb);
-    const uint32_t row0 = rb * TM;
-    const uint32_t col0 = cb * 64u * TN;
-
-    uint32_t acc[TM][TN], wide[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = wide[i][j] = 0;
-
-    const uint32_t kw0 = wave * g.kw_split;
-    const uint32_t kw1 = min(g.KW, kw0 + g.kw_split);
-    const uint32_t* __restrict__ pa = g.CA + row0;
-    const uint32_t* __restrict__ pb = g.CB + col0 + lane;
-    // delayed-reduction interval in k-groups (the whole range when none is needed)
-    const uint32_t step = (OP == OP_DOT2 && g.lw) ? g.lw : (kw1 > kw0 ? kw1 - kw0 : 1u);
-    const uint32_t mask = (1u << g.b) - 1u;
-
-    for (uint32_t kc = kw0; kc < kw1; kc += step) {
-        const uint32_t ke = min(kw1, kc + step);
-#pragma unroll 4
-        for (uint32_t kw = kc; kw < ke; ++kw) {
-            uint32_t av[TM], bv[TN];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) av[i] = pa[(size_t)kw * g.m_pad + i];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) bv[j] = pb[(size_t)kw * g.n_pad + 64 * j];
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = mac<OP>(av[i], bv[j], acc[i][j]);
-        }
-        if (OP == OP_DOT2 && ke < kw1) {
-            // end of a delayed-reduction interval: move the middle digit out
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    wide[i][j] += (acc[i][j] >> g.b) & mask;
-                    acc[i][j] = 0;
-                }
-        }
-    }
-    // value of each output for this wave's k range
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = (OP == OP_DOT2) ? wide[i][j] + ((acc[i][j] >> g.b) & mask) : acc[i][j];
-
-    // split-k: add the S partial sums through LDS; wave w finishes rows i = w, w+S, ...
-    if (S > 1) {
-        __shared__ uint32_t red[S][TM][TN][64];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) red[wave][i][j][lane] = acc[i][j];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            if ((uint32_t)i % S != wave) continue;
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                uint32_t s = 0;
-#pragma unroll
-                for (int w = 0; w < S; ++w) s += red[w][i][j][lane];
-                acc[i][j] = s;
-            }
-        }
-    }
-
-    // epilogue: reduce mod p and store bytes
-    if (g.epi == 0) {
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            if (S > 1 && (uint32_t)i % S != wave) continue;
-            const uint32_t row = row0 + i;
-            if (row >= g.m) continue;
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const uint32_t col = col0 + lane + 64 * j;
-                if (col < g.n) g.C[(size_t)row * g.ldc + col] = (uint8_t)mod_u32(acc[i][j], g.p, g.pmagic);
-            }
-        }
-    } else {
-        // REDQ_e: middle digits (each < Q) of up to e outputs of this lane
-        // packed into one word at q = Q, one REDQ for all of them.
-        const RedqArgs& ra = g.ra;
-        uint64_t word = 0;
-        uint32_t nin = 0;
-        uint32_t rows[8], cols[8];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            if (S > 1 && (uint32_t)i % S != wave) continue;
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                word |= (uint64_t)acc[i][j] << (ra.b * nin);
-                rows[nin] = row0 + i;
-                cols[nin] = col0 + lane + 64 * j;
-                ++nin;
-                const bool last = (i == TM - 1 || (S > 1 && i + S > TM - 1)) && j == TN - 1;
-                if (nin == g.epi_e || last) {
-                    const uint64_t U = redq_compress(word, ra);
-                    for (uint32_t t = 0; t < nin; ++t) {
-                        const uint32_t ut = field(U, t, ra);
-                        uint32_t mu = ut;
-                        if (ra.c && t + 1 < nin) mu = correct_arith(ut, field(U, t + 1, ra), ra);
-                        if (rows[t] < g.m && cols[t] < g.n) g.C[(size_t)rows[t] * g.ldc + cols[t]] = (uint8_t)mu;
-                    }
-                    word = 0;
-                    nin = 0;
-                }
-            }
-        }
-    }
+    gemm_tile<OP, TM, TN, S, FLUSH, EPI>(g, rb, cb, wave, lane, red);
 }
 
 // Pack A (rows, reversed pairs) and B (columns) into the word layouts.
 // Grid: blocks [0, nba) pack A, blocks [nba, ...) pack B; 256 threads, one word each.
-struct PackArgs {
-    const uint8_t* A;
-    const uint8_t* B;
-    uint32_t* CA;
-    uint32_t* CB;
-    uint32_t m, n, kdim, lda, ldb;
-    uint32_t m_pad, n_pad, KW;
-    uint32_t b;       // log2 Q
-    uint32_t op;      // GemmOp
-    uint32_t nba;     // blocks for A
+__global__ __launch_bounds__(256) void k_gemm_pack(PackArgs a) { gemm_pack_block(a, blockIdx.x, threadIdx.x); }
+
+// Coalesced packing of the four-entry layouts when rows start on 4-byte
+// boundaries.  A: a workgroup packs a 64-row x 16-word tile of A through LDS
+// and writes it k-major.  B: a thread takes four
+// consecutive columns of one k-group (one dword from each of four rows) and
+// writes their four words.  Blocks [0, nta) pack A tiles, the rest pack B.
+struct Pack4Args {
+    PackArgs a;
+    uint32_t nta;           // A tiles
+    uint32_t tiles_m;       // A tiles along rows
 };
 
-__global__ __launch_bounds__(256) void k_gemm_pack(PackArgs a) {
-    const uint32_t epw = a.op == OP_MAD ? 1u : 4u;  // entries per word
-    if (blockIdx.x < a.nba) {
-        // CA[kw][row]: thread index = kw * m_pad + row (rows fastest: coalesced stores)
-        const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-        if (t >= (uint64_t)a.KW * a.m_pad) return;
-        const uint32_t kw = (uint32_t)(t / a.m_pad), row = (uint32_t)(t % a.m_pad);
-        uint32_t e[4] = {0, 0, 0, 0};
-        if (row < a.m)
-            for (uint32_t i = 0; i < epw; ++i) {
-                const uint32_t k = kw * epw + i;
-                if (k < a.kdim) e[i] = a.A[(size_t)row * a.lda + k];
+__global__ __launch_bounds__(256) void k_gemm_pack4(Pack4Args pa) {
+    const PackArgs& a = pa.a;
+    if (blockIdx.x < pa.nta) {
+        // tile of 64 rows x 16 k-groups: each wave loads 16 rows as four
+        // 4-row x 64-byte segments, each thread packs one word, and the tile
+        // leaves k-major (each wave writes 4 k-groups of 64 consecutive rows)
+        __shared__ uint32_t tile[16][65];
+        const uint32_t tr = blockIdx.x % pa.tiles_m, tw = blockIdx.x / pa.tiles_m;
+        const uint32_t r0 = tr * 64, w0 = tw * 16;
+        const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+#pragma unroll
+        for (uint32_t it = 0; it < 4; ++it) {
+            const uint32_t rr = wave * 16 + it * 4 + (lane >> 4);
+            const uint32_t ww = lane & 15u;
+            const uint32_t row = r0 + rr, kw = w0 + ww;
+            uint32_t w = 0;
+            if (row < a.m && kw < a.KW) {
+                uint32_t e[4] = {0, 0, 0, 0};
+                if (4 * kw + 3 < a.kdim) {
+                    const uint32_t d = *reinterpret_cast<const uint32_t*>(a.A + (size_t)row * a.lda + 4 * kw);
+                    e[0] = d & 0xFF;
+                    e[1] = (d >> 8) & 0xFF;
+                    e[2] = (d >> 16) & 0xFF;
+                    e[3] = d >> 24;
+                } else {
+                    for (uint32_t i = 0; i < 4; ++i)
+                        if (4 * kw + i < a.kdim) e[i] = a.A[(size_t)row * a.lda + 4 * kw + i];
+                }
+                w = a.op == OP_DOT2 ? (((e[0] << a.b) | e[1]) | (((e[2] << a.b) | e[3]) << 16))
+                                    : (e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24));
             }
-        uint32_t w;
-        if (a.op == OP_DOT2)
-            w = ((e[0] << a.b) | e[1]) | (((e[2] << a.b) | e[3]) << 16);
-        else if (a.op == OP_DOT4)
-            w = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
-        else
-            w = e[0];
-        a.CA[t] = w;
+            tile[ww][rr] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t it = 0; it < 4; ++it) {
+            const uint32_t ww = wave * 4 + it;
+            const uint32_t kw = w0 + ww, row = r0 + lane;
+            if (kw < a.KW && row < a.m_pad) a.CA[(size_t)kw * a.m_pad + row] = tile[ww][lane];
+        }
     } else {
-        const uint64_t t = (uint64_t)(blockIdx.x - a.nba) * 256 + threadIdx.x;
-        if (t >= (uint64_t)a.KW * a.n_pad) return;
-        const uint32_t kw = (uint32_t)(t / a.n_pad), col = (uint32_t)(t % a.n_pad);
-        uint32_t e[4] = {0, 0, 0, 0};
-        if (col < a.n)
-            for (uint32_t i = 0; i < epw; ++i) {
-                const uint32_t k = kw * epw + i;
-                if (k < a.kdim) e[i] = a.B[(size_t)k * a.ldb + col];
+        const uint64_t t = (uint64_t)(blockIdx.x - pa.nta) * 256 + threadIdx.x;
+        const uint32_t q4 = a.n_pad / 4;
+        if (t >= (uint64_t)a.KW * q4) return;
+        const uint32_t kw = (uint32_t)(t / q4), c4 = (uint32_t)(t % q4) * 4;
+        uint32_t d[4] = {0, 0, 0, 0};
+        for (uint32_t i = 0; i < 4; ++i) {
+            const uint32_t k = 4 * kw + i;
+            if (k >= a.kdim) continue;
+            if (c4 + 3 < a.n) {
+                d[i] = *reinterpret_cast<const uint32_t*>(a.B + (size_t)k * a.ldb + c4);
+            } else {
+                for (uint32_t j = 0; j < 4; ++j)
+                    if (c4 + j < a.n) d[i] |= (uint32_t)a.B[(size_t)k * a.ldb + c4 + j] << (8 * j);
             }
-        uint32_t w;
-        if (a.op == OP_DOT2)
-            w = (e[0] | (e[1] << a.b)) | ((e[2] | (e[3] << a.b)) << 16);
-        else if (a.op == OP_DOT4)
-            w = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
-        else
-            w = e[0];
-        a.CB[t] = w;
+        }
+        uint4 out;
+        uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t e0 = (d[0] >> (8 * j)) & 0xFF, e1 = (d[1] >> (8 * j)) & 0xFF;
+            const uint32_t e2 = (d[2] >> (8 * j)) & 0xFF, e3 = (d[3] >> (8 * j)) & 0xFF;
+            o[j] = a.op == OP_DOT2 ? ((e0 | (e1 << a.b)) | ((e2 | (e3 << a.b)) << 16))
+                                   : (e0 | (e1 << 8) | (e2 << 16) | (e3 << 24));
+        }
+        *reinterpret_cast<uint4*>(a.CB + (size_t)kw * a.n_pad + c4) = out;
     }
 }
 
@@ -346,16 +227,6 @@ __global__ __launch_bounds__(256) void k_mfma_pack(MfmaPackArgs a) {
 // Host planning
 // ---------------------------------------------------------------------------
 
-struct GemmPlanResolved {
-    uint32_t algo;
-    uint32_t op;
-    uint32_t b;         // log2 Q (packed)
-    uint32_t lw;        // interval in k-groups (0 = none)
-    uint32_t tm, tn, s;
-    uint32_t epi;
-    uint32_t KW, m_pad, n_pad, k_pad;
-    size_t ws_bytes;
-};
 
 static uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
@@ -448,7 +319,7 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
         // enough waves to fill the chip: aim at >= 8 waves per CU
         const uint64_t tiles = ((m + r->tm - 1) / r->tm) * ((n + 64 * r->tn - 1) / (64 * r->tn));
         r->s = 1;
-        while (r->s < 8 && tiles * r->s < 2048 && (uint64_t)r->KW / (r->s * 2) >= 16) r->s *= 2;
+        while (r->s < 8 && tiles * r->s < 4096 && (uint64_t)r->KW / (r->s * 2) >= 16) r->s *= 2;
     }
     if (r->s != 1 && r->s != 2 && r->s != 4 && r->s != 8) return DQT_E_INVALID;
     // split-k boundaries must fall on interval boundaries of the packed path
@@ -459,9 +330,32 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
     return DQT_OK;
 }
 
+// Events that the next multiply-kernel launch of this thread records at its
+// own start and end (dqt_fgemm_compute_timed); null for ordinary launches.
+static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+template <int OP, int TM, int S, bool FLUSH, int EPI>
+static void launch_words_k(const GemmArgs& g, unsigned grid, hipStream_t s) {
+    if (g_ev_start || g_ev_stop)
+        hipExtLaunchKernelGGL(k_gemm_words<OP, TM, 2, S, FLUSH, EPI>, dim3(grid), dim3(64 * S), 0, s, g_ev_start,
+                              g_ev_stop, 0, g);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_words<OP, TM, 2, S, FLUSH, EPI>), dim3(grid), dim3(64 * S), 0, s, g);
+}
+
 template <int OP, int TM, int S>
 static void launch_words(const GemmArgs& g, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_words<OP, TM, 2, S>), dim3(grid), dim3(64 * S), 0, s, g);
+    if (OP == OP_DOT2) {
+        if (g.lw) {
+            if (g.epi) launch_words_k<OP, TM, S, true, 1>(g, grid, s);
+            else launch_words_k<OP, TM, S, true, 0>(g, grid, s);
+        } else {
+            if (g.epi) launch_words_k<OP, TM, S, false, 1>(g, grid, s);
+            else launch_words_k<OP, TM, S, false, 0>(g, grid, s);
+        }
+    } else {
+        launch_words_k<OP, TM, S, false, 0>(g, grid, s);
+    }
 }
 
 template <int OP, int TM>
@@ -481,6 +375,25 @@ static void launch_words_tm(const GemmArgs& g, unsigned grid, uint32_t tm, uint3
         case 16: launch_words_s<OP, 16>(g, grid, S_, s); break;
         default: launch_words_s<OP, 32>(g, grid, S_, s); break;
     }
+}
+
+dqt_status fgemm_epilogue_args(uint32_t p, uint64_t kdim, const GemmPlanResolved& r, GemmArgs* g) {
+    g->epi = r.epi;
+    if (r.epi == 1) {
+        // The gathered values are whole dot products (all intervals and all
+        // k-splits added), at most kdim (p-1)^2: they are the digits of the
+        // REDQ word, so its q is the smallest power of two above that bound,
+        // and e = floor(53 / log2 q) of them share one word (section 7.6.1).
+        const uint64_t maxdot = (uint64_t)kdim * (p - 1) * (p - 1);
+        uint32_t be = residue_bits(p);
+        while (be < 32 && (1ull << be) <= maxdot) ++be;
+        uint32_t e = 53 / be;
+        if (e > 8) e = 8;
+        if (e < 1) return DQT_E_UNSUPPORTED;
+        g->epi_e = e;
+        DQT_TRY(make_redq_args(p, be, e, e * be, &g->ra));
+    }
+    return DQT_OK;
 }
 
 // Packing step: operands to the word layout of the plan's kernel (either
@@ -526,6 +439,19 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
     pa.KW = r.KW;
     pa.b = r.b;
     pa.op = r.op;
+    const bool a_al = !A || (((uintptr_t)A & 3) == 0 && (lda & 3) == 0);
+    const bool b_al = !B || (((uintptr_t)B & 3) == 0 && (ldb & 3) == 0);
+    if (r.op != OP_MAD && a_al && b_al && (r.n_pad & 3) == 0 && ((uintptr_t)work & 15) == 0) {
+        Pack4Args p4;
+        p4.a = pa;
+        p4.tiles_m = (r.m_pad + 63) / 64;
+        p4.nta = A ? p4.tiles_m * ((r.KW + 15) / 16) : 0;
+        const uint32_t nbb = B ? (uint32_t)(((uint64_t)r.KW * (r.n_pad / 4) + 255) / 256) : 0;
+        if (p4.nta + nbb == 0) return DQT_OK;
+        hipLaunchKernelGGL(k_gemm_pack4, dim3(p4.nta + nbb), dim3(256), 0, s, p4);
+        DQT_LAUNCH_CHECK("fgemm(pack4)");
+        return DQT_OK;
+    }
     const uint32_t nba = A ? (uint32_t)(((uint64_t)r.KW * r.m_pad + 255) / 256) : 0;
     const uint32_t nbb = B ? (uint32_t)(((uint64_t)r.KW * r.n_pad + 255) / 256) : 0;
     pa.nba = nba;
@@ -579,21 +505,8 @@ dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kd
     g.b = r.b ? r.b : 1;
     g.p = p;
     g.pmagic = pmagic;
-    g.epi = r.epi;
-    if (r.epi == 1) {
-        // The gathered values are whole dot products (all intervals and all
-        // k-splits added), at most kdim (p-1)^2: they are the digits of the
-        // REDQ word, so its q is the smallest power of two above that bound,
-        // and e = floor(53 / log2 q) of them share one word (section 7.6.1).
-        const uint64_t maxdot = (uint64_t)kdim * (p - 1) * (p - 1);
-        uint32_t be = residue_bits(p);
-        while (be < 32 && (1ull << be) <= maxdot) ++be;
-        uint32_t e = 53 / be;
-        if (e > 8) e = 8;
-        if (e < 1) return DQT_E_UNSUPPORTED;
-        g.epi_e = e;
-        DQT_TRY(make_redq_args(p, be, e, e * be, &g.ra));
-    }
+    g.op = r.op;
+    DQT_TRY(fgemm_epilogue_args(p, kdim, r, &g));
     const unsigned grid = g.nrb * g.ncb;
     switch (r.op) {
         case OP_DOT2: launch_words_tm<OP_DOT2>(g, grid, r.tm, r.s, s); break;
@@ -657,6 +570,20 @@ extern "C" dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint
     DQT_TRY(fgemm_common_checks(p, m, n, kdim, plan, work_bytes, d_work, &r));
     DQT_TRY(ensure_device_ready());
     return fgemm_compute_enqueue(p, m, n, kdim, d_C, ldc, r, d_work, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* d_C,
+                                              uint64_t ldc, const dqt_gemm_plan* plan, const void* d_work,
+                                              size_t work_bytes, void* start_event, void* stop_event,
+                                              void* stream) {
+    GemmPlanResolved r;
+    DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
+    if (r.algo == DQT_GEMM_MFMA) return DQT_E_UNSUPPORTED;
+    g_ev_start = reinterpret_cast<hipEvent_t>(start_event);
+    g_ev_stop = reinterpret_cast<hipEvent_t>(stop_event);
+    const dqt_status st = dqt_fgemm_compute(p, m, n, kdim, d_C, ldc, plan, d_work, work_bytes, stream);
+    g_ev_start = g_ev_stop = nullptr;
+    return st;
 }
 
 extern "C" dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* d_A, uint64_t lda,

@@ -46,7 +46,12 @@ class _GemmDesc(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("m", ctypes.c_uint32), ("n", ctypes.c_uint32), ("kdim", ctypes.c_uint32),
                 ("lda", ctypes.c_uint32), ("ldb", ctypes.c_uint32), ("ldc", ctypes.c_uint32),
-                ("p", ctypes.c_uint32), ("algo", ctypes.c_uint32)]
+                ("p", ctypes.c_uint32), ("algo", ctypes.c_uint32), ("interval", ctypes.c_uint32),
+                ("log2Q", ctypes.c_uint32), ("epilogue", ctypes.c_uint32)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_uint32), ("ksplit", ctypes.c_uint32)]
 
 
 @dataclass(frozen=True)
@@ -100,9 +105,13 @@ def _load():
         "dqt_gf_mul_plain_u8": [V, V, U64, U32, U32, V, V, V],
         "dqt_polymul_fqt_u8": [V, U32, V, U32, U64, U32, U32, V, V],
         "dqt_fgemm": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
-        "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, V, SZ, V],
+        "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V],
+        "dqt_fgemm_batched_prepare": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V,
+                                      ctypes.POINTER(ctypes.c_void_p)],
+        "dqt_fgemm_batched_run": [V, V],
         "dqt_fgemm_pack": [U32, U64, U64, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_compute": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
+        "dqt_fgemm_compute_timed": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V, V, V],
     }
     for name, args in sigs.items():
         if not hasattr(lib, name):
@@ -114,8 +123,11 @@ def _load():
         lib.dqt_fgemm_workspace_size.argtypes = [U32, U64, U64, U64, ctypes.POINTER(_GemmPlan)]
         lib.dqt_fgemm_workspace_size.restype = SZ
     if hasattr(lib, "dqt_fgemm_batched_workspace_size"):
-        lib.dqt_fgemm_batched_workspace_size.argtypes = [ctypes.POINTER(_GemmDesc), U32]
+        lib.dqt_fgemm_batched_workspace_size.argtypes = [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts)]
         lib.dqt_fgemm_batched_workspace_size.restype = SZ
+    if hasattr(lib, "dqt_batch_free"):
+        lib.dqt_batch_free.argtypes = [V]
+        lib.dqt_batch_free.restype = None
     for name in ("dqt_status_str",):
         getattr(lib, name).argtypes = [ctypes.c_int]
         getattr(lib, name).restype = ctypes.c_char_p
@@ -346,25 +358,88 @@ def fgemm_compute(C: torch.Tensor, p: int, kdim: int, plan: Optional[GemmPlan] =
     return C
 
 
+def fgemm_compute_timed(C: torch.Tensor, p: int, kdim: int, start, stop, plan: Optional[GemmPlan] = None,
+                        workspace: Optional[torch.Tensor] = None, stream=None):
+    """fgemm_compute whose multiply kernel records its own start/end into torch.cuda.Event start/stop."""
+    m, n = C.shape
+    pc = plan._c() if plan is not None else None
+    _check(_load().dqt_fgemm_compute_timed(p, m, n, kdim, _dev(C, "C", torch.uint8), n,
+                                           ctypes.byref(pc) if pc is not None else None,
+                                           _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                                           ctypes.c_void_p(start.cuda_event), ctypes.c_void_p(stop.cuda_event),
+                                           _stream(stream)), "dqt_fgemm_compute_timed")
+    return C
+
+
 def make_descs(items):
-    """ctypes descriptor array from (A, B, C, p, algo) tuples of square/rectangular uint8 device tensors."""
+    """ctypes descriptor array from dicts (or tuples) describing each product.
+
+    Each item: (A, B, C, p) or (A, B, C, p, algo) or a dict with keys A, B, C, p
+    and optional algo, interval, log2Q, epilogue.  A [m, k], B [k, n], C [m, n]
+    are contiguous uint8 device tensors.
+    """
     arr = (_GemmDesc * len(items))()
-    for i, (A, B, C, p, algo) in enumerate(items):
+    for i, it in enumerate(items):
+        if isinstance(it, dict):
+            A, B, C, p = it["A"], it["B"], it["C"], it["p"]
+            algo, interval, log2Q, epi = it.get("algo", 0), it.get("interval", 0), it.get("log2Q", 0), it.get("epilogue", 0)
+        else:
+            A, B, C, p = it[:4]
+            algo = it[4] if len(it) > 4 else 0
+            interval = log2Q = epi = 0
         m, kdim = A.shape
         n = B.shape[1]
-        arr[i] = _GemmDesc(A.data_ptr(), B.data_ptr(), C.data_ptr(), m, n, kdim, kdim, n, n, p, algo)
+        if B.shape[0] != kdim or tuple(C.shape) != (m, n):
+            raise ValueError("descriptor shapes do not match")
+        for t in (A, B, C):
+            _dev(t, "operand", torch.uint8)
+        arr[i] = _GemmDesc(A.data_ptr(), B.data_ptr(), C.data_ptr(), m, n, kdim, kdim, n, n, p, algo, interval,
+                           log2Q, epi)
     return arr
 
 
-def fgemm_batched_workspace_size(descs) -> int:
-    return int(_load().dqt_fgemm_batched_workspace_size(descs, len(descs)))
+def _opts(tile_rows: int, ksplit: int) -> _BatchOpts:
+    return _BatchOpts(tile_rows, ksplit)
 
 
-def fgemm_batched(descs, workspace: torch.Tensor, stream=None):
-    """Run every descriptor (from make_descs) in one persistent launch."""
-    ws = fgemm_batched_workspace_size(descs)
+def fgemm_batched_workspace_size(descs, tile_rows: int = 0, ksplit: int = 0) -> int:
+    o = _opts(tile_rows, ksplit)
+    return int(_load().dqt_fgemm_batched_workspace_size(descs, len(descs), ctypes.byref(o)))
+
+
+class Batch:
+    """A prepared batch (device-resident plan in `workspace`); run() enqueues pack + persistent compute."""
+
+    def __init__(self, descs, workspace: torch.Tensor, tile_rows: int = 0, ksplit: int = 0, stream=None):
+        self._descs = descs
+        self.workspace = workspace
+        self._handle = ctypes.c_void_p()
+        o = _opts(tile_rows, ksplit)
+        _check(_load().dqt_fgemm_batched_prepare(descs, len(descs), ctypes.byref(o), _dev(workspace, "workspace"),
+                                                 workspace.numel() * workspace.element_size(), _stream(stream),
+                                                 ctypes.byref(self._handle)), "dqt_fgemm_batched_prepare")
+
+    def run(self, stream=None):
+        _check(_load().dqt_fgemm_batched_run(self._handle, _stream(stream)), "dqt_fgemm_batched_run")
+
+    def close(self):
+        if self._handle:
+            _load().dqt_batch_free(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fgemm_batched(descs, workspace: torch.Tensor, tile_rows: int = 0, ksplit: int = 0, stream=None):
+    """Run every descriptor (from make_descs) in one packing launch and one persistent launch."""
+    o = _opts(tile_rows, ksplit)
+    ws = fgemm_batched_workspace_size(descs, tile_rows, ksplit)
     if workspace.numel() * workspace.element_size() < ws:
         raise ValueError(f"workspace needs {ws} bytes")
-    _check(_load().dqt_fgemm_batched(descs, len(descs), _dev(workspace, "workspace"),
+    _check(_load().dqt_fgemm_batched(descs, len(descs), ctypes.byref(o), _dev(workspace, "workspace"),
                                      workspace.numel() * workspace.element_size(), _stream(stream)),
            "dqt_fgemm_batched")

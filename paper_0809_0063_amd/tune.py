@@ -1,0 +1,230 @@
+"""Autotuner for the batched F_p products: per (size, p) bucket plan choice.
+
+For each bucket (a range of orders n and a prime p) the tuner times the
+candidate plans on one representative square product and keeps the fastest:
+
+* algo: packed CMM (four entries per word, middle product on 16-bit Kronecker
+  pairs), plain (one entry per word), dot4 (four u8 entries per word);
+* the delayed-reduction interval of the packed path (the largest allowed by
+  eq:lower, or a fraction of it) and the matching Q;
+* the epilogue (one REDC per output, or REDQ over gathered dot products).
+
+The launch shape of the persistent kernel (rows per wave, waves splitting k)
+is one per batch; `tune_launch` times the candidates on the batch itself.
+Results are cached as JSON keyed by the device architecture and the library
+version.  Every candidate produces the same bytes (the parity tests cover all
+of them), so tuning only changes speed.
+
+Cost model seed: the paper's section 5.3 counts multiply-adds and reductions;
+here the counts are one instruction per four multiply-adds (packed), one per
+multiply-add (plain), plus one reduction per output, and the measured times
+replace the model once the tuner has run.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from dataclasses import asdict, dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import dqt as D
+
+BUCKET_EDGES = (16, 32, 64, 128, 256, 512, 1025)
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+@dataclass(frozen=True)
+class BucketPlan:
+    algo: int
+    interval: int = 0
+    log2Q: int = 0
+    epilogue: int = 0
+    us: float = 0.0
+
+    def desc_fields(self) -> Dict[str, int]:
+        return {"algo": self.algo, "interval": self.interval, "log2Q": self.log2Q, "epilogue": self.epilogue}
+
+
+def bucket_of(n: int) -> int:
+    for i in range(len(BUCKET_EDGES) - 1):
+        if n < BUCKET_EDGES[i + 1]:
+            return i
+    return len(BUCKET_EDGES) - 2
+
+
+def representative(bucket: int) -> int:
+    lo, hi = BUCKET_EDGES[bucket], BUCKET_EDGES[bucket + 1] - 1
+    return int(round(math.sqrt(lo * hi)))
+
+
+def cmm_interval_max(p: int, kdim: int) -> int:
+    """Largest delayed-reduction interval of the packed path: L (p-1)^2 < Q with (p-1)(Q+1) < 2^16."""
+    e2 = (p - 1) ** 2
+    bmax = max(b for b in range(1, 17) if (p - 1) * ((1 << b) + 1) < 65536)
+    lmax = ((1 << bmax) - 1) // e2 if e2 else kdim
+    return (lmax // 4) * 4
+
+
+def model_cost(p: int, n: int, plan: BucketPlan) -> float:
+    """Instruction-count model (seed ordering before measurement)."""
+    macs = float(n) ** 3
+    if plan.algo == D.GEMM_CMM:
+        return macs / 4 + n * n * (3 if plan.epilogue == 0 else 5)
+    if plan.algo == D.GEMM_DOT4:
+        return macs / 4 + 3 * n * n
+    return macs + 3 * n * n
+
+
+def fqt_model(N: int, p: int, d: int, beta: int) -> Tuple[float, float, float, float]:
+    """Table tab:mulpol (section 5.3) for a degree-N product: (delayed mul&add, delayed REDC,
+    FQT mul&add, FQT REDQ) with n_d, n_q as printed after the table.
+
+    Reading: q = 2^(beta/(2d+1)) with a real exponent, and the FQT mul&add count
+    includes the ceil((2d+2)/2) multiply-adds of each REDQ_{2d+1}; with these the
+    paper's two worked examples reproduce.
+    """
+    Dq = -(-(N + 1) // (d + 1)) - 1
+    nd = (2 ** (beta + 1)) // ((p - 1) ** 2)
+    q = 2.0 ** (beta / (2 * d + 1))
+    nq = int(q // ((d + 1) * (p - 1) ** 2))
+    delayed_ma = float(2 * N + 1) ** 2
+    delayed_red = float(2 * N + 1) * -(-(2 * N + 1) // nd)
+    fqt_red = float(2 * Dq + 1) * -(-(2 * Dq + 1) // nq)
+    fqt_ma = float(2 * Dq + 1) ** 2 + fqt_red * -(-(2 * d + 2) // 2)
+    return delayed_ma, delayed_red, fqt_ma, fqt_red
+
+
+def candidates(p: int, n: int) -> List[BucketPlan]:
+    out = [BucketPlan(D.GEMM_PLAIN), BucketPlan(D.GEMM_DOT4)]
+    lmax = cmm_interval_max(p, n)
+    if lmax >= 4:
+        ivals = sorted({min(lmax, ((n + 3) // 4) * 4), max(4, (lmax // 2) // 4 * 4)})
+        for iv in ivals:
+            for epi in (D.EPI_REDC, D.EPI_REDQ):
+                out.append(BucketPlan(D.GEMM_CMM, interval=iv if iv < n else 0, epilogue=epi))
+    return out
+
+
+def _time_plan(p: int, n: int, plan: BucketPlan, reps: int = 20) -> float:
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device="cpu").manual_seed(1234 + n * 7 + p)
+    A = torch.randint(0, p, (n, n), dtype=torch.uint8, generator=g).to(dev)
+    B = torch.randint(0, p, (n, n), dtype=torch.uint8, generator=g).to(dev)
+    C = torch.empty((n, n), dtype=torch.uint8, device=dev)
+    gp = D.GemmPlan(algo=plan.algo, interval=plan.interval, log2Q=plan.log2Q, epilogue=plan.epilogue)
+    ws = torch.empty(max(1, D.fgemm_workspace_size(p, n, n, n, gp)), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        D.fgemm(A, B, p, plan=gp, out=C, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        D.fgemm(A, B, p, plan=gp, out=C, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+class Tuner:
+    def __init__(self, cache_path: Optional[str] = DEFAULT_CACHE):
+        self.cache_path = cache_path
+        self.key = self._key()
+        self.table: Dict[str, BucketPlan] = {}
+        self.launch: Optional[Tuple[int, int]] = None
+        self._load()
+
+    @staticmethod
+    def _key() -> str:
+        arch = "cpu"
+        if torch.cuda.is_available():
+            arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        try:
+            ver = D.version()
+        except Exception:
+            ver = "unbuilt"
+        return f"{arch}|{ver}|rocm{torch.version.hip}"
+
+    def _load(self):
+        if self.cache_path and os.path.exists(self.cache_path):
+            try:
+                data = json.load(open(self.cache_path))
+            except (OSError, ValueError):
+                return
+            ent = data.get(self.key)
+            if ent:
+                self.table = {k: BucketPlan(**v) for k, v in ent.get("buckets", {}).items()}
+                if ent.get("launch"):
+                    self.launch = tuple(ent["launch"])
+
+    def save(self):
+        if not self.cache_path:
+            return
+        data = {}
+        if os.path.exists(self.cache_path):
+            try:
+                data = json.load(open(self.cache_path))
+            except (OSError, ValueError):
+                data = {}
+        data[self.key] = {"buckets": {k: asdict(v) for k, v in self.table.items()},
+                          "launch": list(self.launch) if self.launch else None,
+                          "saved": time.strftime("%Y-%m-%d %H:%M:%S")}
+        tmp = self.cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.cache_path)
+
+    def plan(self, p: int, n: int) -> BucketPlan:
+        """Tuned plan of the bucket of n (model order if the bucket was not measured)."""
+        k = f"{p}:{bucket_of(n)}"
+        if k in self.table:
+            return self.table[k]
+        cands = candidates(p, n)
+        return min(cands, key=lambda c: model_cost(p, n, c))
+
+    def tune_bucket(self, p: int, bucket: int, reps: int = 20) -> BucketPlan:
+        n = representative(bucket)
+        best = None
+        for c in candidates(p, n):
+            us = _time_plan(p, n, c, reps)
+            c = BucketPlan(c.algo, c.interval, c.log2Q, c.epilogue, round(us, 3))
+            if best is None or c.us < best.us:
+                best = c
+        # the interval was tuned at the representative order; the largest allowed
+        # interval for the bucket is kept when the whole range fits one interval
+        self.table[f"{p}:{bucket}"] = best
+        return best
+
+    def tune(self, primes: Sequence[int], buckets: Optional[Sequence[int]] = None, reps: int = 20):
+        for p in primes:
+            for b in (buckets if buckets is not None else range(len(BUCKET_EDGES) - 1)):
+                self.tune_bucket(p, b, reps)
+        return self.table
+
+    def tune_launch(self, descs, ws: torch.Tensor, shapes=((16, 4), (8, 2), (16, 2), (8, 4)), reps: int = 3):
+        """Pick (rows per wave, k-split) for a batch by timing its persistent launch."""
+        best = None
+        for tm, ks in shapes:
+            need = D.fgemm_batched_workspace_size(descs, tm, ks)
+            if need == 0 or need > ws.numel():
+                continue
+            b = D.Batch(descs, ws, tm, ks)
+            b.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                b.run()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            b.close()
+            if best is None or dt < best[0]:
+                best = (dt, tm, ks)
+        if best:
+            self.launch = (best[1], best[2])
+        return self.launch
+
+    def desc_fields(self, p: int, n: int) -> Dict[str, int]:
+        return self.plan(p, n).desc_fields()

@@ -36,6 +36,12 @@ def test_small_polymul_workload(dqt):
     with pytest.raises(dqt.DQTError) as e:
         dqt.polymul_u8(to_dev(a), to_dev(b), 3, log2q=4)
     assert e.value.status == dqt.DQT_E_BOUND
+    # all 6,561 pairs and the all-2 worst case at q = 2^6 (the compile-time specialised kernel)
+    elems = np.array(list(itertools.product(range(3), repeat=4)), dtype=np.uint8)
+    ea, eb = np.repeat(elems, len(elems), axis=0), np.tile(elems, (len(elems), 1))
+    assert (to_host(dqt.polymul_u8(to_dev(ea), to_dev(eb), 3, log2q=6)) == O.polymul(ea, eb, 3)).all()
+    w = inputs.worst_case((1027, 4), 3)
+    assert (to_host(dqt.polymul_u8(to_dev(w), to_dev(w), 3, log2q=6)) == O.polymul(w, w, 3)).all()
     plain = to_host(dqt.polymul_plain_u8(to_dev(a), to_dev(b), 3))
     assert (plain == ref).all()
 

@@ -150,6 +150,20 @@ dqt_status dqt_gf_mul_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count,
                          uint32_t log2q, const uint8_t *modulus, uint8_t *d_out, void *stream);
 
 /*
+ * Dot products over GF(p^k) (algorithm FGDP, section 6, theorem thm:fgdp):
+ * d_out[t] = sum_{l<n} a[t][l] * b[t][l] in F_p[X]/(P).  d_a, d_b: uint8
+ * [count][n][k], d_out: uint8 [count][k]; modulus as for dqt_gf_mul_u8.
+ * Products are accumulated in packed words, n_q at a time, with q the
+ * largest power of two such that (2k-1) log2 q <= 53 and n_q the largest
+ * count with q > n_q k (p-1)^2 (eq:bounds); each word costs one REDQ
+ * compression, two table lookups and one field addition.  p <= 127,
+ * 2 <= k <= 6, k ceil(log2 p) <= 12; DQT_E_UNSUPPORTED when not even one
+ * product fits such a word.
+ */
+dqt_status dqt_gf_dot_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t n, uint32_t k, uint32_t p,
+                         const uint8_t *modulus, uint8_t *d_out, void *stream);
+
+/*
  * Plain per-entry comparators (the paper's "delayed" baseline, section 5.1):
  * one coefficient per machine multiply-add, integer accumulation, one
  * reduction (REDC) per output coefficient.  Same layouts and results as the
@@ -244,6 +258,25 @@ dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, 
 dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t *d_C, uint64_t ldc,
                                    const dqt_gemm_plan *plan, const void *d_work, size_t work_bytes,
                                    void *start_event, void *stop_event, void *stream);
+
+/*
+ * One packed operand in a buffer of its own, so that it can stay resident
+ * and be multiplied many times (section 7.1: compressed matrices are often
+ * reused).  side 0 packs the rows of A (rows_or_cols = m, d_X = A, ldx = lda
+ * >= kdim); side 1 packs the columns of B (rows_or_cols = n, d_X = B, ldx =
+ * ldb >= n).  The packed layout depends only on (p, kdim, plan) and on the
+ * packed dimension, so an A packed with m rows can be multiplied by any packed
+ * B with the same (p, kdim, plan).  dqt_fgemm_packed_bytes gives the size of
+ * the packed copy (0 for invalid arguments or an unsupported plan); d_packed
+ * must be 16-byte aligned and hold that many bytes.  dqt_fgemm_packed
+ * multiplies a packed A (m rows) by a packed B (n columns) and writes C; both
+ * must come from dqt_fgemm_pack_side with the same p, kdim and plan.
+ */
+size_t dqt_fgemm_packed_bytes(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, int side, const dqt_gemm_plan *plan);
+dqt_status dqt_fgemm_pack_side(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, const uint8_t *d_X, uint64_t ldx,
+                               int side, const dqt_gemm_plan *plan, void *d_packed, void *stream);
+dqt_status dqt_fgemm_packed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const void *d_CA, const void *d_CB,
+                            uint8_t *d_C, uint64_t ldc, const dqt_gemm_plan *plan, void *stream);
 
 /*
  * Batched F_p matrix products in one persistent launch.

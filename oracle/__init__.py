@@ -137,6 +137,22 @@ def gf_mul(a: np.ndarray, b: np.ndarray, p: int, modulus: Sequence[int], threads
     return out
 
 
+def gf_dot(a: np.ndarray, b: np.ndarray, p: int, modulus: Sequence[int], threads: int = 0) -> np.ndarray:
+    """Dot products over GF(p^k) (algorithm FGDP's result): out[t] = sum_l a[t,l] b[t,l] in the field.
+
+    a, b: uint8 [N, n, k].  Every product is the plain field product (gf_mul);
+    the sum is coefficient-wise mod p, reduced after every addition.
+    """
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    N, n, k = a.shape
+    prods = gf_mul(a.reshape(N * n, k), b.reshape(N * n, k), p, modulus, threads).reshape(N, n, k)
+    out = np.zeros((N, k), dtype=np.int64)
+    for l in range(n):
+        out = (out + prods[:, l, :]) % p
+    return out.astype(np.uint8)
+
+
 def radix_mod(r: np.ndarray, p: int, logq: int, nres: int, threads: int = 0) -> np.ndarray:
     """REDQ's specification (alg:REDQ ENSURE): digits of r in base q = 2^logq, each mod p.
 

@@ -269,10 +269,6 @@ __global__ __launch_bounds__(256) void k_redq_unpack(const uint64_t* __restrict_
 // GF(p^k): the two tables of algorithm FGDP (theorem thm:fgdp), built in LDS
 // ---------------------------------------------------------------------------
 
-struct GfArgs {
-    uint64_t xpow[7];    // X^(K-1+j) mod P for j = 0..K-1, K coefficient bytes each
-    uint32_t k;
-};
 
 // Entry il of T_L: (u_0..u_{K-1}) -> sum_{i<K-1} mu_i X^i (already reduced, degree < K-1).
 // Entry ih of T_H: (u_{K-1}..u_{2K-2}) -> (sum_{i>=K-1} mu_i X^i) mod P.
@@ -678,7 +674,7 @@ extern "C" dqt_status dqt_polymul(const uint64_t* d_a, const uint64_t* d_b, uint
 }
 
 // X^i mod P for i = K-1 .. 2K-2 as K coefficient bytes each (host polynomial arithmetic).
-static dqt_status gf_setup(uint32_t k, uint32_t p, const uint8_t* modulus, GfArgs* ga) {
+dqt_status dqt::gf_setup_args(uint32_t k, uint32_t p, const uint8_t* modulus, GfArgs* ga) {
     if (!modulus || k < 2 || k > 6) return DQT_E_INVALID;
     if (modulus[k] != 1) return DQT_E_INVALID;
     for (uint32_t i = 0; i <= k; ++i)
@@ -727,7 +723,7 @@ extern "C" dqt_status redq_unpack(const uint64_t* d_r, uint64_t count, const dqt
     if (modulus) {
         if (a->nres != 2 * a->k_coeffs - 1) return DQT_E_INVALID;
         GfArgs ga;
-        DQT_TRY(gf_setup(a->k_coeffs, a->p, modulus, &ga));
+        DQT_TRY(gf_setup_args(a->k_coeffs, a->p, modulus, &ga));
         if (gf_smem_bytes(a->k_coeffs, ra.w) > kMaxGfSmem) return DQT_E_UNSUPPORTED;
         if (a->log2q * (a->k_coeffs - 1) + ra.w > 32) return DQT_E_UNSUPPORTED;
         if (count == 0) return DQT_OK;
@@ -879,7 +875,7 @@ extern "C" dqt_status dqt_gf_mul_u8(const uint8_t* d_a, const uint8_t* d_b, uint
                                     uint32_t log2q, const uint8_t* modulus, uint8_t* d_out, void* stream) {
     if (p < 2 || p > 255 || k < 2 || k > 6 || !modulus) return DQT_E_INVALID;
     GfArgs ga;
-    DQT_TRY(gf_setup(k, p, modulus, &ga));
+    DQT_TRY(gf_setup_args(k, p, modulus, &ga));
     dqt_qadic q;
     DQT_TRY(product_qadic(p, k, log2q, &q));
     RedqArgs ra;

@@ -462,13 +462,13 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
 }
 
 // Multiplication and extraction on packed operands.
-dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* C, uint64_t ldc,
-                                 const GemmPlanResolved& r, const void* work, hipStream_t s) {
+dqt_status fgemm_compute_enqueue2(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* C, uint64_t ldc,
+                                  const GemmPlanResolved& r, const void* pA, const void* pB, hipStream_t s) {
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
     if (r.algo == DQT_GEMM_MFMA) {
         MfmaArgs g;
-        g.A8 = reinterpret_cast<const uint8_t*>(work);
-        g.BT8 = g.A8 + (size_t)r.m_pad * r.k_pad;
+        g.A8 = reinterpret_cast<const uint8_t*>(pA);
+        g.BT8 = reinterpret_cast<const uint8_t*>(pB);
         g.C = C;
         g.m = (uint32_t)m;
         g.n = (uint32_t)n;
@@ -486,8 +486,8 @@ dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kd
     }
     GemmArgs g;
     memset(&g, 0, sizeof(g));
-    g.CA = reinterpret_cast<const uint32_t*>(work);
-    g.CB = g.CA + (size_t)r.KW * r.m_pad;
+    g.CA = reinterpret_cast<const uint32_t*>(pA);
+    g.CB = reinterpret_cast<const uint32_t*>(pB);
     g.C = C;
     g.m = (uint32_t)m;
     g.n = (uint32_t)n;
@@ -515,6 +515,13 @@ dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kd
     }
     DQT_LAUNCH_CHECK("fgemm");
     return DQT_OK;
+}
+
+dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* C, uint64_t ldc,
+                                 const GemmPlanResolved& r, const void* work, hipStream_t s) {
+    const uint8_t* w = reinterpret_cast<const uint8_t*>(work);
+    const size_t a_bytes = r.algo == DQT_GEMM_MFMA ? (size_t)r.m_pad * r.k_pad : (size_t)r.KW * r.m_pad * 4;
+    return fgemm_compute_enqueue2(p, m, n, kdim, C, ldc, r, w, w + a_bytes, s);
 }
 
 dqt_status fgemm_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A, uint64_t lda,
@@ -584,6 +591,57 @@ extern "C" dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n
     const dqt_status st = dqt_fgemm_compute(p, m, n, kdim, d_C, ldc, plan, d_work, work_bytes, stream);
     g_ev_start = g_ev_stop = nullptr;
     return st;
+}
+
+// Packed operands in caller-chosen buffers (one side at a time), so that a
+// packed B can stay resident and be multiplied by many row blocks of A.
+static dqt_status side_plan(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, int side, const dqt_gemm_plan* plan,
+                            GemmPlanResolved* r) {
+    if (side != 0 && side != 1) return DQT_E_INVALID;
+    // the packed layout of one side does not depend on the other dimension
+    return resolve_plan(p, side == 0 ? rows_or_cols : 1, side == 1 ? rows_or_cols : 1, kdim, plan, r);
+}
+
+static size_t side_bytes(const GemmPlanResolved& r, int side) {
+    if (r.algo == DQT_GEMM_MFMA) return (size_t)r.k_pad * (side == 0 ? r.m_pad : r.n_pad);
+    return (size_t)r.KW * (side == 0 ? r.m_pad : r.n_pad) * sizeof(uint32_t);
+}
+
+extern "C" size_t dqt_fgemm_packed_bytes(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, int side,
+                                         const dqt_gemm_plan* plan) {
+    GemmPlanResolved r;
+    if (side_plan(p, rows_or_cols, kdim, side, plan, &r) != DQT_OK) return 0;
+    return side_bytes(r, side);
+}
+
+extern "C" dqt_status dqt_fgemm_pack_side(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, const uint8_t* d_X,
+                                          uint64_t ldx, int side, const dqt_gemm_plan* plan, void* d_packed,
+                                          void* stream) {
+    GemmPlanResolved r;
+    DQT_TRY(side_plan(p, rows_or_cols, kdim, side, plan, &r));
+    if (rows_or_cols == 0) return DQT_OK;
+    if (!d_X || !d_packed) return DQT_E_INVALID;
+    if ((side == 0 && ldx < kdim) || (side == 1 && ldx < rows_or_cols) || ldx > 0xFFFFFFFFull) return DQT_E_INVALID;
+    DQT_TRY(ensure_device_ready());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the pack kernels address A's words from the workspace start and B's after
+    // A's; place the target so that the requested side lands on d_packed
+    uint8_t* base = reinterpret_cast<uint8_t*>(d_packed);
+    if (side == 1) base -= side_bytes(r, 0);
+    if (side == 0)
+        return fgemm_pack_enqueue(rows_or_cols, 1, kdim, d_X, ldx, nullptr, 1, r, base, s);
+    return fgemm_pack_enqueue(1, rows_or_cols, kdim, nullptr, 1, d_X, ldx, r, base, s);
+}
+
+extern "C" dqt_status dqt_fgemm_packed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const void* d_CA,
+                                       const void* d_CB, uint8_t* d_C, uint64_t ldc, const dqt_gemm_plan* plan,
+                                       void* stream) {
+    GemmPlanResolved r;
+    DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
+    if (m == 0 || n == 0) return DQT_OK;
+    if (!d_CA || !d_CB || !d_C || ldc < n || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
+    DQT_TRY(ensure_device_ready());
+    return fgemm_compute_enqueue2(p, m, n, kdim, d_C, ldc, r, d_CA, d_CB, reinterpret_cast<hipStream_t>(stream));
 }
 
 extern "C" dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* d_A, uint64_t lda,

@@ -26,6 +26,15 @@ uint32_t residue_bits(uint32_t p);
 // Grid size for a streaming kernel over `items` work items of `per_block` each.
 unsigned stream_grid(uint64_t items, unsigned per_block, unsigned waves_per_cu = 8);
 
+// GF(p^k) set-up shared by the GF kernels: X^(k-1+j) mod P for j = 0..k-1,
+// k coefficient bytes each (the reductions the two FGDP tables apply).
+struct GfArgs {
+    uint64_t xpow[7];
+    uint32_t k;
+};
+// Checks the monic modulus (k+1 coefficients below p, leading 1) and fills ga.
+dqt_status gf_setup_args(uint32_t k, uint32_t p, const uint8_t* modulus, GfArgs* ga);
+
 }  // namespace dqt
 
 #define DQT_TRY(expr)                         \

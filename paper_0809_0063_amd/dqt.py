@@ -103,6 +103,7 @@ def _load():
         "dqt_gf_mul_u8": [V, V, U64, U32, U32, U32, V, V, V],
         "dqt_polymul_plain_u8": [V, V, U64, U32, U32, V, V],
         "dqt_gf_mul_plain_u8": [V, V, U64, U32, U32, V, V, V],
+        "dqt_gf_dot_u8": [V, V, U64, U32, U32, U32, V, V, V],
         "dqt_polymul_fqt_u8": [V, U32, V, U32, U64, U32, U32, V, V],
         "dqt_fgemm": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V],
@@ -112,6 +113,8 @@ def _load():
         "dqt_fgemm_pack": [U32, U64, U64, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_compute": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_compute_timed": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V, V, V],
+        "dqt_fgemm_pack_side": [U32, U64, U64, V, U64, I, ctypes.POINTER(_GemmPlan), V, V],
+        "dqt_fgemm_packed": [U32, U64, U64, U64, V, V, V, U64, ctypes.POINTER(_GemmPlan), V],
     }
     for name, args in sigs.items():
         if not hasattr(lib, name):
@@ -125,6 +128,9 @@ def _load():
     if hasattr(lib, "dqt_fgemm_batched_workspace_size"):
         lib.dqt_fgemm_batched_workspace_size.argtypes = [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts)]
         lib.dqt_fgemm_batched_workspace_size.restype = SZ
+    if hasattr(lib, "dqt_fgemm_packed_bytes"):
+        lib.dqt_fgemm_packed_bytes.argtypes = [U32, U64, U64, I, ctypes.POINTER(_GemmPlan)]
+        lib.dqt_fgemm_packed_bytes.restype = SZ
     if hasattr(lib, "dqt_batch_free"):
         lib.dqt_batch_free.argtypes = [V]
         lib.dqt_batch_free.restype = None
@@ -290,6 +296,21 @@ def gf_mul_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
     return out
 
 
+def gf_dot_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
+              out: Optional[torch.Tensor] = None, stream=None):
+    """Dot products over GF(p^k) by FGDP: uint8 [N, n, k] x uint8 [N, n, k] -> uint8 [N, k]."""
+    if a.dim() != 3 or a.shape != b.shape:
+        raise ValueError("a and b must be [N, n, k] with the same shape")
+    N, n, k = a.shape
+    if out is None:
+        out = torch.empty((N, k), dtype=torch.uint8, device=a.device)
+    mod = _host_modulus(modulus)
+    _check(_load().dqt_gf_dot_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), N, n, k, p,
+                                 ctypes.cast(mod, ctypes.c_void_p), _dev(out, "out", torch.uint8), _stream(stream)),
+           "dqt_gf_dot_u8")
+    return out
+
+
 def gf_mul_plain_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
                     out: Optional[torch.Tensor] = None, stream=None):
     _u8_pair(a, b)
@@ -369,6 +390,87 @@ def fgemm_compute_timed(C: torch.Tensor, p: int, kdim: int, start, stop, plan: O
                                            ctypes.c_void_p(start.cuda_event), ctypes.c_void_p(stop.cuda_event),
                                            _stream(stream)), "dqt_fgemm_compute_timed")
     return C
+
+
+def fgemm_packed_bytes(p: int, rows_or_cols: int, kdim: int, side: int, plan: Optional[GemmPlan] = None) -> int:
+    """Bytes of one packed operand (side 0: the m rows of A; side 1: the n columns of B)."""
+    pc = plan._c() if plan is not None else None
+    return int(_load().dqt_fgemm_packed_bytes(p, rows_or_cols, kdim, side, ctypes.byref(pc) if pc is not None else None))
+
+
+def fgemm_pack_side(X: torch.Tensor, p: int, side: int, plan: Optional[GemmPlan] = None,
+                    out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Packed copy of A [m, k] (side 0) or B [k, n] (side 1) in a buffer of its own (uint8 tensor)."""
+    if X.dim() != 2:
+        raise ValueError("a matrix is required")
+    rows_or_cols, kdim = (X.shape[0], X.shape[1]) if side == 0 else (X.shape[1], X.shape[0])
+    nb = fgemm_packed_bytes(p, rows_or_cols, kdim, side, plan)
+    if nb == 0:
+        raise DQTError(DQT_E_UNSUPPORTED, "dqt_fgemm_packed_bytes", "no packed layout for these arguments")
+    if out is None:
+        out = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    elif out.numel() * out.element_size() < nb:
+        raise ValueError("packed buffer too small")
+    pc = plan._c() if plan is not None else None
+    _check(_load().dqt_fgemm_pack_side(p, rows_or_cols, kdim, _dev(X, "X", torch.uint8), X.shape[1], side,
+                                       ctypes.byref(pc) if pc is not None else None, _dev(out, "packed"),
+                                       _stream(stream)), "dqt_fgemm_pack_side")
+    return out
+
+
+def fgemm_packed(CA: torch.Tensor, CB: torch.Tensor, p: int, m: int, n: int, kdim: int,
+                 plan: Optional[GemmPlan] = None, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """C = A.B mod p from a packed A (m rows) and a packed B (n columns) made by fgemm_pack_side."""
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.uint8, device=CA.device)
+    if tuple(out.shape) != (m, n):
+        raise ValueError("C must be [m, n]")
+    pc = plan._c() if plan is not None else None
+    _check(_load().dqt_fgemm_packed(p, m, n, kdim, _dev(CA, "CA"), _dev(CB, "CB"), _dev(out, "C", torch.uint8),
+                                    out.stride(0), ctypes.byref(pc) if pc is not None else None, _stream(stream)),
+           "dqt_fgemm_packed")
+    return out
+
+
+class FgemmCall:
+    """One F_p product with its arguments marshalled once, for repeated launches.
+
+    pack() and compute() / compute_timed() enqueue the same two phases as
+    fgemm on the stream given at construction; the operands, output and
+    workspace must stay alive and unchanged in shape while the object is used.
+    """
+
+    def __init__(self, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, p: int, plan: Optional[GemmPlan] = None,
+                 workspace: Optional[torch.Tensor] = None, stream=None):
+        m, kdim = A.shape
+        n = B.shape[1]
+        if B.shape[0] != kdim or tuple(C.shape) != (m, n):
+            raise ValueError("shapes do not match")
+        ws = fgemm_workspace_size(p, m, n, kdim, plan)
+        if ws and (workspace is None or workspace.numel() * workspace.element_size() < ws):
+            workspace = torch.empty(ws, dtype=torch.uint8, device=A.device)
+        self._keep = (A, B, C, workspace)
+        self._pc = plan._c() if plan is not None else None
+        pcp = ctypes.byref(self._pc) if self._pc is not None else None
+        wptr = _dev(workspace, "workspace") if ws else None
+        wbytes = workspace.numel() * workspace.element_size() if ws else 0
+        st = _stream(stream)
+        self._lib = _load()
+        self._pack_args = (p, m, n, kdim, _dev(A, "A", torch.uint8), kdim, _dev(B, "B", torch.uint8), n, pcp,
+                           wptr, wbytes, st)
+        self._comp_args = (p, m, n, kdim, _dev(C, "C", torch.uint8), n, pcp, wptr, wbytes)
+        self._st = st
+
+    def pack(self):
+        _check(self._lib.dqt_fgemm_pack(*self._pack_args), "dqt_fgemm_pack")
+
+    def compute(self):
+        _check(self._lib.dqt_fgemm_compute(*self._comp_args, self._st), "dqt_fgemm_compute")
+
+    def compute_timed(self, start, stop):
+        _check(self._lib.dqt_fgemm_compute_timed(*self._comp_args, ctypes.c_void_p(start.cuda_event),
+                                                 ctypes.c_void_p(stop.cuda_event), self._st),
+               "dqt_fgemm_compute_timed")
 
 
 def make_descs(items):

@@ -114,6 +114,23 @@ class Server:
             self.cache.put(key, ent, a.nbytes + b.nbytes, pinned)
         return ent
 
+    def _packed_b(self, i: int, B: torch.Tensor, p: int, stream, pinned: set) -> torch.Tensor:
+        key = (i, "CB")
+        ent = self.cache.get(key)
+        if ent is None:
+            with torch.cuda.stream(stream):
+                CB = D.fgemm_pack_side(B, p, 1, plan=self.plan)
+                ready = torch.cuda.Event()
+                ready.record(stream)
+            self.cache.put(key, (CB, ready), CB.numel(), pinned)
+            return CB
+        CB, ready = ent
+        # packed on another slot's stream: order this stream after the packing, and
+        # keep the allocator from reusing the buffer before this stream is done with it
+        stream.wait_event(ready)
+        CB.record_stream(stream)
+        return CB
+
     def _gemm_chunk_rows(self, n: int) -> int:
         rows = max(16, int(self.chunk_macs // max(1, n * n)))
         rows = (rows // 16) * 16
@@ -123,8 +140,8 @@ class Server:
         if pl.kind == "gemm":
             n = pl.n
             rows = self._gemm_chunk_rows(n)
-            ws = D.fgemm_workspace_size(pl.p, rows, n, n, self.plan)
-            return n * n + ws + 2 * n * n
+            ca = D.fgemm_packed_bytes(pl.p, rows, n, 0, self.plan)
+            return n * n + ca + 2 * n * n
         return pl.n * (2 * pl.deg + 1) + 2 * pl.n * (pl.deg + 1)
 
     # --- request set-up ---------------------------------------------------------
@@ -138,7 +155,9 @@ class Server:
             r.out = torch.empty((n, n), dtype=torch.uint8, device=self.dev)
             rows = self._gemm_chunk_rows(n)
             r.chunks = [(r0, min(n, r0 + rows)) for r0 in range(0, n, rows)]
-            r.ws = {}
+            r.CB = self._packed_b(r.item, B, pl.p, s, pinned)
+            r.CA = torch.empty(D.fgemm_packed_bytes(pl.p, rows, n, 0, self.plan), dtype=torch.uint8,
+                               device=self.dev)
         else:
             r.out = torch.empty((pl.n, 2 * pl.deg + 1), dtype=torch.uint8, device=self.dev)
             r.chunks = [None]
@@ -152,7 +171,10 @@ class Server:
             if pl.kind == "gemm":
                 r0, r1 = c
                 m = r1 - r0
-                D.fgemm(r.A[r0:r1], r.B, pl.p, plan=self.plan, out=r.out[r0:r1], workspace=r.ws.get(m))
+                # the rows of this chunk are packed into the request's buffer (the stream orders the
+                # reuse of that buffer by the next chunk); B stays packed in the residency cache
+                D.fgemm_pack_side(r.A[r0:r1], pl.p, 0, plan=self.plan, out=r.CA)
+                D.fgemm_packed(r.CA, r.CB, pl.p, m, pl.n, pl.n, plan=self.plan, out=r.out[r0:r1])
             else:
                 polymul(r.A, r.B, pl.p, out=r.out)
         r.next_chunk += 1

@@ -1,0 +1,93 @@
+"""The batched and serving workloads as measured by the benchmark.
+
+* batched: 10,000 square F_p products, n log-uniform in [16, 1024], p in
+  {2,3,5,7}; all of them in one packing launch plus one persistent launch,
+  captured in a graph; the time of a replay and the F_p op rate.
+* serving: a Poisson stream over a pool of payloads (F_p products of order
+  32..2048 and polynomial-product batches of degree 2..15, batch 1..4096,
+  p in {2,3,5,7,11}); p50/p99 latency and throughput at a fixed rate.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import dqt as D
+from . import inputs
+from . import serve as S
+
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inputs.SEED_BATCH) -> Dict[str, float]:
+    dev = torch.device("cuda:0")
+    items = inputs.batch_items(n_items, seed=seed)
+    t0 = time.perf_counter()
+    ops, macs, dot_ops = [], 0.0, 0.0
+    for it in items:
+        A, B = inputs.item_operands(it)
+        d = {"A": torch.from_numpy(A).to(dev), "B": torch.from_numpy(B).to(dev),
+             "C": torch.empty((it.n, it.n), dtype=torch.uint8, device=dev), "p": it.p}
+        if tuner is not None:
+            d.update(tuner.desc_fields(it.p, it.n))
+        ops.append(d)
+        macs += float(it.n) ** 3
+        dot_ops += float(it.n) * it.n * ((it.n + 3) // 4)
+    gen_s = time.perf_counter() - t0
+    descs = D.make_descs(ops)
+    launch = tuner.launch if (tuner is not None and tuner.launch) else (16, 4)
+    ws = torch.empty(D.fgemm_batched_workspace_size(descs, *launch), dtype=torch.uint8, device=dev)
+    batch = D.Batch(descs, ws, *launch)
+    batch.run()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            batch.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / replays
+    # a cheap spot check of the replayed output (full parity is in the tests)
+    C0 = ops[0]["C"].cpu().numpy()
+    A0, B0 = inputs.item_operands(items[0])
+    assert (C0[:1] == (A0[:1].astype(np.int64) @ B0.astype(np.int64)) % items[0].p).all()
+    batch.close()
+    return {"products": n_items, "ms_per_replay": round(sec * 1e3, 3), "fp_gop_s": round(2 * macs / sec / 1e9, 1),
+            "packed_lane_op_frac": round(dot_ops / sec / PEAK_LANE_OPS, 4), "launch": list(launch),
+            "input_gen_s": round(gen_s, 1)}
+
+
+def serving(n_requests: int = 5000, warmup: int = 500, qps: Optional[float] = None, n_gemm: int = 600,
+            n_poly: int = 600, hbm_budget: int = 16 << 30, seed: int = inputs.SEED_SERVE) -> Dict[str, float]:
+    pool = inputs.serve_pool(n_gemm=n_gemm, n_poly=n_poly, seed=seed)
+    server = S.Server(pool, hbm_budget=hbm_budget, slots=8)
+    if qps is None:
+        # saturation estimate: mean service time of a request run alone, on a sample
+        idx = inputs.request_sequence(32, len(pool), seed=seed + 3)
+        t0 = time.perf_counter()
+        for i in idx:
+            S.run_alone(server, int(i))
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / len(idx)
+        qps = 0.8 / per
+    arr = inputs.poisson_arrivals(n_requests + warmup, qps, seed=seed + 1)
+    seq = inputs.request_sequence(n_requests + warmup, len(pool), seed=seed + 2)
+    done = server.run(arr, seq, max_wall=240.0)
+    st = S.Server.summary(done, warmup, pool)
+    st["qps_offered"] = round(qps, 1)
+    st["completed"] = len(done)
+    st["cache_hit_rate"] = round(server.cache.hits / max(1, server.cache.hits + server.cache.misses), 3)
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}

@@ -104,3 +104,23 @@ def test_fgemm_workspace_sizes(D):
     # packing bounds: a Kronecker pair must fit a 16-bit lane, the interval must fit Q
     assert D.fgemm_workspace_size(251, 64, 64, 64, D.GemmPlan(algo=D.GEMM_CMM)) == 0
     assert D.fgemm_workspace_size(3, 64, 64, 64, D.GemmPlan(algo=D.GEMM_CMM, interval=8192)) == 0
+
+
+def test_packed_side_sizes_add_up_to_the_workspace(D):
+    """Host logic of the resident-operand calls: the two packed sides are the two halves of the workspace."""
+    for p in (2, 3, 7, 13):
+        for (m, n, k) in ((1, 1, 1), (17, 130, 333), (1024, 1024, 1024), (64, 5, 4097)):
+            for plan in (None, D.GemmPlan(algo=D.GEMM_CMM), D.GemmPlan(algo=D.GEMM_PLAIN),
+                         D.GemmPlan(algo=D.GEMM_DOT4), D.GemmPlan(algo=D.GEMM_MFMA),
+                         D.GemmPlan(algo=D.GEMM_CMM, tile_rows=8)):
+                ws = D.fgemm_workspace_size(p, m, n, k, plan)
+                a = D.fgemm_packed_bytes(p, m, k, 0, plan)
+                b = D.fgemm_packed_bytes(p, n, k, 1, plan)
+                assert a + b == ws, (p, m, n, k, plan, a, b, ws)
+    assert D.fgemm_packed_bytes(3, 8, 8, 5, None) == 0
+    assert D.fgemm_packed_bytes(1, 8, 8, 0, None) == 0
+    lib = D.lib()
+    # null operand or packed buffer, bad side: refused before any launch
+    assert lib.dqt_fgemm_pack_side(3, 8, 8, None, 8, 0, None, None, None) == D.DQT_E_INVALID
+    assert lib.dqt_fgemm_pack_side(3, 8, 8, None, 8, 3, None, None, None) == D.DQT_E_INVALID
+    assert lib.dqt_fgemm_packed(3, 8, 8, 8, None, None, None, 8, None, None) == D.DQT_E_INVALID

@@ -115,3 +115,52 @@ def test_fgemm_workspace_errors(dqt):
                            ctypes.c_void_p(C.data_ptr()), 64, None, ctypes.c_void_p(small.data_ptr()), ws - 1,
                            _stream(None))
     assert st == dqt.DQT_E_WORKSPACE
+
+
+@pytest.mark.parametrize("p", [2, 3, 7])
+def test_fgemm_packed_operands_reused(dqt, p):
+    """A packed B kept in its own buffer times several packed A (different m, ragged), and one packed A
+    times two packed B: every product equals the oracle (section 7.1, reuse of compressed matrices)."""
+    g = np.random.default_rng(100 + p)
+    k, n = 333, 257
+    _, B = inputs.gemm_pair(1, n, k, p, seed=int(g.integers(1 << 30)))
+    dB = to_dev(B)
+    for plan in [None] + _all_algos(dqt):
+        CB = dqt.fgemm_pack_side(dB, p, 1, plan=plan)
+        assert CB.numel() == dqt.fgemm_packed_bytes(p, n, k, 1, plan)
+        for m in (1, 17, 130):
+            A, _ = inputs.gemm_pair(m, 1, k, p, seed=int(g.integers(1 << 30)))
+            dA = to_dev(A)
+            CA = dqt.fgemm_pack_side(dA, p, 0, plan=plan)
+            got = to_host(dqt.fgemm_packed(CA, CB, p, m, n, k, plan=plan))
+            assert (got == O.fgemm(A, B, p)).all(), (plan, m)
+            # the same packed A against a second B with fewer columns
+            _, B2 = inputs.gemm_pair(1, 65, k, p, seed=int(g.integers(1 << 30)))
+            CB2 = dqt.fgemm_pack_side(to_dev(B2), p, 1, plan=plan)
+            got2 = to_host(dqt.fgemm_packed(CA, CB2, p, m, 65, k, plan=plan))
+            assert (got2 == O.fgemm(A, B2, p)).all(), (plan, m)
+
+
+def test_fgemm_packed_argument_errors(dqt):
+    import torch
+    dA = to_dev(inputs.gemm_pair(8, 8, 8, 3)[0])
+    assert dqt.fgemm_packed_bytes(3, 8, 8, 2, None) == 0
+    with pytest.raises(dqt.DQTError):
+        dqt.fgemm_pack_side(dA, 3, 2)
+    CA = dqt.fgemm_pack_side(dA, 3, 0)
+    with pytest.raises(ValueError):
+        dqt.fgemm_pack_side(dA, 3, 0, out=torch.empty(4, dtype=torch.uint8, device=dA.device))
+    with pytest.raises(ValueError):
+        dqt.fgemm_packed(CA, CA, 3, 8, 8, 8, out=torch.empty((8, 9), dtype=torch.uint8, device=dA.device))
+
+
+def test_fgemm_call_object_matches(dqt):
+    """The prepared-argument launcher gives the same bytes as fgemm."""
+    import torch
+    A, B = inputs.gemm_pair(200, 300, 500, 5)
+    dA, dB = to_dev(A), to_dev(B)
+    C = torch.empty((200, 300), dtype=torch.uint8, device=dA.device)
+    call = dqt.FgemmCall(dA, dB, C, 5, plan=dqt.GemmPlan(algo=dqt.GEMM_CMM))
+    call.pack()
+    call.compute()
+    assert (to_host(C) == O.fgemm(A, B, 5)).all()

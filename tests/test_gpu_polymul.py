@@ -210,3 +210,23 @@ def test_fqt_long_products(dqt, p):
         w = inputs.worst_case((64, na), p)
         wb = inputs.worst_case((64, nb), p)
         assert (to_host(dqt.polymul_fqt_u8(to_dev(w), to_dev(wb), p)) == O.polymul(w, wb, p)).all()
+
+
+@pytest.mark.parametrize("p,k,n", [(3, 5, 1), (3, 5, 7), (7, 3, 1), (7, 3, 9), (7, 3, 10), (7, 3, 100), (3, 2, 1000),
+                                   (3, 2, 20000), (2, 6, 33), (5, 4, 17), (13, 3, 5)])
+def test_gf_dot_products(dqt, p, k, n):
+    """FGDP dot products: packed sums of n_q products, one REDQ and two lookups per word."""
+    P = inputs.irreducible(p, k)
+    g = np.random.default_rng(p * 100 + k * 10 + n)
+    count = 257 if n < 1000 else 17
+    a = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
+    b = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
+    ref = O.gf_dot(a, b, p, P)
+    try:
+        got = to_host(dqt.gf_dot_u8(to_dev(a), to_dev(b), p, P))
+    except dqt.DQTError as e:
+        assert e.status == dqt.DQT_E_UNSUPPORTED, e
+        return
+    assert (got == ref).all()
+    w = inputs.worst_case((5, n, k), p)
+    assert (to_host(dqt.gf_dot_u8(to_dev(w), to_dev(w), p, P)) == O.gf_dot(w, w, p, P)).all()

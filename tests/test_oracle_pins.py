@@ -403,3 +403,22 @@ def test_dqt_bounds_worked_cases():
     # GF(3^5) and GF(7^3) products
     assert O.dqt_bounds_ok(3, 5, 1, 5, 53) and O.dqt_bounds_ok(7, 3, 1, 7, 53)
     assert not O.dqt_bounds_ok(7, 3, 1, 6, 53)
+
+
+def test_gf_dot_pins():
+    """Dot products: n = 1 is the product; sums split at any point add up; pure-Python sums agree."""
+    for p, k in [(3, 5), (7, 3), (3, 2)]:
+        P = inputs.irreducible(p, k)
+        g = np.random.default_rng(p + k)
+        a = g.integers(0, p, size=(40, 9, k), dtype=np.uint8)
+        b = g.integers(0, p, size=(40, 9, k), dtype=np.uint8)
+        d = O.gf_dot(a, b, p, P)
+        assert (O.gf_dot(a[:, :1], b[:, :1], p, P) == O.gf_mul(a[:, 0], b[:, 0], p, P)).all()
+        d1, d2 = O.gf_dot(a[:, :4], b[:, :4], p, P), O.gf_dot(a[:, 4:], b[:, 4:], p, P)
+        assert (d == (d1.astype(int) + d2) % p).all()
+        for t in range(5):
+            acc = [0] * k
+            for l in range(9):
+                pr = O.gf_mul_py(a[t, l].tolist(), b[t, l].tolist(), p, P)
+                acc = [(x + y) % p for x, y in zip(acc, pr)]
+            assert d[t].tolist() == acc

@@ -11,7 +11,9 @@ Printed: one JSON line.  `value` is F_p Gop/s (2 m n k per step) of the
 packed path; `roofline` is the packed multiply kernel against the VALU issue
 rate; `cpu_baseline` is the CPU oracle on a bounded sample; `extra` holds the
 other measured paths (plain per-entry, dot4 and INT8 matrix-core comparators,
-one-word polynomial products and GF(p^k) products against HBM).
+one-word polynomial products and GF(p^k) products against HBM, the batched
+workload of 10,000 products in one graph replay, and the serving loop's
+latency percentiles).
 """
 from __future__ import annotations
 
@@ -28,6 +30,24 @@ METRIC = "F_p GEMM Gop/s + polymul/s, packed DQT+REDQ vs plain modular; p99 late
 PEAK_LANE_OPS = 256 * 64 * 2.4e9          # VALU lane-instructions per second (256 CUs, wave64, 2.4 GHz)
 PEAK_HBM = 8.0e12                          # bytes per second
 MNK = 1024
+EVENT_EVERY = 8                            # steps per kernel-timed step
+
+
+# HBM bytes per launch of the timed multiply kernel, from two rocprofv3 counter
+# runs (FETCH_SIZE, WRITE_SIZE; the summary and its commands are in profiles/),
+# valid only for the kernel sources they were taken on (their SHA-256).
+TRAFFIC_SOURCES = ("paper_0809_0063_amd/csrc/dqt_gemm.hip", "paper_0809_0063_amd/csrc/dqt_gemm_tile.h",
+                   "paper_0809_0063_amd/csrc/dqt_device.h")
+TRAFFIC = {"sha256": "e51d0c2ea2bc8e19101a1b56fdc6b1ebb6ab1513e84cc69cb3851472194d4f43", "bytes": 11697882}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -37,6 +57,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the comparator measurements")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the batched (10,000 products) and serving measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference kernel for counter scaling)")
     return ap.parse_args()
@@ -104,8 +126,11 @@ def main():
         wcall.compute()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps; events around the packed multiply kernel of every step
-    n_ev = args.steps
+    # timed region: K whole steps; the packed multiply kernel of every EVENT_EVERY-th step
+    # records its own start and end (a launch that records events costs the host more, so
+    # recording on every step would slow the steps it measures)
+    sampled = list(range(0, args.steps, EVENT_EVERY))
+    n_ev = len(sampled)
     ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
     ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
     t_start = torch.cuda.Event(enable_timing=True)
@@ -118,8 +143,11 @@ def main():
     t_start.record(stream)
     for i in range(args.steps):
         call.pack()
-        # the multiply kernel records its own start and end into ev_a[i], ev_b[i]
-        call.compute_timed(ev_a[i], ev_b[i])
+        if i % EVENT_EVERY == 0:
+            # the multiply kernel records its own start and end into the events
+            call.compute_timed(ev_a[i // EVENT_EVERY], ev_b[i // EVENT_EVERY])
+        else:
+            call.compute()
     t_end.record(stream)
     torch.cuda.synchronize()
     total_s = t_start.elapsed_time(t_end) / 1e3
@@ -143,9 +171,10 @@ def main():
         "peak": round(PEAK_LANE_OPS / 1e12, 3),
         "unit": "Tlane-op/s",
         "frac": round(achieved / PEAK_LANE_OPS, 4),
-        "traffic": None,
+        "traffic": TRAFFIC["bytes"] if TRAFFIC["sha256"] == kernel_sources_sha256() else None,
         "kernel": "k_gemm_words<DOT2> (packed multiply-accumulate + epilogue)",
         "kernel_us": round(kern_s * 1e6, 3),
+        "kernel_samples": n_ev,
         "fp_top_s": round(fp_ops / kern_s / 1e12, 2),
     }
 
@@ -196,6 +225,16 @@ def main():
                 extra[f"gf_{pp}^{k}_{name}"] = {"mul_s": round(n / s, 1), "GB_s": round(3 * k * n / s / 1e9, 1),
                                                "hbm_frac": round(3 * k * n / s / PEAK_HBM, 4)}
             del dx, dy, oz
+
+    if not args.no_extra and not args.no_workloads:
+        from paper_0809_0063_amd import workloads as W
+        for name, fn in (("batched_10000", lambda: W.batched(10000, replays=3)),
+                         ("serving", lambda: W.serving(n_requests=2000, warmup=200))):
+            try:
+                extra[name] = fn()
+            except Exception as e:  # reported in the output line, not hidden
+                extra[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu:

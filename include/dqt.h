@@ -211,9 +211,11 @@ typedef struct dqt_gemm_plan {
     uint32_t algo;          /* dqt_gemm_algo */
     uint32_t log2Q;         /* 0 = smallest allowed by eq:lower for the interval */
     uint32_t interval;      /* delayed-reduction interval in k (0 = whole kdim); multiple of 4 */
-    uint32_t tile_rows;     /* rows per wave (CMM/PLAIN: 8, 16 or 32; 0 = default) */
+    uint32_t tile_rows;     /* rows per wave (CMM/PLAIN/DOT4: 8, 16 or 32; 0 = default 8) */
     uint32_t ksplit;        /* waves splitting kdim inside a workgroup (1, 2, 4, 8; 0 = default) */
     uint32_t epilogue;      /* dqt_gemm_epilogue */
+    uint32_t tile_cols;     /* columns per lane of a wave (CMM/PLAIN/DOT4: 2 or 4; 0 = default 4; 4 needs
+                               tile_rows 8 or 16) */
 } dqt_gemm_plan;
 
 /*
@@ -227,8 +229,8 @@ size_t dqt_fgemm_workspace_size(uint32_t p, uint64_t m, uint64_t n, uint64_t kdi
  * CMM bounds (eq:lower with the interval in place of kdim): interval*(p-1)^2
  * < Q, and (p-1)(Q+1) < 2^16 so that a Kronecker pair fits a 16-bit lane of
  * the packed word.  d_work: device workspace of at least
- * dqt_fgemm_workspace_size(...) bytes (packed operands); its contents on
- * entry are ignored.
+ * dqt_fgemm_workspace_size(...) bytes (packed operands), 16-byte aligned
+ * (DQT_E_INVALID otherwise); its contents on entry are ignored.
  */
 dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t *d_A, uint64_t lda,
                      const uint8_t *d_B, uint64_t ldb, uint8_t *d_C, uint64_t ldc, const dqt_gemm_plan *plan,

@@ -121,6 +121,7 @@ static BatchLayout batch_layout(const dqt_gemm_desc* descs, uint32_t count, uint
         pl.log2Q = d.log2Q;
         pl.epilogue = d.epilogue;
         pl.tile_rows = tm;
+        pl.tile_cols = 2;
         pl.ksplit = s;
         if (d.algo == DQT_GEMM_MFMA || d.algo == DQT_GEMM_RIGHT) {
             *st = DQT_E_UNSUPPORTED;
@@ -251,6 +252,8 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
         pk.KW = R.KW;
         pk.b = R.b;
         pk.op = R.op;
+        pk.tm = R.tm;
+        pk.cbw = 64 * R.tn;
         pk.nba = (uint32_t)(((uint64_t)R.KW * R.m_pad + 255) / 256);
         bd.pack_blocks = pk.nba + (uint32_t)(((uint64_t)R.KW * R.n_pad + 255) / 256);
         prefix[i] = (uint32_t)blocks;

@@ -20,12 +20,18 @@
 // INT8 matrix cores (exact int32 accumulation while k (p-1)^2 < 2^31).
 //
 // Layout on the device (workspace, written by the pack kernel each call):
-//   CA: [KW][m_pad] uint32, k-major, so the words of 16 consecutive rows at one
-//       k-group are one 64-byte scalar load (rows are uniform across a wave).
-//   CB: [KW][n_pad] uint32, k-major, column words contiguous (coalesced).
-// Each wave owns TM rows (uniform, held in SGPRs) and 64*TN columns (one per
-// lane and per j); S waves of a workgroup split k and add their partial sums
-// through LDS before the epilogue.
+//   CA: [m_pad/TM][KW][TM] uint32: the words of the TM rows of a row block at
+//       consecutive k-groups are consecutive, so one unrolled step of the k
+//       loop reads them with scalar loads from one base address;
+//   CB: [n_pad/(64 TN)][KW][64 TN] uint32: the words of a column block at one
+//       k-group are consecutive, lane l of a wave holding columns
+//       l TN .. l TN + TN - 1 (one vector load per lane and k-group).
+// Each wave owns TM rows (uniform, held in SGPRs) and 64*TN columns; S waves
+// of a workgroup split k and add their partial sums through LDS before the
+// epilogue.  On this chip every instruction of the k loop other than the
+// dot product costs an issue slot of the SIMD, so the layouts exist to keep
+// the loop down to the dot products, one scalar and one vector load per
+// k-group and a pointer increment per unrolled step.
 
 #include <string.h>
 
@@ -61,10 +67,11 @@ __global__ __launch_bounds__(64 * S) void k_gemm_words(GemmArgs g) {
 __global__ __launch_bounds__(256) void k_gemm_pack(PackArgs a) { gemm_pack_block(a, blockIdx.x, threadIdx.x); }
 
 // Coalesced packing of the four-entry layouts when rows start on 4-byte
-// boundaries.  A: a workgroup packs a 64-row x 16-word tile of A through LDS
-// and writes it k-major.  B: a thread takes four
-// consecutive columns of one k-group (one dword from each of four rows) and
-// writes their four words.  Blocks [0, nta) pack A tiles, the rest pack B.
+// boundaries.  A: a workgroup packs a 64-row x 16-word tile of A (one dword
+// of a row per word) through LDS and writes it as the 64/TM row blocks of the
+// tile-major layout.  B: a thread takes four consecutive columns of one
+// k-group (one dword from each of four rows) and writes their four words.
+// Blocks [0, nta) pack A tiles, the rest pack B.
 struct Pack4Args {
     PackArgs a;
     uint32_t nta;           // A tiles
@@ -74,9 +81,6 @@ struct Pack4Args {
 __global__ __launch_bounds__(256) void k_gemm_pack4(Pack4Args pa) {
     const PackArgs& a = pa.a;
     if (blockIdx.x < pa.nta) {
-        // tile of 64 rows x 16 k-groups: each wave loads 16 rows as four
-        // 4-row x 64-byte segments, each thread packs one word, and the tile
-        // leaves k-major (each wave writes 4 k-groups of 64 consecutive rows)
         __shared__ uint32_t tile[16][65];
         const uint32_t tr = blockIdx.x % pa.tiles_m, tw = blockIdx.x / pa.tiles_m;
         const uint32_t r0 = tr * 64, w0 = tw * 16;
@@ -99,17 +103,21 @@ __global__ __launch_bounds__(256) void k_gemm_pack4(Pack4Args pa) {
                     for (uint32_t i = 0; i < 4; ++i)
                         if (4 * kw + i < a.kdim) e[i] = a.A[(size_t)row * a.lda + 4 * kw + i];
                 }
-                w = a.op == OP_DOT2 ? (((e[0] << a.b) | e[1]) | (((e[2] << a.b) | e[3]) << 16))
-                                    : (e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24));
+                w = pack_a_word(a.op, a.b, e);
             }
             tile[ww][rr] = w;
         }
         __syncthreads();
+        // out: row block s of the tile, k-group ww, row i: consecutive threads
+        // write consecutive words of one row block
+        const uint32_t rb0 = r0 / a.tm;
 #pragma unroll
         for (uint32_t it = 0; it < 4; ++it) {
-            const uint32_t ww = wave * 4 + it;
-            const uint32_t kw = w0 + ww, row = r0 + lane;
-            if (kw < a.KW && row < a.m_pad) a.CA[(size_t)kw * a.m_pad + row] = tile[ww][lane];
+            const uint32_t t = it * 256 + threadIdx.x;
+            const uint32_t i = t % a.tm, ww = (t / a.tm) % 16, sb = t / (16 * a.tm);
+            const uint32_t row = r0 + sb * a.tm + i, kw = w0 + ww;
+            if (kw < a.KW && row < a.m_pad)
+                a.CA[((size_t)(rb0 + sb) * a.KW + kw) * a.tm + i] = tile[ww][sb * a.tm + i];
         }
     } else {
         const uint64_t t = (uint64_t)(blockIdx.x - pa.nta) * 256 + threadIdx.x;
@@ -130,12 +138,12 @@ __global__ __launch_bounds__(256) void k_gemm_pack4(Pack4Args pa) {
         uint4 out;
         uint32_t* o = reinterpret_cast<uint32_t*>(&out);
         for (uint32_t j = 0; j < 4; ++j) {
-            const uint32_t e0 = (d[0] >> (8 * j)) & 0xFF, e1 = (d[1] >> (8 * j)) & 0xFF;
-            const uint32_t e2 = (d[2] >> (8 * j)) & 0xFF, e3 = (d[3] >> (8 * j)) & 0xFF;
-            o[j] = a.op == OP_DOT2 ? ((e0 | (e1 << a.b)) | ((e2 | (e3 << a.b)) << 16))
-                                   : (e0 | (e1 << 8) | (e2 << 16) | (e3 << 24));
+            const uint32_t e[4] = {(d[0] >> (8 * j)) & 0xFF, (d[1] >> (8 * j)) & 0xFF, (d[2] >> (8 * j)) & 0xFF,
+                                   (d[3] >> (8 * j)) & 0xFF};
+            o[j] = pack_b_word(a.op, a.b, e);
         }
-        *reinterpret_cast<uint4*>(a.CB + (size_t)kw * a.n_pad + c4) = out;
+        const uint32_t cb = c4 / a.cbw, c = c4 % a.cbw;
+        *reinterpret_cast<uint4*>(a.CB + ((size_t)cb * a.KW + kw) * a.cbw + c) = out;
     }
 }
 
@@ -308,9 +316,13 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
         default:
             return DQT_E_UNSUPPORTED;
     }
-    r->tm = pl.tile_rows ? pl.tile_rows : 16;
+    // Tile shape: fixed defaults (not derived from m or n), so that the packed
+    // layout of one operand never depends on the other operand's size.
+    r->tm = pl.tile_rows ? pl.tile_rows : 8;
+    r->tn = pl.tile_cols ? pl.tile_cols : 4;
     if (r->tm != 8 && r->tm != 16 && r->tm != 32) return DQT_E_INVALID;
-    r->tn = 2;
+    if (r->tn != 2 && r->tn != 4) return DQT_E_INVALID;
+    if (r->tm == 32 && r->tn == 4) return DQT_E_INVALID;
     const uint32_t epw = r->op == OP_MAD ? 1 : 4;
     r->KW = (uint32_t)((kdim + epw - 1) / epw);
     if (pl.ksplit) {
@@ -322,6 +334,9 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
         while (r->s < 8 && tiles * r->s < 4096 && (uint64_t)r->KW / (r->s * 2) >= 16) r->s *= 2;
     }
     if (r->s != 1 && r->s != 2 && r->s != 4 && r->s != 8) return DQT_E_INVALID;
+    // the split-k reduction buffer (s tm tn 64 words) stays within 64 KB of LDS
+    if (pl.ksplit && (uint64_t)r->s * r->tm * r->tn * 256 > 65536) return DQT_E_INVALID;
+    while ((uint64_t)r->s * r->tm * r->tn * 256 > 65536) r->s /= 2;
     // split-k boundaries must fall on interval boundaries of the packed path
     r->m_pad = (uint32_t)round_up(m ? m : 1, r->tm);
     r->n_pad = (uint32_t)round_up(n ? n : 1, 64 * r->tn);
@@ -334,46 +349,56 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
 // own start and end (dqt_fgemm_compute_timed); null for ordinary launches.
 static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
-template <int OP, int TM, int S, bool FLUSH, int EPI>
+template <int OP, int TM, int TN, int S, bool FLUSH, int EPI>
 static void launch_words_k(const GemmArgs& g, unsigned grid, hipStream_t s) {
     if (g_ev_start || g_ev_stop)
-        hipExtLaunchKernelGGL(k_gemm_words<OP, TM, 2, S, FLUSH, EPI>, dim3(grid), dim3(64 * S), 0, s, g_ev_start,
+        hipExtLaunchKernelGGL(k_gemm_words<OP, TM, TN, S, FLUSH, EPI>, dim3(grid), dim3(64 * S), 0, s, g_ev_start,
                               g_ev_stop, 0, g);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_words<OP, TM, 2, S, FLUSH, EPI>), dim3(grid), dim3(64 * S), 0, s, g);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_words<OP, TM, TN, S, FLUSH, EPI>), dim3(grid), dim3(64 * S), 0, s,
+                           g);
 }
 
-template <int OP, int TM, int S>
+template <int OP, int TM, int TN, int S>
 static void launch_words(const GemmArgs& g, unsigned grid, hipStream_t s) {
     if (OP == OP_DOT2) {
         if (g.lw) {
-            if (g.epi) launch_words_k<OP, TM, S, true, 1>(g, grid, s);
-            else launch_words_k<OP, TM, S, true, 0>(g, grid, s);
+            if (g.epi) launch_words_k<OP, TM, TN, S, true, 1>(g, grid, s);
+            else launch_words_k<OP, TM, TN, S, true, 0>(g, grid, s);
         } else {
-            if (g.epi) launch_words_k<OP, TM, S, false, 1>(g, grid, s);
-            else launch_words_k<OP, TM, S, false, 0>(g, grid, s);
+            if (g.epi) launch_words_k<OP, TM, TN, S, false, 1>(g, grid, s);
+            else launch_words_k<OP, TM, TN, S, false, 0>(g, grid, s);
         }
     } else {
-        launch_words_k<OP, TM, S, false, 0>(g, grid, s);
+        launch_words_k<OP, TM, TN, S, false, 0>(g, grid, s);
     }
 }
 
-template <int OP, int TM>
+template <int OP, int TM, int TN>
 static void launch_words_s(const GemmArgs& g, unsigned grid, uint32_t S_, hipStream_t s) {
     switch (S_) {
-        case 1: launch_words<OP, TM, 1>(g, grid, s); break;
-        case 2: launch_words<OP, TM, 2>(g, grid, s); break;
-        case 4: launch_words<OP, TM, 4>(g, grid, s); break;
-        default: launch_words<OP, TM, 8>(g, grid, s); break;
+        case 1: launch_words<OP, TM, TN, 1>(g, grid, s); break;
+        case 2: launch_words<OP, TM, TN, 2>(g, grid, s); break;
+        case 4: launch_words<OP, TM, TN, 4>(g, grid, s); break;
+        default:
+            // plans whose reduction buffer exceeds 64 KB are refused by resolve_plan
+            if constexpr (8 * TM * TN * 256 <= 65536) launch_words<OP, TM, TN, 8>(g, grid, s);
+            break;
     }
 }
 
+// (TM, TN) in {(8,2), (8,4), (16,2), (16,4), (32,2)} (checked by resolve_plan)
 template <int OP>
-static void launch_words_tm(const GemmArgs& g, unsigned grid, uint32_t tm, uint32_t S_, hipStream_t s) {
-    switch (tm) {
-        case 8: launch_words_s<OP, 8>(g, grid, S_, s); break;
-        case 16: launch_words_s<OP, 16>(g, grid, S_, s); break;
-        default: launch_words_s<OP, 32>(g, grid, S_, s); break;
+static void launch_words_tm(const GemmArgs& g, unsigned grid, uint32_t tm, uint32_t tn, uint32_t S_, hipStream_t s) {
+    if (tn == 4) {
+        if (tm == 8) launch_words_s<OP, 8, 4>(g, grid, S_, s);
+        else launch_words_s<OP, 16, 4>(g, grid, S_, s);
+    } else {
+        switch (tm) {
+            case 8: launch_words_s<OP, 8, 2>(g, grid, S_, s); break;
+            case 16: launch_words_s<OP, 16, 2>(g, grid, S_, s); break;
+            default: launch_words_s<OP, 32, 2>(g, grid, S_, s); break;
+        }
     }
 }
 
@@ -439,6 +464,8 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
     pa.KW = r.KW;
     pa.b = r.b;
     pa.op = r.op;
+    pa.tm = r.tm;
+    pa.cbw = 64 * r.tn;
     const bool a_al = !A || (((uintptr_t)A & 3) == 0 && (lda & 3) == 0);
     const bool b_al = !B || (((uintptr_t)B & 3) == 0 && (ldb & 3) == 0);
     if (r.op != OP_MAD && a_al && b_al && (r.n_pad & 3) == 0 && ((uintptr_t)work & 15) == 0) {
@@ -484,6 +511,11 @@ dqt_status fgemm_compute_enqueue2(uint32_t p, uint64_t m, uint64_t n, uint64_t k
         DQT_LAUNCH_CHECK("fgemm(mfma)");
         return DQT_OK;
     }
+    // the k loop reads B with 8- or 16-byte vector loads
+    if (((uintptr_t)pA & 15) || ((uintptr_t)pB & 15)) {
+        set_error("fgemm: packed operands (workspace) must be 16-byte aligned");
+        return DQT_E_INVALID;
+    }
     GemmArgs g;
     memset(&g, 0, sizeof(g));
     g.CA = reinterpret_cast<const uint32_t*>(pA);
@@ -509,9 +541,9 @@ dqt_status fgemm_compute_enqueue2(uint32_t p, uint64_t m, uint64_t n, uint64_t k
     DQT_TRY(fgemm_epilogue_args(p, kdim, r, &g));
     const unsigned grid = g.nrb * g.ncb;
     switch (r.op) {
-        case OP_DOT2: launch_words_tm<OP_DOT2>(g, grid, r.tm, r.s, s); break;
-        case OP_DOT4: launch_words_tm<OP_DOT4>(g, grid, r.tm, r.s, s); break;
-        default: launch_words_tm<OP_MAD>(g, grid, r.tm, r.s, s); break;
+        case OP_DOT2: launch_words_tm<OP_DOT2>(g, grid, r.tm, r.tn, r.s, s); break;
+        case OP_DOT4: launch_words_tm<OP_DOT4>(g, grid, r.tm, r.tn, r.s, s); break;
+        default: launch_words_tm<OP_MAD>(g, grid, r.tm, r.tn, r.s, s); break;
     }
     DQT_LAUNCH_CHECK("fgemm");
     return DQT_OK;
@@ -551,6 +583,7 @@ static dqt_status fgemm_common_checks(uint32_t p, uint64_t m, uint64_t n, uint64
                                       size_t work_bytes, const void* d_work, GemmPlanResolved* r) {
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, r));
     if (r->ws_bytes && (!d_work || work_bytes < r->ws_bytes)) return DQT_E_WORKSPACE;
+    if (r->ws_bytes && ((uintptr_t)d_work & 15)) return DQT_E_INVALID;
     return DQT_OK;
 }
 
@@ -620,7 +653,7 @@ extern "C" dqt_status dqt_fgemm_pack_side(uint32_t p, uint64_t rows_or_cols, uin
     GemmPlanResolved r;
     DQT_TRY(side_plan(p, rows_or_cols, kdim, side, plan, &r));
     if (rows_or_cols == 0) return DQT_OK;
-    if (!d_X || !d_packed) return DQT_E_INVALID;
+    if (!d_X || !d_packed || ((uintptr_t)d_packed & 15)) return DQT_E_INVALID;
     if ((side == 0 && ldx < kdim) || (side == 1 && ldx < rows_or_cols) || ldx > 0xFFFFFFFFull) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -640,6 +673,7 @@ extern "C" dqt_status dqt_fgemm_packed(uint32_t p, uint64_t m, uint64_t n, uint6
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
     if (m == 0 || n == 0) return DQT_OK;
     if (!d_CA || !d_CB || !d_C || ldc < n || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
+    if (((uintptr_t)d_CA & 15) || ((uintptr_t)d_CB & 15)) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     return fgemm_compute_enqueue2(p, m, n, kdim, d_C, ldc, r, d_CA, d_CB, reinterpret_cast<hipStream_t>(stream));
 }
@@ -654,6 +688,7 @@ extern "C" dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdi
     if (lda < kdim || ldb < n || ldc < n) return DQT_E_INVALID;
     if (lda > 0xFFFFFFFFull || ldb > 0xFFFFFFFFull || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
     if (r.ws_bytes && (!d_work || work_bytes < r.ws_bytes)) return DQT_E_WORKSPACE;
+    if (r.ws_bytes && ((uintptr_t)d_work & 15)) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     return fgemm_enqueue(p, m, n, kdim, d_A, lda, d_B, ldb, d_C, ldc, r, d_work, reinterpret_cast<hipStream_t>(stream));
 }

@@ -74,16 +74,53 @@ struct TileSmem {
     static constexpr int words = (S > 1) ? S * TM * TN * 64 : 1;
 };
 
+// Words of TN consecutive columns held by one lane (one vector load).
+template <int TN>
+struct LaneWords;
+template <>
+struct LaneWords<2> {
+    typedef uint2 T;
+    static __device__ __forceinline__ void get(const uint2& v, uint32_t (&o)[2]) {
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct LaneWords<4> {
+    typedef uint4 T;
+    static __device__ __forceinline__ void get(const uint4& v, uint32_t (&o)[4]) {
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+
+// k-groups per unrolled step: the A words of one step stay within 64 SGPRs.
+template <int TM>
+struct KUnroll {
+    static constexpr int value = TM <= 8 ? 8 : (TM == 16 ? 4 : 2);
+};
+
 // FLUSH = false: the whole k range of a wave is one delayed-reduction
 // interval (no intermediate extraction, no second accumulator).
 // EPI: 0 = one REDC per output, 1 = REDQ over gathered dot products (a
 // template parameter so that the REDC kernels keep no REDQ parameters in
 // SGPRs, which hold the prefetched words of A during the k loop).
+//
+// Packed layouts (tile-major, so that the operands of consecutive k-groups
+// are consecutive in memory and the loads of an unrolled step share one base
+// address with immediate offsets):
+//   CA: [m_pad / TM][KW][TM]          row block, k-group, row in the block;
+//   CB: [n_pad / (64 TN)][KW][64 TN]  column block, k-group, column in the
+//                                     block (lane l owns columns l TN .. l TN + TN - 1).
 template <int OP, int TM, int TN, int S, bool FLUSH, int EPI>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32_t cb, uint32_t wave, uint32_t lane,
                                           uint32_t* red) {
+    constexpr int U = KUnroll<TM>::value;
+    typedef typename LaneWords<TN>::T V;
     const uint32_t row0 = rb * TM;
-    const uint32_t col0 = cb * 64u * TN;
+    const uint32_t col0 = cb * 64u * TN + lane * TN;
 
     uint32_t acc[TM][TN];
     uint32_t wide[FLUSH ? TM : 1][FLUSH ? TN : 1];
@@ -98,34 +135,46 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
             for (int j = 0; j < TN; ++j) wide[FLUSH ? i : 0][FLUSH ? j : 0] = 0;
     }
 
-    const uint32_t kw0 = wave * g.kw_split;
+    const uint32_t kw0 = min(g.KW, wave * g.kw_split);
     const uint32_t kw1 = min(g.KW, kw0 + g.kw_split);
-    const uint32_t* __restrict__ pa = g.CA + row0;
-    const uint32_t* __restrict__ pb = g.CB + col0 + lane;
+    const uint32_t* __restrict__ pa = g.CA + ((size_t)rb * g.KW + kw0) * TM;
+    const V* __restrict__ pb = reinterpret_cast<const V*>(g.CB + ((size_t)cb * g.KW + kw0) * (64u * TN)) + lane;
     const uint32_t mask = (1u << g.b) - 1u;
 
-    auto body = [&](uint32_t kw) {
+    auto body = [&](int u) {
         uint32_t av[TM], bv[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) av[i] = pa[(size_t)kw * g.m_pad + i];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) bv[j] = pb[(size_t)kw * g.n_pad + 64 * j];
+        for (int i = 0; i < TM; ++i) av[i] = pa[u * TM + i];
+        LaneWords<TN>::get(pb[u * 64], bv);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) acc[i][j] = mac<OP>(av[i], bv[j], acc[i][j]);
     };
+    // n consecutive k-groups from (pa, pb), advancing both
+    auto run = [&](uint32_t n) {
+        uint32_t c = 0;
+        for (; c + U <= n; c += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) body(u);
+            pa += U * TM;
+            pb += U * 64;
+        }
+        for (; c < n; ++c) {
+            body(0);
+            pa += TM;
+            pb += 64;
+        }
+    };
 
+    const uint32_t nk = kw1 - kw0;
     if (!FLUSH) {
-#pragma unroll 8
-        for (uint32_t kw = kw0; kw < kw1; ++kw) body(kw);
+        run(nk);
     } else {
         // delayed-reduction interval in k-groups
-        const uint32_t step = g.lw ? g.lw : (kw1 > kw0 ? kw1 - kw0 : 1u);
-        for (uint32_t kc = kw0; kc < kw1; kc += step) {
-            const uint32_t ke = min(kw1, kc + step);
-#pragma unroll 4
-            for (uint32_t kw = kc; kw < ke; ++kw) body(kw);
+        const uint32_t step = g.lw ? g.lw : (nk ? nk : 1u);
+        for (uint32_t kc = 0; kc < nk; kc += step) {
+            run(min(step, nk - kc));
             // end of an interval: move the middle digit out
 #pragma unroll
             for (int i = 0; i < TM; ++i)
@@ -173,10 +222,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
             if (S > 1 && (uint32_t)i % S != wave) continue;
             const uint32_t row = row0 + i;
             if (row >= ge.m) continue;
+            uint8_t* out = ge.C + (size_t)row * ge.ldc + col0;
+            uint32_t v = 0;
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const uint32_t col = col0 + lane + 64 * j;
-                if (col < ge.n) ge.C[(size_t)row * ge.ldc + col] = (uint8_t)mod_u32(acc[i][j], ge.p, ge.pmagic);
+            for (int j = 0; j < TN; ++j) v |= mod_u32(acc[i][j], ge.p, ge.pmagic) << (8 * j);
+            if (col0 + TN <= ge.n && ((uintptr_t)out & (TN - 1)) == 0) {
+                if (TN == 4) *reinterpret_cast<uint32_t*>(out) = v;
+                else *reinterpret_cast<uint16_t*>(out) = (uint16_t)v;
+            } else {
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    if (col0 + j < ge.n) out[j] = (uint8_t)(v >> (8 * j));
             }
         }
     } else {
@@ -193,15 +249,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
             for (int j = 0; j < TN; ++j) {
                 word |= (uint64_t)acc[i][j] << (ra.b * nin);
                 rows[nin] = row0 + i;
-                cols[nin] = col0 + lane + 64 * j;
+                cols[nin] = col0 + j;
                 ++nin;
                 const bool last = (i + S > TM - 1) && j == TN - 1;
                 if (nin == ge.epi_e || last) {
-                    const uint64_t U = redq_compress(word, ra);
+                    const uint64_t U2 = redq_compress(word, ra);
                     for (uint32_t t = 0; t < nin; ++t) {
-                        const uint32_t ut = field(U, t, ra);
+                        const uint32_t ut = field(U2, t, ra);
                         uint32_t mu = ut;
-                        if (ra.c && t + 1 < nin) mu = correct_arith(ut, field(U, t + 1, ra), ra);
+                        if (ra.c && t + 1 < nin) mu = correct_arith(ut, field(U2, t + 1, ra), ra);
                         if (rows[t] < ge.m && cols[t] < ge.n) ge.C[(size_t)rows[t] * ge.ldc + cols[t]] = (uint8_t)mu;
                     }
                     word = 0;
@@ -212,7 +268,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
     }
 }
 
-// Pack one 256-word block of the operands of a product (A blocks first).
+// Pack one 256-word block of the operands of a product (A blocks first),
+// into the tile-major layouts above.
 struct PackArgs {
     const uint8_t* A;
     const uint8_t* B;
@@ -223,47 +280,52 @@ struct PackArgs {
     uint32_t b;       // log2 Q
     uint32_t op;      // GemmOp
     uint32_t nba;     // blocks for A
+    uint32_t tm;      // rows per row block of CA
+    uint32_t cbw;     // columns per column block of CB (64 TN)
 };
+
+__device__ __forceinline__ uint32_t pack_a_word(uint32_t op, uint32_t b, const uint32_t (&e)[4]) {
+    if (op == OP_DOT2) return ((e[0] << b) | e[1]) | (((e[2] << b) | e[3]) << 16);
+    if (op == OP_DOT4) return e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+    return e[0];
+}
+
+__device__ __forceinline__ uint32_t pack_b_word(uint32_t op, uint32_t b, const uint32_t (&e)[4]) {
+    if (op == OP_DOT2) return (e[0] | (e[1] << b)) | ((e[2] | (e[3] << b)) << 16);
+    if (op == OP_DOT4) return e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+    return e[0];
+}
 
 __device__ __forceinline__ void gemm_pack_block(const PackArgs& a, uint32_t blk, uint32_t tid) {
     const uint32_t epw = a.op == OP_MAD ? 1u : 4u;  // entries per word
     if (blk < a.nba) {
-        // CA[kw][row]: word index = kw * m_pad + row (rows fastest: coalesced stores)
+        // word index t = (rb KW + kw) tm + i (stores coalesced)
         const uint64_t t = (uint64_t)blk * 256 + tid;
         if (t >= (uint64_t)a.KW * a.m_pad) return;
-        const uint32_t kw = (uint32_t)(t / a.m_pad), row = (uint32_t)(t % a.m_pad);
+        const uint32_t i = (uint32_t)(t % a.tm);
+        const uint64_t q = t / a.tm;
+        const uint32_t kw = (uint32_t)(q % a.KW), row = (uint32_t)(q / a.KW) * a.tm + i;
         uint32_t e[4] = {0, 0, 0, 0};
         if (row < a.m)
-            for (uint32_t i = 0; i < epw; ++i) {
-                const uint32_t k = kw * epw + i;
-                if (k < a.kdim) e[i] = a.A[(size_t)row * a.lda + k];
+            for (uint32_t x = 0; x < epw; ++x) {
+                const uint32_t k = kw * epw + x;
+                if (k < a.kdim) e[x] = a.A[(size_t)row * a.lda + k];
             }
-        uint32_t w;
-        if (a.op == OP_DOT2)
-            w = ((e[0] << a.b) | e[1]) | (((e[2] << a.b) | e[3]) << 16);
-        else if (a.op == OP_DOT4)
-            w = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
-        else
-            w = e[0];
-        a.CA[t] = w;
+        a.CA[t] = pack_a_word(a.op, a.b, e);
     } else {
+        // word index t = (cb KW + kw) cbw + c
         const uint64_t t = (uint64_t)(blk - a.nba) * 256 + tid;
         if (t >= (uint64_t)a.KW * a.n_pad) return;
-        const uint32_t kw = (uint32_t)(t / a.n_pad), col = (uint32_t)(t % a.n_pad);
+        const uint32_t c = (uint32_t)(t % a.cbw);
+        const uint64_t q = t / a.cbw;
+        const uint32_t kw = (uint32_t)(q % a.KW), col = (uint32_t)(q / a.KW) * a.cbw + c;
         uint32_t e[4] = {0, 0, 0, 0};
         if (col < a.n)
-            for (uint32_t i = 0; i < epw; ++i) {
-                const uint32_t k = kw * epw + i;
-                if (k < a.kdim) e[i] = a.B[(size_t)k * a.ldb + col];
+            for (uint32_t x = 0; x < epw; ++x) {
+                const uint32_t k = kw * epw + x;
+                if (k < a.kdim) e[x] = a.B[(size_t)k * a.ldb + col];
             }
-        uint32_t w;
-        if (a.op == OP_DOT2)
-            w = (e[0] | (e[1] << a.b)) | ((e[2] | (e[3] << a.b)) << 16);
-        else if (a.op == OP_DOT4)
-            w = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
-        else
-            w = e[0];
-        a.CB[t] = w;
+        a.CB[t] = pack_b_word(a.op, a.b, e);
     }
 }
 

@@ -39,7 +39,8 @@ class _Qadic(ctypes.Structure):
 
 class _GemmPlan(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_uint32), ("log2Q", ctypes.c_uint32), ("interval", ctypes.c_uint32),
-                ("tile_rows", ctypes.c_uint32), ("ksplit", ctypes.c_uint32), ("epilogue", ctypes.c_uint32)]
+                ("tile_rows", ctypes.c_uint32), ("ksplit", ctypes.c_uint32), ("epilogue", ctypes.c_uint32),
+                ("tile_cols", ctypes.c_uint32)]
 
 
 class _GemmDesc(ctypes.Structure):
@@ -75,9 +76,11 @@ class GemmPlan:
     tile_rows: int = 0
     ksplit: int = 0
     epilogue: int = EPI_REDC
+    tile_cols: int = 0
 
     def _c(self) -> _GemmPlan:
-        return _GemmPlan(self.algo, self.log2Q, self.interval, self.tile_rows, self.ksplit, self.epilogue)
+        return _GemmPlan(self.algo, self.log2Q, self.interval, self.tile_rows, self.ksplit, self.epilogue,
+                         self.tile_cols)
 
 
 _lib = None

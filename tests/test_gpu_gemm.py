@@ -66,18 +66,21 @@ def test_fgemm_plans(dqt):
     A, B = inputs.gemm_pair(200, 300, 1000, p, seed=11)
     ref = O.fgemm(A, B, p)
     dA, dB = to_dev(A), to_dev(B)
-    for tm in (8, 16, 32):
+    for tm, tn in ((8, 2), (8, 4), (16, 2), (16, 4), (32, 2)):
         for ks in (1, 2, 4, 8):
-            if tm == 32 and ks == 8:
+            if ks * tm * tn * 256 > 65536:
+                with pytest.raises(dqt.DQTError):
+                    dqt.fgemm(dA, dB, p, plan=dqt.GemmPlan(algo=dqt.GEMM_CMM, tile_rows=tm, tile_cols=tn, ksplit=ks))
                 continue
             for interval in (0, 4, 64, 500, 508):
                 for epi in (dqt.EPI_REDC, dqt.EPI_REDQ):
-                    plan = dqt.GemmPlan(algo=dqt.GEMM_CMM, interval=interval, tile_rows=tm, ksplit=ks, epilogue=epi)
+                    plan = dqt.GemmPlan(algo=dqt.GEMM_CMM, interval=interval, tile_rows=tm, tile_cols=tn, ksplit=ks,
+                                        epilogue=epi)
                     got = to_host(dqt.fgemm(dA, dB, p, plan=plan))
                     assert (got == ref).all(), plan
             for algo in (dqt.GEMM_PLAIN, dqt.GEMM_DOT4):
-                got = to_host(dqt.fgemm(dA, dB, p, plan=dqt.GemmPlan(algo=algo, tile_rows=tm, ksplit=ks)))
-                assert (got == ref).all(), (algo, tm, ks)
+                got = to_host(dqt.fgemm(dA, dB, p, plan=dqt.GemmPlan(algo=algo, tile_rows=tm, tile_cols=tn, ksplit=ks)))
+                assert (got == ref).all(), (algo, tm, tn, ks)
 
 
 def test_fgemm_large_prime_routes_plain(dqt):
@@ -115,6 +118,12 @@ def test_fgemm_workspace_errors(dqt):
                            ctypes.c_void_p(C.data_ptr()), 64, None, ctypes.c_void_p(small.data_ptr()), ws - 1,
                            _stream(None))
     assert st == dqt.DQT_E_WORKSPACE
+    # a workspace that is not 16-byte aligned is refused before any launch
+    big = torch.zeros(ws + 64, dtype=torch.uint8, device=device())
+    st = _load().dqt_fgemm(3, 64, 64, 64, ctypes.c_void_p(A.data_ptr()), 64, ctypes.c_void_p(A.data_ptr()), 64,
+                           ctypes.c_void_p(C.data_ptr()), 64, None, ctypes.c_void_p(big.data_ptr() + 4), ws,
+                           _stream(None))
+    assert st == dqt.DQT_E_INVALID
 
 
 @pytest.mark.parametrize("p", [2, 3, 7])

@@ -191,7 +191,8 @@ def main():
     reps_big = max(2, args.steps // 20)
     if not args.no_extra:
         for name, algo in (("plain_mad", D.GEMM_PLAIN), ("plain_dot4", D.GEMM_DOT4), ("mfma_int8", D.GEMM_MFMA),
-                           ("cmm_redq_epilogue", None)):
+                           ("cmm_redq_epilogue", None), ("right_compressed_f64mfma", D.GEMM_RIGHT),
+                           ("left_compressed_f64mfma", D.GEMM_LEFT), ("full_compressed_f64mfma", D.GEMM_FULL)):
             pl = D.GemmPlan(algo=algo) if algo is not None else D.GemmPlan(algo=D.GEMM_CMM, epilogue=D.EPI_REDQ)
             w2 = torch.empty(max(1, D.fgemm_workspace_size(p, MNK, MNK, MNK, pl)), dtype=torch.uint8, device=dev)
             c2 = D.FgemmCall(dA, dB, dC, p, plan=pl, workspace=w2, stream=stream)

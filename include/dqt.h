@@ -199,7 +199,11 @@ typedef enum dqt_gemm_algo {
     DQT_GEMM_PLAIN = 2,     /* one entry per multiply-add, delayed REDC */
     DQT_GEMM_DOT4 = 3,      /* plain, four u8 entries per hardware dot instruction */
     DQT_GEMM_MFMA = 4,      /* plain, INT8 matrix cores, exact int32 accumulation */
-    DQT_GEMM_RIGHT = 5      /* right-compressed (section 7.4): A times row-packed B, REDQ per word */
+    DQT_GEMM_RIGHT = 5,     /* right compressed (section 7.4): e columns of B per binary64 word, A
+                               uncompressed, product on the FP64 matrix cores, one REDQ_e per word */
+    DQT_GEMM_LEFT = 6,      /* left compressed (section 7.4, the transpose): e rows of A per word */
+    DQT_GEMM_FULL = 7       /* full compression (section 7.5): 2 rows of A in powers of Q times e_c
+                               columns of B in powers of Theta = Q^2, 2 e_c digits per word */
 } dqt_gemm_algo;
 
 typedef enum dqt_gemm_epilogue {
@@ -226,6 +230,12 @@ size_t dqt_fgemm_workspace_size(uint32_t p, uint64_t m, uint64_t n, uint64_t kdi
 
 /*
  * F_p matrix product.  plan == NULL: DQT_GEMM_AUTO with defaults.
+ * RIGHT / LEFT / FULL: Q is the smallest power of two above kdim (p-1)^2
+ * (eq:lower) unless log2Q asks for a larger one, and a word holds
+ * floor(52 / log2 Q) digits (at most 8; eq:upper with one spare bit), so
+ * every product and partial sum is an integer below 2^52, exact in binary64;
+ * DQT_E_UNSUPPORTED when fewer than two digits fit (four for FULL).  ksplit
+ * applies; tile_rows, tile_cols, interval and epilogue are ignored.
  * CMM bounds (eq:lower with the interval in place of kdim): interval*(p-1)^2
  * < Q, and (p-1)(Q+1) < 2^16 so that a Kronecker pair fits a 16-bit lane of
  * the packed word.  d_work: device workspace of at least

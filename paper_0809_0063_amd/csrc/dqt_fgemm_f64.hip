@@ -1,0 +1,325 @@
+// Right, Left and Full compressed F_p matrix products on the FP64 matrix cores
+// (section 7.4 "Right or Left Compressed Matrix Multiplication" and section
+// 7.5 "Full Compression" of the paper).
+//
+// Right compression packs e consecutive columns of B into one word,
+// CB[l][j'] = sum_t B[l][e j' + t] Q^t, and multiplies the uncompressed A by
+// it: CC[i][j'] = sum_t (sum_l A[i][l] B[l][e j' + t]) Q^t, whose e digits are
+// the dot products of e outputs; one REDQ_e per word recovers all of them
+// (eq:LeftComp: A = Uncompress(CA); CC = A x CB; REDQ(CC)).  Left compression
+// is the transpose: e consecutive rows of A per word, B uncompressed.  Full
+// compression packs both: e_r rows of A in powers of Q and e_c columns of B in
+// powers of Theta = Q^(e_r) (eq:qtheta with equality), so that a word of CC
+// holds e_r e_c digits Q^(s + e_r t) (eq:dq).
+//
+// Exactness: every digit of CC is a dot product of length k bounded by
+// k (p-1)^2 < Q (eq:lower), so no digit carries, and the words stay below
+// Q^(e_r e_c) <= 2^52 (eq:upper with beta = 53 and one spare bit): every
+// product and every partial sum is an integer below 2^52, exact in binary64
+// in any order of summation, so the FP64 matrix cores compute CC exactly.
+//
+// On MI355X the FP64 matrix cores (v_mfma_f64_16x16x4_f64, 1024 multiply-adds
+// per instruction) issue far fewer instructions per multiply-add than the
+// vector units, and each multiply-add here carries e_r e_c F_p multiply-adds.
+//
+// Device layouts (workspace):
+//   Ad: [Mw_pad/16][K_pad/4][64] binary64, lane l of a 16x4 block holding
+//       word row l%16 at k = l/16 (the matrix-core A operand layout);
+//   Bd: [Nw_pad/16][K_pad/4][64] binary64, lane l holding k = l/16 of word
+//       column l%16 (the B operand layout).
+// The accumulator of a 16x16 block holds, in lane l and element r, word row
+// l/16 + 4r and word column l%16.
+
+#include <string.h>
+
+#include <hip/hip_ext.h>
+
+#include "dqt_gemm_tile.h"
+#include "dqt_internal.h"
+
+namespace dqt {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct F64Args {
+    const double* Ad;
+    const double* Bd;
+    uint8_t* C;
+    uint32_t m, n, ldc;
+    uint32_t nks;          // k-steps of 4 (K_pad / 4)
+    uint32_t ks_split;     // k-steps per wave
+    uint32_t nrb;          // row blocks of the grid (Mw_pad / (16 TR))
+    uint32_t er, ec;       // rows / columns per word
+    RedqArgs ra;           // REDQ_(er ec) of a word of CC
+};
+
+struct F64PackArgs {
+    const uint8_t* A;
+    const uint8_t* B;
+    double* Ad;
+    double* Bd;
+    uint32_t m, n, kdim, lda, ldb;
+    uint32_t nks;
+    uint64_t na;           // doubles of Ad
+    uint64_t nb;           // doubles of Bd
+    uint32_t er, ec, b;    // rows/columns per word, log2 Q
+};
+
+// Uncompress/compress the operands into the matrix-core layouts (one double
+// per thread, grid-stride).
+__global__ __launch_bounds__(256) void k_f64_pack(F64PackArgs a) {
+    const uint64_t total = a.na + a.nb;
+    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < total; t += (uint64_t)gridDim.x * 256) {
+        if (t < a.na) {
+            const uint32_t l = (uint32_t)(t & 63), ks = (uint32_t)((t >> 6) % a.nks);
+            const uint32_t rb = (uint32_t)((t >> 6) / a.nks);
+            const uint32_t iw = rb * 16 + (l & 15), k = ks * 4 + (l >> 4);
+            uint64_t w = 0;
+            if (k < a.kdim)
+                for (uint32_t s = 0; s < a.er; ++s) {
+                    const uint32_t row = iw * a.er + s;
+                    if (row < a.m) w |= (uint64_t)a.A[(size_t)row * a.lda + k] << (a.b * s);
+                }
+            a.Ad[t] = (double)w;
+        } else {
+            const uint64_t u = t - a.na;
+            const uint32_t l = (uint32_t)(u & 63), ks = (uint32_t)((u >> 6) % a.nks);
+            const uint32_t cb = (uint32_t)((u >> 6) / a.nks);
+            const uint32_t jw = cb * 16 + (l & 15), k = ks * 4 + (l >> 4);
+            uint64_t w = 0;
+            if (k < a.kdim)
+                for (uint32_t x = 0; x < a.ec; ++x) {
+                    const uint32_t col = jw * a.ec + x;
+                    if (col < a.n) w |= (uint64_t)a.B[(size_t)k * a.ldb + col] << (a.b * a.er * x);
+                }
+            a.Bd[u] = (double)w;
+        }
+    }
+}
+
+// One workgroup: KS waves on one block of 16 TR x 16 TC words, each wave a
+// range of k-steps; partial sums (exact) added through LDS; then REDQ of
+// every word and the bytes of its digits scattered to C.
+template <int TR, int TC, int KS>
+__global__ __launch_bounds__(64 * KS) void k_f64_mm(F64Args g) {
+    __shared__ double red[KS > 1 ? KS * TR * TC * 4 * 64 : 1];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    uint32_t bid = blockIdx.x, nblk = gridDim.x, logical = bid;
+    if ((nblk & 7u) == 0) logical = (bid & 7u) * (nblk >> 3) + (bid >> 3);
+    const uint32_t rb = logical % g.nrb, cb = logical / g.nrb;
+    const uint32_t ks0 = min(g.nks, wave * g.ks_split), ks1 = min(g.nks, ks0 + g.ks_split);
+
+    const double* pa[TR];
+    const double* pb[TC];
+#pragma unroll
+    for (int r = 0; r < TR; ++r) pa[r] = g.Ad + ((size_t)(rb * TR + r) * g.nks + ks0) * 64 + lane;
+#pragma unroll
+    for (int c = 0; c < TC; ++c) pb[c] = g.Bd + ((size_t)(cb * TC + c) * g.nks + ks0) * 64 + lane;
+    f64x4 acc[TR][TC];
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+#pragma unroll
+        for (int c = 0; c < TC; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    // operands of the next two k-steps are loaded while the current ones multiply
+    constexpr int PF = 2;
+    const uint32_t n = ks1 - ks0;
+    double fa[PF][TR], fb[PF][TC];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+#pragma unroll
+        for (int r = 0; r < TR; ++r) fa[u][r] = (u < (int)n) ? pa[r][u * 64] : 0.0;
+#pragma unroll
+        for (int c = 0; c < TC; ++c) fb[u][c] = (u < (int)n) ? pb[c][u * 64] : 0.0;
+    }
+    for (uint32_t s = 0; s < n; s += PF) {
+        double ca[PF][TR], cbv[PF][TC];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+#pragma unroll
+            for (int r = 0; r < TR; ++r) ca[u][r] = fa[u][r];
+#pragma unroll
+            for (int c = 0; c < TC; ++c) cbv[u][c] = fb[u][c];
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const uint32_t nx = s + PF + u;
+            if (nx < n) {
+#pragma unroll
+                for (int r = 0; r < TR; ++r) fa[u][r] = pa[r][(size_t)nx * 64];
+#pragma unroll
+                for (int c = 0; c < TC; ++c) fb[u][c] = pb[c][(size_t)nx * 64];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            if (s + u < n) {
+#pragma unroll
+                for (int r = 0; r < TR; ++r)
+#pragma unroll
+                    for (int c = 0; c < TC; ++c)
+                        acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u][r], cbv[u][c], acc[r][c], 0, 0, 0);
+            }
+        }
+    }
+
+    // split-k: wave w finishes the words q = w, w + KS, ... of its lane
+    constexpr int NQ = TR * TC * 4;
+    double v[NQ];
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+#pragma unroll
+        for (int c = 0; c < TC; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[(r * TC + c) * 4 + e] = acc[r][c][e];
+    if (KS > 1) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) red[(wave * NQ + q) * 64 + lane] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if ((uint32_t)q % KS != wave) continue;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < KS; ++w) sum += red[(w * NQ + q) * 64 + lane];
+            v[q] = sum;
+        }
+    }
+    const RedqArgs& ra = g.ra;
+    const uint32_t nd = g.er * g.ec;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (KS > 1 && (uint32_t)q % KS != wave) continue;
+        const int t = q / 4, e = q % 4;
+        const uint32_t iw = (rb * TR + t / TC) * 16 + (lane >> 4) + 4 * e;
+        const uint32_t jw = (cb * TC + t % TC) * 16 + (lane & 15u);
+        const uint64_t word = (uint64_t)v[q];   // an integer below 2^52
+        const uint64_t U = redq_compress(word, ra);
+        // digit d = s + er x (row s of the word's rows, column x of its columns)
+        uint32_t prev = field(U, 0, ra);
+        for (uint32_t d = 0; d < nd; ++d) {
+            const uint32_t next = d + 1 < nd ? field(U, d + 1, ra) : 0;
+            const uint32_t mu = (ra.c && d + 1 < nd) ? correct_arith(prev, next, ra) : prev;
+            prev = next;
+            const uint32_t row = iw * g.er + d % g.er, col = jw * g.ec + d / g.er;
+            if (row < g.m && col < g.n) g.C[(size_t)row * g.ldc + col] = (uint8_t)mu;
+        }
+    }
+}
+
+static uint64_t rup(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+// Plan of a compressed product on the matrix cores.  algo: DQT_GEMM_RIGHT
+// (er = 1), DQT_GEMM_LEFT (ec = 1), DQT_GEMM_FULL (both).  In the resolved
+// plan, m_pad / n_pad are the padded word rows / columns, k_pad the padded
+// inner dimension, tm / tn the 16x16 blocks per wave and s the k-split.
+dqt_status f64_plan(uint32_t algo, uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint32_t want_b,
+                    uint32_t want_ks, GemmPlanResolved* r) {
+    // smallest Q with kdim (p-1)^2 < Q (eq:lower); digits per word within 52 bits
+    const uint64_t bound = (kdim ? kdim : 1) * (uint64_t)(p - 1) * (p - 1);
+    uint32_t b = 1;
+    while (b < 52 && (1ull << b) <= bound) ++b;
+    if (want_b) {
+        if (want_b < b || want_b > 26) return DQT_E_BOUND;
+        b = want_b;
+    }
+    const uint32_t D = 52 / b;
+    if (D < 2) return DQT_E_UNSUPPORTED;   // not even two digits per word: no compression
+    switch (algo) {
+        case DQT_GEMM_RIGHT: r->er = 1; r->ec = D > 8 ? 8 : D; break;
+        case DQT_GEMM_LEFT: r->er = D > 8 ? 8 : D; r->ec = 1; break;
+        case DQT_GEMM_FULL:
+            if (D < 4) return DQT_E_UNSUPPORTED;   // two rows and two columns per word at least
+            r->er = 2;
+            r->ec = D / 2 > 4 ? 4 : D / 2;
+            break;
+        default: return DQT_E_UNSUPPORTED;
+    }
+    r->algo = algo;
+    r->b = b;
+    r->tm = 2;
+    r->tn = 2;
+    const uint64_t Mw = (m + r->er - 1) / r->er, Nw = (n + r->ec - 1) / r->ec;
+    r->m_pad = (uint32_t)rup(Mw ? Mw : 1, 16 * r->tm);
+    r->n_pad = (uint32_t)rup(Nw ? Nw : 1, 16 * r->tn);
+    const uint32_t nks = (uint32_t)((kdim + 3) / 4);
+    r->k_pad = 4 * (nks ? nks : 1);
+    if (want_ks) {
+        if (want_ks != 1 && want_ks != 2 && want_ks != 4 && want_ks != 8) return DQT_E_INVALID;
+        r->s = want_ks;
+    } else {
+        // enough waves for the chip: k split across up to 8 waves of a workgroup
+        const uint64_t blocks = (uint64_t)(r->m_pad / (16 * r->tm)) * (r->n_pad / (16 * r->tn));
+        r->s = 1;
+        while (r->s < 8 && blocks * r->s < 2048 && (r->k_pad / 4) / (r->s * 2) >= 8) r->s *= 2;
+    }
+    r->ws_bytes = ((size_t)r->m_pad + r->n_pad) * r->k_pad * sizeof(double);
+    return DQT_OK;
+}
+
+size_t f64_side_bytes(const GemmPlanResolved& r, int side) {
+    return (size_t)(side == 0 ? r.m_pad : r.n_pad) * r.k_pad * sizeof(double);
+}
+
+template <int KS>
+static void launch_f64_mm(const F64Args& g, unsigned grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(k_f64_mm<2, 2, KS>, dim3(grid), dim3(64 * KS), 0, s, e0, e1, 0, g);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_f64_mm<2, 2, KS>), dim3(grid), dim3(64 * KS), 0, s, g);
+}
+
+// Either operand may be NULL (its packed copy is kept).
+dqt_status f64_pack_enqueue(const GemmPlanResolved& r, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A,
+                            uint64_t lda, const uint8_t* B, uint64_t ldb, void* pA, void* pB, hipStream_t s) {
+    F64PackArgs a;
+    a.A = A;
+    a.B = B;
+    a.Ad = reinterpret_cast<double*>(pA);
+    a.Bd = reinterpret_cast<double*>(pB);
+    a.m = (uint32_t)m;
+    a.n = (uint32_t)n;
+    a.kdim = (uint32_t)kdim;
+    a.lda = (uint32_t)lda;
+    a.ldb = (uint32_t)ldb;
+    a.nks = r.k_pad / 4;
+    a.na = A ? (uint64_t)r.m_pad * r.k_pad : 0;
+    a.nb = B ? (uint64_t)r.n_pad * r.k_pad : 0;
+    a.er = r.er;
+    a.ec = r.ec;
+    a.b = r.b;
+    if (a.na + a.nb == 0) return DQT_OK;
+    hipLaunchKernelGGL(k_f64_pack, dim3(stream_grid(a.na + a.nb, 256, 8)), dim3(256), 0, s, a);
+    DQT_LAUNCH_CHECK("fgemm(f64 pack)");
+    return DQT_OK;
+}
+
+dqt_status f64_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t m, uint64_t n, uint8_t* C, uint64_t ldc,
+                               const void* pA, const void* pB, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    F64Args g;
+    memset(&g, 0, sizeof(g));
+    g.Ad = reinterpret_cast<const double*>(pA);
+    g.Bd = reinterpret_cast<const double*>(pB);
+    g.C = C;
+    g.m = (uint32_t)m;
+    g.n = (uint32_t)n;
+    g.ldc = (uint32_t)ldc;
+    g.nks = r.k_pad / 4;
+    g.ks_split = (g.nks + r.s - 1) / r.s;
+    g.nrb = r.m_pad / (16 * r.tm);
+    g.er = r.er;
+    g.ec = r.ec;
+    const uint32_t nd = r.er * r.ec;
+    DQT_TRY(make_redq_args(p, r.b, nd, nd * r.b, &g.ra));
+    const unsigned grid = g.nrb * (r.n_pad / (16 * r.tn));
+    switch (r.s) {
+        case 1: launch_f64_mm<1>(g, grid, s, e0, e1); break;
+        case 2: launch_f64_mm<2>(g, grid, s, e0, e1); break;
+        case 4: launch_f64_mm<4>(g, grid, s, e0, e1); break;
+        default: launch_f64_mm<8>(g, grid, s, e0, e1); break;
+    }
+    DQT_LAUNCH_CHECK("fgemm(f64)");
+    return DQT_OK;
+}
+
+}  // namespace dqt

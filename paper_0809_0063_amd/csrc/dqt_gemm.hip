@@ -281,6 +281,7 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
     if (p < 2 || p > 255) return DQT_E_INVALID;
     if (m > 0x7FFFFFFFull || n > 0x7FFFFFFFull || kdim > 0x7FFFFFFFull) return DQT_E_INVALID;
     uint32_t algo = pl.algo;
+    if (is_f64_algo(algo)) return f64_plan(algo, p, m, n, kdim, pl.log2Q, pl.ksplit, r);
     uint32_t b = 0, interval = 0;
     const bool cmm_ok = cmm_params(p, kdim, pl.interval, pl.log2Q, &b, &interval);
     if (algo == DQT_GEMM_AUTO) algo = cmm_ok ? DQT_GEMM_CMM : DQT_GEMM_PLAIN;
@@ -425,6 +426,9 @@ dqt_status fgemm_epilogue_args(uint32_t p, uint64_t kdim, const GemmPlanResolved
 // operand may be skipped by passing NULL, to reuse a packed one).
 dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A, uint64_t lda, const uint8_t* B,
                               uint64_t ldb, const GemmPlanResolved& r, void* work, hipStream_t s) {
+    if (is_f64_algo(r.algo))
+        return f64_pack_enqueue(r, m, n, kdim, A, lda, B, ldb, work,
+                                reinterpret_cast<uint8_t*>(work) + f64_side_bytes(r, 0), s);
     if (r.algo == DQT_GEMM_MFMA) {
         MfmaPackArgs pa;
         pa.A = A;
@@ -492,6 +496,13 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
 dqt_status fgemm_compute_enqueue2(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* C, uint64_t ldc,
                                   const GemmPlanResolved& r, const void* pA, const void* pB, hipStream_t s) {
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
+    if (is_f64_algo(r.algo)) {
+        if (((uintptr_t)pA & 15) || ((uintptr_t)pB & 15)) {
+            set_error("fgemm: packed operands (workspace) must be 16-byte aligned");
+            return DQT_E_INVALID;
+        }
+        return f64_compute_enqueue(r, p, m, n, C, ldc, pA, pB, s, g_ev_start, g_ev_stop);
+    }
     if (r.algo == DQT_GEMM_MFMA) {
         MfmaArgs g;
         g.A8 = reinterpret_cast<const uint8_t*>(pA);
@@ -552,7 +563,9 @@ dqt_status fgemm_compute_enqueue2(uint32_t p, uint64_t m, uint64_t n, uint64_t k
 dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t* C, uint64_t ldc,
                                  const GemmPlanResolved& r, const void* work, hipStream_t s) {
     const uint8_t* w = reinterpret_cast<const uint8_t*>(work);
-    const size_t a_bytes = r.algo == DQT_GEMM_MFMA ? (size_t)r.m_pad * r.k_pad : (size_t)r.KW * r.m_pad * 4;
+    const size_t a_bytes = is_f64_algo(r.algo)        ? f64_side_bytes(r, 0)
+                           : r.algo == DQT_GEMM_MFMA ? (size_t)r.m_pad * r.k_pad
+                                                     : (size_t)r.KW * r.m_pad * 4;
     return fgemm_compute_enqueue2(p, m, n, kdim, C, ldc, r, w, w + a_bytes, s);
 }
 
@@ -636,6 +649,7 @@ static dqt_status side_plan(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, in
 }
 
 static size_t side_bytes(const GemmPlanResolved& r, int side) {
+    if (is_f64_algo(r.algo)) return f64_side_bytes(r, side);
     if (r.algo == DQT_GEMM_MFMA) return (size_t)r.k_pad * (side == 0 ? r.m_pad : r.n_pad);
     return (size_t)r.KW * (side == 0 ? r.m_pad : r.n_pad) * sizeof(uint32_t);
 }

@@ -338,8 +338,20 @@ struct GemmPlanResolved {
     uint32_t tm, tn, s;
     uint32_t epi;
     uint32_t KW, m_pad, n_pad, k_pad;
+    uint32_t er, ec;    // rows / columns of the operands per word (matrix-core compressed products)
     size_t ws_bytes;
 };
+// Compressed products on the FP64 matrix cores (dqt_fgemm_f64.hip).
+dqt_status f64_plan(uint32_t algo, uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint32_t want_b,
+                    uint32_t want_ks, GemmPlanResolved* r);
+size_t f64_side_bytes(const GemmPlanResolved& r, int side);
+dqt_status f64_pack_enqueue(const GemmPlanResolved& r, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A,
+                            uint64_t lda, const uint8_t* B, uint64_t ldb, void* pA, void* pB, hipStream_t s);
+dqt_status f64_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t m, uint64_t n, uint8_t* C, uint64_t ldc,
+                               const void* pA, const void* pB, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+inline bool is_f64_algo(uint32_t algo) {
+    return algo == DQT_GEMM_RIGHT || algo == DQT_GEMM_LEFT || algo == DQT_GEMM_FULL;
+}
 dqt_status fgemm_resolve(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const dqt_gemm_plan* plan,
                          GemmPlanResolved* r);
 // Epilogue parameters (REDQ_e word layout) of a resolved plan.

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libdqt.so")
 
 DQT_OK, DQT_E_INVALID, DQT_E_BOUND, DQT_E_UNSUPPORTED, DQT_E_DEVICE, DQT_E_WORKSPACE = 0, -1, -2, -3, -4, -5
 
-GEMM_AUTO, GEMM_CMM, GEMM_PLAIN, GEMM_DOT4, GEMM_MFMA, GEMM_RIGHT = 0, 1, 2, 3, 4, 5
+GEMM_AUTO, GEMM_CMM, GEMM_PLAIN, GEMM_DOT4, GEMM_MFMA, GEMM_RIGHT, GEMM_LEFT, GEMM_FULL = 0, 1, 2, 3, 4, 5, 6, 7
 EPI_REDC, EPI_REDQ = 0, 1
 
 

@@ -112,7 +112,8 @@ def test_packed_side_sizes_add_up_to_the_workspace(D):
         for (m, n, k) in ((1, 1, 1), (17, 130, 333), (1024, 1024, 1024), (64, 5, 4097)):
             for plan in (None, D.GemmPlan(algo=D.GEMM_CMM), D.GemmPlan(algo=D.GEMM_PLAIN),
                          D.GemmPlan(algo=D.GEMM_DOT4), D.GemmPlan(algo=D.GEMM_MFMA),
-                         D.GemmPlan(algo=D.GEMM_CMM, tile_rows=8)):
+                         D.GemmPlan(algo=D.GEMM_CMM, tile_rows=8), D.GemmPlan(algo=D.GEMM_RIGHT),
+                         D.GemmPlan(algo=D.GEMM_LEFT), D.GemmPlan(algo=D.GEMM_FULL)):
                 ws = D.fgemm_workspace_size(p, m, n, k, plan)
                 a = D.fgemm_packed_bytes(p, m, k, 0, plan)
                 b = D.fgemm_packed_bytes(p, n, k, 1, plan)
@@ -124,3 +125,21 @@ def test_packed_side_sizes_add_up_to_the_workspace(D):
     assert lib.dqt_fgemm_pack_side(3, 8, 8, None, 8, 0, None, None, None) == D.DQT_E_INVALID
     assert lib.dqt_fgemm_pack_side(3, 8, 8, None, 8, 3, None, None, None) == D.DQT_E_INVALID
     assert lib.dqt_fgemm_packed(3, 8, 8, 8, None, None, None, 8, None, None) == D.DQT_E_INVALID
+
+
+def test_compressed_f64_plan_sizes(D):
+    """Matrix-core compressed products: digits per word from eq:lower and the 52-bit budget."""
+    # p = 3, k = 1024: Q = 2^13, four digits per word
+    m = n = k = 1024
+    ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_RIGHT))
+    assert ws == (1024 + 256) * 1024 * 8          # A uncompressed, B four columns per word
+    ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_LEFT))
+    assert ws == (256 + 1024) * 1024 * 8
+    ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_FULL))
+    assert ws == (512 + 512) * 1024 * 8           # two rows and two columns per word
+    # fewer than two digits per word: unsupported (size 0); FULL needs four
+    assert D.fgemm_workspace_size(251, 64, 64, 1 << 20, D.GemmPlan(algo=D.GEMM_RIGHT)) == 0
+    assert D.fgemm_workspace_size(13, 64, 64, 1024, D.GemmPlan(algo=D.GEMM_FULL)) == 0
+    assert D.fgemm_workspace_size(13, 64, 64, 1024, D.GemmPlan(algo=D.GEMM_RIGHT)) > 0
+    # a Q below the bound is refused
+    assert D.fgemm_workspace_size(3, 64, 64, 1024, D.GemmPlan(algo=D.GEMM_RIGHT, log2Q=12)) == 0

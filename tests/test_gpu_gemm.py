@@ -173,3 +173,87 @@ def test_fgemm_call_object_matches(dqt):
     call.pack()
     call.compute()
     assert (to_host(C) == O.fgemm(A, B, 5)).all()
+
+
+def _f64_digits(p, k):
+    """Digits per binary64 word of the matrix-core compressed products: floor(52 / log2 Q) with
+    Q the smallest power of two above k (p-1)^2 (eq:lower, eq:upper)."""
+    b = max(1, (k * (p - 1) ** 2).bit_length())
+    return 52 // b
+
+
+def _f64_plans(dqt, p, k):
+    d = _f64_digits(p, k)
+    out = []
+    if d >= 2:
+        out += [dqt.GemmPlan(algo=dqt.GEMM_RIGHT), dqt.GemmPlan(algo=dqt.GEMM_LEFT)]
+    if d >= 4:
+        out.append(dqt.GemmPlan(algo=dqt.GEMM_FULL))
+    return out
+
+
+def test_compressed_f64_1024_p3(dqt):
+    """Right, Left and Full compression on the FP64 matrix cores, 1024^3 over F_3, uniform and all-2."""
+    A, B = inputs.gemm_pair(1024, 1024, 1024, 3)
+    ref = O.fgemm(A, B, 3)
+    dA, dB = to_dev(A), to_dev(B)
+    plans = _f64_plans(dqt, 3, 1024)
+    assert len(plans) == 3
+    for plan in plans:
+        got = to_host(dqt.fgemm(dA, dB, 3, plan=plan))
+        assert (got == ref).all(), plan
+    W = to_dev(inputs.worst_case((1024, 1024), 3))
+    for plan in plans:
+        got = to_host(dqt.fgemm(W, W, 3, plan=plan))
+        assert (got == (1024 * 4) % 3).all(), plan
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 11, 13, 31, 251])
+def test_compressed_f64_ragged_and_bounds(dqt, p):
+    """Ragged shapes (rows or columns not a multiple of the words' e) and the worst case at inner
+    dimensions whose bound k (p-1)^2 sits just below and at a power of two."""
+    g = np.random.default_rng(500 + p)
+    for _ in range(6):
+        m, n, k = (int(x) for x in g.integers(1, 260, size=3))
+        A, B = inputs.gemm_pair(m, n, k, p, seed=int(g.integers(1 << 30)))
+        ref = O.fgemm(A, B, p)
+        dA, dB = to_dev(A), to_dev(B)
+        for plan in _f64_plans(dqt, p, k):
+            for ks in (0, 1, 8):
+                pl = dqt.GemmPlan(algo=plan.algo, ksplit=ks)
+                got = to_host(dqt.fgemm(dA, dB, p, plan=pl))
+                assert (got == ref).all(), (m, n, k, pl)
+    e2 = (p - 1) ** 2
+    for k in sorted({1, 3, 4, 5, max(1, (1 << 12) // e2), (1 << 12) // e2 + 1, 1023, 1024, 1025, 2048}):
+        A = to_dev(inputs.worst_case((37, k), p))
+        B = to_dev(inputs.worst_case((k, 70), p))
+        want = (k * e2) % p
+        plans = _f64_plans(dqt, p, k)
+        for plan in plans:
+            got = to_host(dqt.fgemm(A, B, p, plan=plan))
+            assert (got == want).all(), (p, k, plan)
+        if not plans:
+            with pytest.raises(dqt.DQTError) as e:
+                dqt.fgemm(A, B, p, plan=dqt.GemmPlan(algo=dqt.GEMM_RIGHT))
+            assert e.value.status == dqt.DQT_E_UNSUPPORTED
+
+
+def test_compressed_f64_larger_q_and_reuse(dqt):
+    """A larger Q than needed (log2Q) still gives the same bytes; packed sides reused."""
+    p, m, n, k = 5, 130, 257, 200
+    A, B = inputs.gemm_pair(m, n, k, p, seed=77)
+    ref = O.fgemm(A, B, p)
+    dA, dB = to_dev(A), to_dev(B)
+    for algo in (dqt.GEMM_RIGHT, dqt.GEMM_LEFT, dqt.GEMM_FULL):
+        for b in (0, 13):
+            plan = dqt.GemmPlan(algo=algo, log2Q=b)
+            assert (to_host(dqt.fgemm(dA, dB, p, plan=plan)) == ref).all(), plan
+        plan = dqt.GemmPlan(algo=algo)
+        CB = dqt.fgemm_pack_side(dB, p, 1, plan=plan)
+        for rows in (1, 64, 130):
+            CA = dqt.fgemm_pack_side(dA[:rows].contiguous(), p, 0, plan=plan)
+            got = to_host(dqt.fgemm_packed(CA, CB, p, rows, n, k, plan=plan))
+            assert (got == ref[:rows]).all(), (algo, rows)
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.fgemm(dA, dB, p, plan=dqt.GemmPlan(algo=dqt.GEMM_RIGHT, log2Q=5))   # below k (p-1)^2
+    assert e.value.status == dqt.DQT_E_BOUND

@@ -215,6 +215,21 @@ def main():
         s = timed_loop(lambda: D.polymul_u8(d65a, d65b, 3, out=o65, log2q=6), reps_gemm, 3, torch)
         extra["polymul_65536_packed"] = {"us_per_call": round(s * 1e6, 2), "polymul_s": round(65536 / s, 1)}
         del da, db, out
+        # long products by blocks (FQT): degree 47 over F_3, 2^20 products, schoolbook and Karatsuba blocks
+        nl = 1 << 20
+        al, bl = inputs.polymul_pairs(nl, 48, 3)
+        dal, dbl = torch.from_numpy(al).to(dev), torch.from_numpy(bl).to(dev)
+        ol = torch.empty((nl, 95), dtype=torch.uint8, device=dev)
+        for name, fn in (("fqt", lambda: D.polymul_fqt_u8(dal, dbl, 3, out=ol)),
+                         ("fqt_karatsuba1", lambda: D.polymul_fqt_kara_u8(dal, dbl, 3, levels=1, out=ol)),
+                         ("fqt_karatsuba2", lambda: D.polymul_fqt_kara_u8(dal, dbl, 3, levels=2, out=ol)),
+                         ("plain", lambda: D.polymul_plain_u8(dal, dbl, 3, out=ol))):
+            try:
+                s = timed_loop(fn, reps_big, 2, torch)
+                extra["polymul_deg47_f3_" + name] = {"polymul_s": round(nl / s, 1), "us_per_call": round(s * 1e6, 1)}
+            except D.DQTError as e:
+                extra["polymul_deg47_f3_" + name] = {"error": str(e)}
+        del dal, dbl, ol
         for (pp, k) in ((3, 5), (7, 3)):
             P = inputs.irreducible(pp, k)
             x, y = inputs.gf_pairs(n, k, pp)

@@ -186,6 +186,18 @@ dqt_status dqt_gf_mul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t 
 dqt_status dqt_polymul_fqt_u8(const uint8_t *d_a, uint32_t na, const uint8_t *d_b, uint32_t nb, uint64_t count,
                               uint32_t p, uint32_t block, uint8_t *d_out, void *stream);
 
+/*
+ * dqt_polymul_fqt_u8 with the block products by Karatsuba's recursion
+ * (`levels` = 1 or 2 levels, schoolbook below; the subquadratic FQT of
+ * section 5.3, figure fig:pmkara).  The recursion runs on the packed block
+ * words as integers modulo 2^64 (the evaluation at q is a ring morphism), so
+ * the output blocks, their REDQ and the bytes are those of
+ * dqt_polymul_fqt_u8.  Same arguments and errors; DQT_E_INVALID for another
+ * `levels`.
+ */
+dqt_status dqt_polymul_fqt_kara_u8(const uint8_t *d_a, uint32_t na, const uint8_t *d_b, uint32_t nb, uint64_t count,
+                                   uint32_t p, uint32_t block, uint32_t levels, uint8_t *d_out, void *stream);
+
 /* ---------------------------------------------------------------------------
  * F_p matrix product C = A.B mod p (section 7).
  * A: uint8 m x kdim, row-major, leading dimension lda >= kdim.

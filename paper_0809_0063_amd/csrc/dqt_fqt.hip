@@ -1,4 +1,6 @@
-// Long polynomial products by the FQT (section 5.2 of the paper).
+// Long polynomial products by the FQT (section 5.2 of the paper), with the
+// block products either schoolbook or by Karatsuba's recursion on the packed
+// block words (the subquadratic variant of figure fig:pmkara).
 //
 // A polynomial of degree < na is cut into blocks of BS = d+1 coefficients,
 // P = sum_i P_i Y^i with Y = X^BS, and each block is packed in one word at
@@ -81,6 +83,104 @@ __global__ __launch_bounds__(256) void k_polymul_fqt(const uint8_t* __restrict__
     }
 }
 
+// Karatsuba on polynomials (in Y = X^BS) whose coefficients are packed block
+// words.  The evaluation at q is a ring morphism, so the recursion can run on
+// the words as integers modulo 2^64: the middle term (a0 + a1)(b0 + b1) - a0 b0
+// - a1 b1 is, as an integer, exactly the packed word of a0 b1 + a1 b0, even
+// where the intermediate words wrap, and every final W_t equals the
+// schoolbook's sum of block products, below 2^53 with every digit below q.
+// LEV levels of recursion, schoolbook below.
+template <int N, int LEV>
+struct Kara {
+    static __device__ __forceinline__ void mul(const uint64_t* a, const uint64_t* b, uint64_t* r) {
+        if constexpr (LEV == 0 || N < 4) {
+#pragma unroll
+            for (int t = 0; t < 2 * N - 1; ++t) r[t] = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+                for (int j = 0; j < N; ++j) r[i + j] += a[i] * b[j];
+        } else {
+            constexpr int H = N / 2;       // low half; the high half has N - H >= H words
+            constexpr int G = N - H;
+            uint64_t r0[2 * H - 1], r2[2 * G - 1], m[2 * G - 1], sa[G], sb[G];
+            Kara<H, LEV - 1>::mul(a, b, r0);
+            Kara<G, LEV - 1>::mul(a + H, b + H, r2);
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                sa[i] = a[H + i] + (i < H ? a[i] : 0ull);
+                sb[i] = b[H + i] + (i < H ? b[i] : 0ull);
+            }
+            Kara<G, LEV - 1>::mul(sa, sb, m);
+#pragma unroll
+            for (int t = 0; t < 2 * G - 1; ++t) m[t] -= r2[t] + (t < 2 * H - 1 ? r0[t] : 0ull);
+#pragma unroll
+            for (int t = 0; t < 2 * N - 1; ++t) r[t] = 0;
+#pragma unroll
+            for (int t = 0; t < 2 * H - 1; ++t) r[t] += r0[t];
+#pragma unroll
+            for (int t = 0; t < 2 * G - 1; ++t) r[H + t] += m[t];
+#pragma unroll
+            for (int t = 0; t < 2 * G - 1; ++t) r[2 * H + t] += r2[t];
+        }
+    }
+};
+
+template <int BS, int MAXB, int LEV>
+__global__ __launch_bounds__(256) void k_polymul_fqt_kara(const uint8_t* __restrict__ A, uint32_t na,
+                                                          const uint8_t* __restrict__ B, uint32_t nb,
+                                                          uint8_t* __restrict__ OUT, uint64_t count, RedqArgs ra) {
+    constexpr int NR = 2 * BS - 1;
+    constexpr int NW = 2 * MAXB - 1;
+    __shared__ uint16_t tab[4096];
+    build_correction_table(tab, ra);
+    __syncthreads();
+    const uint32_t nout = na + nb - 1;
+    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < count; t += (uint64_t)gridDim.x * 256) {
+        const uint8_t* x = A + t * na;
+        const uint8_t* y = B + t * nb;
+        uint64_t aw[MAXB], bw[MAXB], W[NW];
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            uint64_t va = 0, vb = 0;
+#pragma unroll
+            for (int s = 0; s < BS; ++s) {
+                const uint32_t c = i * BS + s;
+                if (c < na) va |= (uint64_t)x[c] << (ra.b * s);
+                if (c < nb) vb |= (uint64_t)y[c] << (ra.b * s);
+            }
+            aw[i] = va;
+            bw[i] = vb;
+        }
+        Kara<MAXB, LEV>::mul(aw, bw, W);
+        uint8_t* z = OUT + t * nout;
+        uint32_t carry[BS > 1 ? BS - 1 : 1];
+#pragma unroll
+        for (int s = 0; s < BS - 1; ++s) carry[s] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if ((uint32_t)(BS * w) >= nout) break;
+            const uint64_t U = redq_compress(W[w], ra);
+            uint32_t mu[NR];
+            redq_correct<NR>(U, ra, tab, [&](int s, uint32_t v) { mu[s] = v; });
+#pragma unroll
+            for (int s = 0; s < BS; ++s) {
+                uint32_t v = mu[s] + (s < BS - 1 ? carry[s] : 0u);
+                v = v >= ra.p ? v - ra.p : v;
+                const uint32_t pos = BS * w + s;
+                if (pos < nout) z[pos] = (uint8_t)v;
+            }
+#pragma unroll
+            for (int s = 0; s < BS - 1; ++s) carry[s] = mu[BS + s];
+        }
+#pragma unroll
+        for (int s = 0; s < BS - 1; ++s) {
+            const uint32_t pos = BS * NW + s;
+            if (pos < nout) z[pos] = (uint8_t)carry[s];
+        }
+    }
+}
+
 // Cost of one product with block size bs (block multiplies + REDQ words),
 // the time-memory trade-off model of table tab:mulpol with a REDQ priced at
 // about 40 machine operations.
@@ -120,14 +220,24 @@ static void launch_fqt_b(uint32_t maxb, const uint8_t* A, uint32_t na, const uin
     else launch_fqt<BS, 16>(A, na, B, nb, out, count, ra, s);
 }
 
-}  // namespace dqt
+template <int BS, int LEV>
+static void launch_kara_b(uint32_t maxb, const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint8_t* out,
+                          uint64_t count, const RedqArgs& ra, hipStream_t s) {
+    const dim3 grid(stream_grid(count, 256)), blk(256);
+    if (maxb <= 4) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 4, LEV>), grid, blk, 0, s, A, na, B, nb, out, count, ra);
+    else if (maxb <= 8) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 8, LEV>), grid, blk, 0, s, A, na, B, nb, out, count, ra);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 16, LEV>), grid, blk, 0, s, A, na, B, nb, out, count, ra);
+}
 
-using namespace dqt;
+template <int BS>
+static void launch_kara(uint32_t levels, uint32_t maxb, const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb,
+                        uint8_t* out, uint64_t count, const RedqArgs& ra, hipStream_t s) {
+    if (levels == 1) launch_kara_b<BS, 1>(maxb, A, na, B, nb, out, count, ra, s);
+    else launch_kara_b<BS, 2>(maxb, A, na, B, nb, out, count, ra, s);
+}
 
-extern "C" dqt_status dqt_polymul_fqt_u8(const uint8_t* d_a, uint32_t na, const uint8_t* d_b, uint32_t nb,
-                                         uint64_t count, uint32_t p, uint32_t block, uint8_t* d_out, void* stream) {
-    if (p < 2 || p > 255 || na < 1 || nb < 1 || na > 64 || nb > 64) return DQT_E_INVALID;
-    // choose the block size (2..6) and q
+// Block size and q of a product (shared by both entry points).
+static dqt_status fqt_choose(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out) {
     uint32_t best_bs = 0, best_b = 0;
     double best = 1e300;
     for (uint32_t bs = 2; bs <= 6; ++bs) {
@@ -144,6 +254,46 @@ extern "C" dqt_status dqt_polymul_fqt_u8(const uint8_t* d_a, uint32_t na, const 
         }
     }
     if (!best_bs) return block ? DQT_E_BOUND : DQT_E_UNSUPPORTED;
+    *bs_out = best_bs;
+    *b_out = best_b;
+    return DQT_OK;
+}
+
+}  // namespace dqt
+
+using namespace dqt;
+
+extern "C" dqt_status dqt_polymul_fqt_kara_u8(const uint8_t* d_a, uint32_t na, const uint8_t* d_b, uint32_t nb,
+                                              uint64_t count, uint32_t p, uint32_t block, uint32_t levels,
+                                              uint8_t* d_out, void* stream) {
+    if (p < 2 || p > 255 || na < 1 || nb < 1 || na > 64 || nb > 64) return DQT_E_INVALID;
+    if (levels < 1 || levels > 2) return DQT_E_INVALID;
+    uint32_t bs = 0, b = 0;
+    DQT_TRY(fqt_choose(p, na, nb, block, &bs, &b));
+    RedqArgs ra;
+    DQT_TRY(make_redq_args(p, b, 2 * bs - 1, (2 * bs - 1) * b, &ra));
+    if (count == 0) return DQT_OK;
+    if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
+    DQT_TRY(ensure_device_ready());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs;
+    const uint32_t maxb = Na > Nb ? Na : Nb;
+    switch (bs) {
+        case 2: launch_kara<2>(levels, maxb, d_a, na, d_b, nb, d_out, count, ra, s); break;
+        case 3: launch_kara<3>(levels, maxb, d_a, na, d_b, nb, d_out, count, ra, s); break;
+        case 4: launch_kara<4>(levels, maxb, d_a, na, d_b, nb, d_out, count, ra, s); break;
+        case 5: launch_kara<5>(levels, maxb, d_a, na, d_b, nb, d_out, count, ra, s); break;
+        default: launch_kara<6>(levels, maxb, d_a, na, d_b, nb, d_out, count, ra, s); break;
+    }
+    DQT_LAUNCH_CHECK("dqt_polymul_fqt_kara_u8");
+    return DQT_OK;
+}
+
+extern "C" dqt_status dqt_polymul_fqt_u8(const uint8_t* d_a, uint32_t na, const uint8_t* d_b, uint32_t nb,
+                                         uint64_t count, uint32_t p, uint32_t block, uint8_t* d_out, void* stream) {
+    if (p < 2 || p > 255 || na < 1 || nb < 1 || na > 64 || nb > 64) return DQT_E_INVALID;
+    uint32_t best_bs = 0, best_b = 0;
+    DQT_TRY(fqt_choose(p, na, nb, block, &best_bs, &best_b));
     RedqArgs ra;
     DQT_TRY(make_redq_args(p, best_b, 2 * best_bs - 1, (2 * best_bs - 1) * best_b, &ra));
     if (count == 0) return DQT_OK;

@@ -108,6 +108,7 @@ def _load():
         "dqt_gf_mul_plain_u8": [V, V, U64, U32, U32, V, V, V],
         "dqt_gf_dot_u8": [V, V, U64, U32, U32, U32, V, V, V],
         "dqt_polymul_fqt_u8": [V, U32, V, U32, U64, U32, U32, V, V],
+        "dqt_polymul_fqt_kara_u8": [V, U32, V, U32, U64, U32, U32, U32, V, V],
         "dqt_fgemm": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V],
         "dqt_fgemm_batched_prepare": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V,
@@ -282,6 +283,20 @@ def polymul_fqt_u8(a: torch.Tensor, b: torch.Tensor, p: int, block: int = 0, out
         out = torch.empty((n, na + nb - 1), dtype=torch.uint8, device=a.device)
     _check(_load().dqt_polymul_fqt_u8(_dev(a, "a", torch.uint8), na, _dev(b, "b", torch.uint8), nb, n, p, block,
                                       _dev(out, "out", torch.uint8), _stream(stream)), "dqt_polymul_fqt_u8")
+    return out
+
+
+def polymul_fqt_kara_u8(a: torch.Tensor, b: torch.Tensor, p: int, levels: int = 1, block: int = 0,
+                        out: Optional[torch.Tensor] = None, stream=None):
+    """FQT products with Karatsuba block products (levels 1 or 2): same shapes and bytes as polymul_fqt_u8."""
+    _u8_pair(a, b)
+    n, na = a.shape
+    nb = b.shape[1]
+    if out is None:
+        out = torch.empty((n, na + nb - 1), dtype=torch.uint8, device=a.device)
+    _check(_load().dqt_polymul_fqt_kara_u8(_dev(a, "a", torch.uint8), na, _dev(b, "b", torch.uint8), nb, n, p, block,
+                                           levels, _dev(out, "out", torch.uint8), _stream(stream)),
+           "dqt_polymul_fqt_kara_u8")
     return out
 
 

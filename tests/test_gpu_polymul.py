@@ -212,6 +212,41 @@ def test_fqt_long_products(dqt, p):
         assert (to_host(dqt.polymul_fqt_u8(to_dev(w), to_dev(wb), p)) == O.polymul(w, wb, p)).all()
 
 
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 11])
+def test_fqt_karatsuba_products(dqt, p):
+    """Karatsuba block products (1 and 2 levels) give the oracle's bytes, also for unequal lengths,
+    every admissible block size and the all-(p-1) worst case (digits at their bound)."""
+    ran = 0
+    for na, nb in [(3, 3), (8, 8), (16, 16), (5, 13), (16, 2), (1, 9), (32, 32), (20, 7), (48, 48), (45, 31)]:
+        a, b = inputs.polymul_pairs(257, na, p, seed=na * 31 + nb, kb=nb)
+        ref = O.polymul(a, b, p)
+        da, db = to_dev(a), to_dev(b)
+        for levels in (1, 2):
+            for block in (0, 2, 3, 4, 5, 6):
+                try:
+                    got = to_host(dqt.polymul_fqt_kara_u8(da, db, p, levels=levels, block=block))
+                except dqt.DQTError as e:
+                    # refused exactly when the schoolbook FQT refuses (same block and q choice)
+                    assert e.status in (dqt.DQT_E_BOUND, dqt.DQT_E_UNSUPPORTED), e
+                    with pytest.raises(dqt.DQTError) as e2:
+                        dqt.polymul_fqt_u8(da, db, p, block=block)
+                    assert e2.value.status == e.status
+                    continue
+                assert (got == ref).all(), (p, na, nb, levels, block)
+                ran += 1
+        w, wb = inputs.worst_case((64, na), p), inputs.worst_case((64, nb), p)
+        want = O.polymul(w, wb, p)
+        for levels in (1, 2):
+            try:
+                got = to_host(dqt.polymul_fqt_kara_u8(to_dev(w), to_dev(wb), p, levels=levels))
+            except dqt.DQTError:
+                continue
+            assert (got == want).all(), (p, na, nb, levels)
+    assert ran >= 40
+    with pytest.raises(dqt.DQTError):
+        dqt.polymul_fqt_kara_u8(da, db, p, levels=3)
+
+
 @pytest.mark.parametrize("p,k,n", [(3, 5, 1), (3, 5, 7), (7, 3, 1), (7, 3, 9), (7, 3, 10), (7, 3, 100), (3, 2, 1000),
                                    (3, 2, 20000), (2, 6, 33), (5, 4, 17), (13, 3, 5)])
 def test_gf_dot_products(dqt, p, k, n):

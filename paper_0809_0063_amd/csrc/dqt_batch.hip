@@ -254,8 +254,10 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
         pk.op = R.op;
         pk.tm = R.tm;
         pk.cbw = 64 * R.tn;
-        pk.nba = (uint32_t)(((uint64_t)R.KW * R.m_pad + 255) / 256);
-        bd.pack_blocks = pk.nba + (uint32_t)(((uint64_t)R.KW * R.n_pad + 255) / 256);
+        pk.al = ((((uintptr_t)d.A & 3) == 0 && (d.lda & 3) == 0) ? 1u : 0u) |
+                ((((uintptr_t)d.B & 3) == 0 && (d.ldb & 3) == 0) ? 2u : 0u);
+        pk.nba = pack_blocks_for((uint64_t)R.KW * R.m_pad, R.op);
+        bd.pack_blocks = pk.nba + pack_blocks_for((uint64_t)R.KW * R.n_pad, R.op);
         prefix[i] = (uint32_t)blocks;
         blocks += bd.pack_blocks;
     }

@@ -483,9 +483,11 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
         DQT_LAUNCH_CHECK("fgemm(pack4)");
         return DQT_OK;
     }
-    const uint32_t nba = A ? (uint32_t)(((uint64_t)r.KW * r.m_pad + 255) / 256) : 0;
-    const uint32_t nbb = B ? (uint32_t)(((uint64_t)r.KW * r.n_pad + 255) / 256) : 0;
+    const uint32_t nba = A ? pack_blocks_for((uint64_t)r.KW * r.m_pad, r.op) : 0;
+    const uint32_t nbb = B ? pack_blocks_for((uint64_t)r.KW * r.n_pad, r.op) : 0;
     pa.nba = nba;
+    pa.al = (a_al ? 1u : 0u) | (b_al ? 2u : 0u);
+    if (r.op != OP_MAD && ((uintptr_t)work & 15)) return DQT_E_INVALID;   // 16-byte stores
     if (nba + nbb == 0) return DQT_OK;
     hipLaunchKernelGGL(k_gemm_pack, dim3(nba + nbb), dim3(256), 0, s, pa);
     DQT_LAUNCH_CHECK("fgemm(pack)");

@@ -282,7 +282,16 @@ struct PackArgs {
     uint32_t nba;     // blocks for A
     uint32_t tm;      // rows per row block of CA
     uint32_t cbw;     // columns per column block of CB (64 TN)
+    uint32_t al;      // bit 0: A and lda 4-byte aligned; bit 1: B and ldb 4-byte aligned
 };
+
+// Words packed per thread: four (one 16-byte store) for the four-entry
+// layouts, one for the one-entry layout.
+__host__ __device__ inline uint32_t pack_words_per_thread(uint32_t op) { return op == OP_MAD ? 1u : 4u; }
+__host__ __device__ inline uint32_t pack_blocks_for(uint64_t words, uint32_t op) {
+    const uint64_t per_block = 256ull * pack_words_per_thread(op);
+    return (uint32_t)((words + per_block - 1) / per_block);
+}
 
 __device__ __forceinline__ uint32_t pack_a_word(uint32_t op, uint32_t b, const uint32_t (&e)[4]) {
     if (op == OP_DOT2) return ((e[0] << b) | e[1]) | (((e[2] << b) | e[3]) << 16);
@@ -296,8 +305,65 @@ __device__ __forceinline__ uint32_t pack_b_word(uint32_t op, uint32_t b, const u
     return e[0];
 }
 
+// Four entries (one k-group) of a row of A, or of four rows of B at one column
+// group, as dwords: whole-dword loads when aligned and inside the matrix.
+__device__ __forceinline__ uint32_t row_group(const uint8_t* p, uint32_t k0, uint32_t kdim, bool aligned) {
+    if (aligned && k0 + 3 < kdim) return *reinterpret_cast<const uint32_t*>(p + k0);
+    uint32_t d = 0;
+    for (uint32_t x = 0; x < 4; ++x)
+        if (k0 + x < kdim) d |= (uint32_t)p[k0 + x] << (8 * x);
+    return d;
+}
+
+__device__ __forceinline__ void gemm_pack_block4(const PackArgs& a, uint32_t blk, uint32_t tid) {
+    if (blk < a.nba) {
+        // words w0 .. w0+3 of CA: rows i0 .. i0+3 of row block rb at k-group kw
+        const uint64_t w0 = ((uint64_t)blk * 256 + tid) * 4;
+        if (w0 >= (uint64_t)a.KW * a.m_pad) return;
+        const uint32_t i0 = (uint32_t)(w0 % a.tm);
+        const uint64_t q = w0 / a.tm;
+        const uint32_t kw = (uint32_t)(q % a.KW), row0 = (uint32_t)(q / a.KW) * a.tm + i0;
+        uint4 out;
+        uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+        for (uint32_t x = 0; x < 4; ++x) {
+            const uint32_t row = row0 + x;
+            const uint32_t d = row < a.m ? row_group(a.A + (size_t)row * a.lda, 4 * kw, a.kdim, a.al & 1u) : 0u;
+            const uint32_t e[4] = {d & 0xFF, (d >> 8) & 0xFF, (d >> 16) & 0xFF, d >> 24};
+            o[x] = pack_a_word(a.op, a.b, e);
+        }
+        *reinterpret_cast<uint4*>(a.CA + w0) = out;
+    } else {
+        // words w0 .. w0+3 of CB: columns c0 .. c0+3 of column block cb at k-group kw
+        const uint64_t w0 = ((uint64_t)(blk - a.nba) * 256 + tid) * 4;
+        if (w0 >= (uint64_t)a.KW * a.n_pad) return;
+        const uint32_t c0 = (uint32_t)(w0 % a.cbw);
+        const uint64_t q = w0 / a.cbw;
+        const uint32_t kw = (uint32_t)(q % a.KW), col0 = (uint32_t)(q / a.KW) * a.cbw + c0;
+        uint32_t d[4];
+#pragma unroll
+        for (uint32_t x = 0; x < 4; ++x) {
+            const uint32_t k = 4 * kw + x;
+            d[x] = k < a.kdim ? row_group(a.B + (size_t)k * a.ldb, col0, a.n, a.al & 2u) : 0u;
+        }
+        uint4 out;
+        uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t e[4] = {(d[0] >> (8 * j)) & 0xFF, (d[1] >> (8 * j)) & 0xFF, (d[2] >> (8 * j)) & 0xFF,
+                                   (d[3] >> (8 * j)) & 0xFF};
+            o[j] = pack_b_word(a.op, a.b, e);
+        }
+        *reinterpret_cast<uint4*>(a.CB + w0) = out;
+    }
+}
+
 __device__ __forceinline__ void gemm_pack_block(const PackArgs& a, uint32_t blk, uint32_t tid) {
     const uint32_t epw = a.op == OP_MAD ? 1u : 4u;  // entries per word
+    if (epw == 4) {
+        gemm_pack_block4(a, blk, tid);
+        return;
+    }
     if (blk < a.nba) {
         // word index t = (rb KW + kw) tm + i (stores coalesced)
         const uint64_t t = (uint64_t)blk * 256 + tid;

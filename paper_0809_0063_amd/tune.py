@@ -109,24 +109,34 @@ def candidates(p: int, n: int) -> List[BucketPlan]:
     return out
 
 
-def _time_plan(p: int, n: int, plan: BucketPlan, reps: int = 20) -> float:
+def _time_plan(p: int, n: int, plan: BucketPlan, reps: int = 20, launch=(16, 4)) -> float:
+    """Microseconds per product of a batch of identical-size products run with this plan.
+
+    The products of a bucket are run the way the batched workload runs them
+    (one packing launch + one persistent launch over all of them), enough of
+    them that the launches are not the measurement.
+    """
     dev = torch.device("cuda:0")
     g = torch.Generator(device="cpu").manual_seed(1234 + n * 7 + p)
     A = torch.randint(0, p, (n, n), dtype=torch.uint8, generator=g).to(dev)
     B = torch.randint(0, p, (n, n), dtype=torch.uint8, generator=g).to(dev)
-    C = torch.empty((n, n), dtype=torch.uint8, device=dev)
-    gp = D.GemmPlan(algo=plan.algo, interval=plan.interval, log2Q=plan.log2Q, epilogue=plan.epilogue)
-    ws = torch.empty(max(1, D.fgemm_workspace_size(p, n, n, n, gp)), dtype=torch.uint8, device=dev)
-    for _ in range(3):
-        D.fgemm(A, B, p, plan=gp, out=C, workspace=ws)
+    count = int(min(2048, max(16, (1 << 33) // (n ** 3))))
+    Cs = torch.empty((count, n, n), dtype=torch.uint8, device=dev)
+    fields = plan.desc_fields()
+    descs = D.make_descs([dict(A=A, B=B, C=Cs[i], p=p, **fields) for i in range(count)])
+    ws = torch.empty(D.fgemm_batched_workspace_size(descs, *launch), dtype=torch.uint8, device=dev)
+    batch = D.Batch(descs, ws, *launch)
+    for _ in range(2):
+        batch.run()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        D.fgemm(A, B, p, plan=gp, out=C, workspace=ws)
+        batch.run()
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) * 1e3 / reps
+    batch.close()
+    return e0.elapsed_time(e1) * 1e3 / reps / count
 
 
 class Tuner:
@@ -185,7 +195,7 @@ class Tuner:
         cands = candidates(p, n)
         return min(cands, key=lambda c: model_cost(p, n, c))
 
-    def tune_bucket(self, p: int, bucket: int, reps: int = 20) -> BucketPlan:
+    def tune_bucket(self, p: int, bucket: int, reps: int = 5) -> BucketPlan:
         n = representative(bucket)
         best = None
         for c in candidates(p, n):
@@ -198,7 +208,7 @@ class Tuner:
         self.table[f"{p}:{bucket}"] = best
         return best
 
-    def tune(self, primes: Sequence[int], buckets: Optional[Sequence[int]] = None, reps: int = 20):
+    def tune(self, primes: Sequence[int], buckets: Optional[Sequence[int]] = None, reps: int = 5):
         for p in primes:
             for b in (buckets if buckets is not None else range(len(BUCKET_EDGES) - 1)):
                 self.tune_bucket(p, b, reps)
@@ -228,3 +238,42 @@ class Tuner:
 
     def desc_fields(self, p: int, n: int) -> Dict[str, int]:
         return self.plan(p, n).desc_fields()
+
+
+def main(argv=None):
+    """Tune every (bucket, p) of the batched workload and its launch shape; write the cache."""
+    import argparse
+
+    from . import inputs
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--primes", type=int, nargs="+", default=list(inputs.BATCH_PRIMES))
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--launch-items", type=int, default=2000,
+                    help="products of the batched workload used to time the launch shapes")
+    args = ap.parse_args(argv)
+    t = Tuner(args.out)
+    t0 = time.time()
+    t.tune(args.primes, reps=args.reps)
+    for k in sorted(t.table):
+        print(k, t.table[k], flush=True)
+    # launch shape on a prefix of the batched workload with the tuned plans
+    dev = torch.device("cuda:0")
+    items = inputs.batch_items(10000)[: args.launch_items]
+    ops = []
+    for it in items:
+        A, B = inputs.item_operands(it)
+        d = {"A": torch.from_numpy(A).to(dev), "B": torch.from_numpy(B).to(dev),
+             "C": torch.empty((it.n, it.n), dtype=torch.uint8, device=dev), "p": it.p}
+        d.update(t.desc_fields(it.p, it.n))
+        ops.append(d)
+    descs = D.make_descs(ops)
+    need = max(D.fgemm_batched_workspace_size(descs, tm, ks) for tm, ks in ((16, 4), (8, 2), (16, 2), (8, 4)))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    print("launch", t.tune_launch(descs, ws), flush=True)
+    t.save()
+    print(f"tuned in {time.time() - t0:.1f} s -> {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -22,7 +22,10 @@ from . import serve as S
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
-def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inputs.SEED_BATCH) -> Dict[str, float]:
+def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inputs.SEED_BATCH,
+            algo: Optional[int] = None) -> Dict[str, float]:
+    """One graph replay of the whole batch; `algo` forces one algorithm for every product
+    (otherwise the tuner's per-bucket plan, or the library default)."""
     dev = torch.device("cuda:0")
     items = inputs.batch_items(n_items, seed=seed)
     t0 = time.perf_counter()
@@ -31,12 +34,18 @@ def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inpu
         A, B = inputs.item_operands(it)
         d = {"A": torch.from_numpy(A).to(dev), "B": torch.from_numpy(B).to(dev),
              "C": torch.empty((it.n, it.n), dtype=torch.uint8, device=dev), "p": it.p}
-        if tuner is not None:
+        if algo is not None:
+            d["algo"] = algo
+        elif tuner is not None:
             d.update(tuner.desc_fields(it.p, it.n))
         ops.append(d)
         macs += float(it.n) ** 3
         dot_ops += float(it.n) * it.n * ((it.n + 3) // 4)
     gen_s = time.perf_counter() - t0
+    algo_count: Dict[int, int] = {}
+    for d in ops:
+        a = d.get("algo", 0)
+        algo_count[a] = algo_count.get(a, 0) + 1
     descs = D.make_descs(ops)
     launch = tuner.launch if (tuner is not None and tuner.launch) else (16, 4)
     ws = torch.empty(D.fgemm_batched_workspace_size(descs, *launch), dtype=torch.uint8, device=dev)
@@ -67,6 +76,8 @@ def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inpu
     batch.close()
     return {"products": n_items, "ms_per_replay": round(sec * 1e3, 3), "fp_gop_s": round(2 * macs / sec / 1e9, 1),
             "packed_lane_op_frac": round(dot_ops / sec / PEAK_LANE_OPS, 4), "launch": list(launch),
+            "tuned_buckets": len(tuner.table) if (tuner is not None and algo is None) else 0,
+            "algos": {str(k): v for k, v in sorted(algo_count.items())},
             "input_gen_s": round(gen_s, 1)}
 
 

@@ -22,11 +22,17 @@
 // per instruction) issue far fewer instructions per multiply-add than the
 // vector units, and each multiply-add here carries e_r e_c F_p multiply-adds.
 //
-// Device layouts (workspace):
+// Device layouts (workspace), Left and Full:
 //   Ad: [Mw_pad/16][K_pad/4][64] binary64, lane l of a 16x4 block holding
 //       word row l%16 at k = l/16 (the matrix-core A operand layout);
 //   Bd: [Nw_pad/16][K_pad/4][64] binary64, lane l holding k = l/16 of word
 //       column l%16 (the B operand layout).
+// Right (A uncompressed): A stays uint8, copied to [Mw_pad][K_pad] with zero
+// padding (K_pad a multiple of 16), and converted to binary64 in registers;
+// inside each group of 16 k the matrix-core steps take k = 4g + s (step s,
+// lane group g = l/16), so that lane l reads the four A entries of its four
+// steps as one dword.  Bd: [Nw_pad/16][K_pad/16][4][64] binary64, step s of
+// group c, lane l holding k = 16c + 4(l/16) + s of word column l%16.
 // The accumulator of a 16x16 block holds, in lane l and element r, word row
 // l/16 + 4r and word column l%16.
 
@@ -64,6 +70,37 @@ struct F64PackArgs {
     uint64_t nb;           // doubles of Bd
     uint32_t er, ec, b;    // rows/columns per word, log2 Q
 };
+
+// Right: A copied as uint8 with zero padding (four bytes per thread), B
+// packed e columns per binary64 word in the permuted-k step layout.
+__global__ __launch_bounds__(256) void k_f64_pack_right(F64PackArgs a) {
+    const uint32_t kp = a.nks * 4;           // K_pad (multiple of 16)
+    const uint64_t nad = a.na / 4;           // dwords of the A copy
+    const uint64_t total = nad + a.nb;
+    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < total; t += (uint64_t)gridDim.x * 256) {
+        if (t < nad) {
+            const uint32_t row = (uint32_t)(t / (kp / 4)), k0 = (uint32_t)(t % (kp / 4)) * 4;
+            uint32_t d = 0;
+            if (row < a.m)
+                for (uint32_t x = 0; x < 4; ++x)
+                    if (k0 + x < a.kdim) d |= (uint32_t)a.A[(size_t)row * a.lda + k0 + x] << (8 * x);
+            reinterpret_cast<uint32_t*>(a.Ad)[t] = d;
+        } else {
+            const uint64_t u = t - nad;
+            const uint32_t l = (uint32_t)(u & 63), st = (uint32_t)((u >> 6) & 3);
+            const uint64_t q = u >> 8;
+            const uint32_t c = (uint32_t)(q % (kp / 16)), cb = (uint32_t)(q / (kp / 16));
+            const uint32_t jw = cb * 16 + (l & 15), k = 16 * c + 4 * (l >> 4) + st;
+            uint64_t w = 0;
+            if (k < a.kdim)
+                for (uint32_t x = 0; x < a.ec; ++x) {
+                    const uint32_t col = jw * a.ec + x;
+                    if (col < a.n) w |= (uint64_t)a.B[(size_t)k * a.ldb + col] << (a.b * x);
+                }
+            a.Bd[u] = (double)w;
+        }
+    }
+}
 
 // Uncompress/compress the operands into the matrix-core layouts (one double
 // per thread, grid-stride).
@@ -207,6 +244,107 @@ __global__ __launch_bounds__(64 * KS) void k_f64_mm(F64Args g) {
     }
 }
 
+// Right compression: A as uint8 (four entries of a lane's four steps in one
+// dword, converted to binary64 in registers), B words in the step layout; 2x2
+// blocks of 16x16 words per wave, KS waves splitting the groups of 16 k.
+template <int KS>
+__global__ __launch_bounds__(64 * KS) void k_f64_right(F64Args g) {
+    constexpr int TR = 2, TC = 2;
+    __shared__ double red[KS > 1 ? KS * TR * TC * 4 * 64 : 1];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    uint32_t bid = blockIdx.x, nblk = gridDim.x, logical = bid;
+    if ((nblk & 7u) == 0) logical = (bid & 7u) * (nblk >> 3) + (bid >> 3);
+    const uint32_t rb = logical % g.nrb, cb = logical / g.nrb;
+    const uint32_t ng = g.nks / 4;                       // groups of 16 k
+    const uint32_t g0 = min(ng, wave * g.ks_split), g1 = min(ng, g0 + g.ks_split);
+    const uint32_t kp = g.nks * 4;
+    const uint8_t* A8 = reinterpret_cast<const uint8_t*>(g.Ad);
+    const uint32_t* pa[TR];
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+        pa[r] = reinterpret_cast<const uint32_t*>(A8 + (size_t)((rb * TR + r) * 16 + (lane & 15u)) * kp) + (lane >> 4);
+    const double* pb[TC];
+#pragma unroll
+    for (int c = 0; c < TC; ++c) pb[c] = g.Bd + (size_t)(cb * TC + c) * ng * 256 + lane;
+    f64x4 acc[TR][TC];
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+#pragma unroll
+        for (int c = 0; c < TC; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (uint32_t gi = g0; gi < g1; ++gi) {
+        uint32_t ad[TR];
+#pragma unroll
+        for (int r = 0; r < TR; ++r) ad[r] = pa[r][(size_t)gi * 4];
+        double bv[TC][4];
+#pragma unroll
+        for (int c = 0; c < TC; ++c)
+#pragma unroll
+            for (int st = 0; st < 4; ++st) bv[c][st] = pb[c][(size_t)gi * 256 + st * 64];
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int r = 0; r < TR; ++r) {
+                const double av = (double)((ad[r] >> (8 * st)) & 0xFFu);
+#pragma unroll
+                for (int c = 0; c < TC; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c][st], acc[r][c], 0, 0, 0);
+            }
+    }
+    constexpr int NQ = TR * TC * 4;
+    double v[NQ];
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+#pragma unroll
+        for (int c = 0; c < TC; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[(r * TC + c) * 4 + e] = acc[r][c][e];
+    if (KS > 1) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) red[(wave * NQ + q) * 64 + lane] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if ((uint32_t)q % KS != wave) continue;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < KS; ++w) sum += red[(w * NQ + q) * 64 + lane];
+            v[q] = sum;
+        }
+    }
+    const RedqArgs& ra = g.ra;
+    const uint32_t nd = g.ec;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (KS > 1 && (uint32_t)q % KS != wave) continue;
+        const int t = q / 4, e = q % 4;
+        const uint32_t row = (rb * TR + t / TC) * 16 + (lane >> 4) + 4 * e;
+        const uint32_t jw = (cb * TC + t % TC) * 16 + (lane & 15u);
+        if (row >= g.m) continue;
+        const uint64_t U = redq_compress((uint64_t)v[q], ra);
+        uint8_t* out = g.C + (size_t)row * g.ldc + jw * nd;
+        uint32_t prev = field(U, 0, ra);
+        if (nd == 4 && jw * 4 + 3 < g.n && ((uintptr_t)out & 3) == 0) {
+            // the four digits are four adjacent outputs: one dword store
+            uint32_t bytes = 0;
+#pragma unroll
+            for (uint32_t d = 0; d < 4; ++d) {
+                const uint32_t next = d + 1 < 4 ? field(U, d + 1, ra) : 0;
+                const uint32_t mu = (ra.c && d + 1 < 4) ? correct_arith(prev, next, ra) : prev;
+                prev = next;
+                bytes |= mu << (8 * d);
+            }
+            *reinterpret_cast<uint32_t*>(out) = bytes;
+            continue;
+        }
+        for (uint32_t d = 0; d < nd; ++d) {
+            const uint32_t next = d + 1 < nd ? field(U, d + 1, ra) : 0;
+            const uint32_t mu = (ra.c && d + 1 < nd) ? correct_arith(prev, next, ra) : prev;
+            prev = next;
+            if (jw * nd + d < g.n) out[d] = (uint8_t)mu;
+        }
+    }
+}
+
 static uint64_t rup(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
 // Plan of a compressed product on the matrix cores.  algo: DQT_GEMM_RIGHT
@@ -242,22 +380,29 @@ dqt_status f64_plan(uint32_t algo, uint32_t p, uint64_t m, uint64_t n, uint64_t 
     const uint64_t Mw = (m + r->er - 1) / r->er, Nw = (n + r->ec - 1) / r->ec;
     r->m_pad = (uint32_t)rup(Mw ? Mw : 1, 16 * r->tm);
     r->n_pad = (uint32_t)rup(Nw ? Nw : 1, 16 * r->tn);
-    const uint32_t nks = (uint32_t)((kdim + 3) / 4);
-    r->k_pad = 4 * (nks ? nks : 1);
+    const uint32_t kq = algo == DQT_GEMM_RIGHT ? 16 : 4;   // k padding (Right: groups of 16)
+    const uint64_t kpad = (kdim + kq - 1) / kq * kq;
+    r->k_pad = (uint32_t)(kpad ? kpad : kq);
     if (want_ks) {
-        if (want_ks != 1 && want_ks != 2 && want_ks != 4 && want_ks != 8) return DQT_E_INVALID;
+        if (want_ks != 1 && want_ks != 2 && want_ks != 4 && want_ks != 8 &&
+            !(want_ks == 16 && algo == DQT_GEMM_RIGHT))
+            return DQT_E_INVALID;
         r->s = want_ks;
     } else {
         // enough waves for the chip: k split across up to 8 waves of a workgroup
         const uint64_t blocks = (uint64_t)(r->m_pad / (16 * r->tm)) * (r->n_pad / (16 * r->tn));
         r->s = 1;
-        while (r->s < 8 && blocks * r->s < 2048 && (r->k_pad / 4) / (r->s * 2) >= 8) r->s *= 2;
+        if (algo == DQT_GEMM_RIGHT)
+            while (r->s < 16 && blocks * r->s < 4096 && (r->k_pad / 16) / (r->s * 2) >= 2) r->s *= 2;
+        else
+            while (r->s < 8 && blocks * r->s < 2048 && (r->k_pad / 4) / (r->s * 2) >= 8) r->s *= 2;
     }
-    r->ws_bytes = ((size_t)r->m_pad + r->n_pad) * r->k_pad * sizeof(double);
+    r->ws_bytes = f64_side_bytes(*r, 0) + f64_side_bytes(*r, 1);
     return DQT_OK;
 }
 
 size_t f64_side_bytes(const GemmPlanResolved& r, int side) {
+    if (side == 0 && r.algo == DQT_GEMM_RIGHT) return ((size_t)r.m_pad * r.k_pad + 15) / 16 * 16;  // uint8 copy of A
     return (size_t)(side == 0 ? r.m_pad : r.n_pad) * r.k_pad * sizeof(double);
 }
 
@@ -267,6 +412,14 @@ static void launch_f64_mm(const F64Args& g, unsigned grid, hipStream_t s, hipEve
         hipExtLaunchKernelGGL(k_f64_mm<2, 2, KS>, dim3(grid), dim3(64 * KS), 0, s, e0, e1, 0, g);
     else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_f64_mm<2, 2, KS>), dim3(grid), dim3(64 * KS), 0, s, g);
+}
+
+template <int KS>
+static void launch_f64_right(const F64Args& g, unsigned grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(k_f64_right<KS>, dim3(grid), dim3(64 * KS), 0, s, e0, e1, 0, g);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_f64_right<KS>), dim3(grid), dim3(64 * KS), 0, s, g);
 }
 
 // Either operand may be NULL (its packed copy is kept).
@@ -289,6 +442,11 @@ dqt_status f64_pack_enqueue(const GemmPlanResolved& r, uint64_t m, uint64_t n, u
     a.ec = r.ec;
     a.b = r.b;
     if (a.na + a.nb == 0) return DQT_OK;
+    if (r.algo == DQT_GEMM_RIGHT) {
+        hipLaunchKernelGGL(k_f64_pack_right, dim3(stream_grid(a.na / 4 + a.nb, 256, 8)), dim3(256), 0, s, a);
+        DQT_LAUNCH_CHECK("fgemm(f64 pack)");
+        return DQT_OK;
+    }
     hipLaunchKernelGGL(k_f64_pack, dim3(stream_grid(a.na + a.nb, 256, 8)), dim3(256), 0, s, a);
     DQT_LAUNCH_CHECK("fgemm(f64 pack)");
     return DQT_OK;
@@ -305,13 +463,24 @@ dqt_status f64_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t m
     g.n = (uint32_t)n;
     g.ldc = (uint32_t)ldc;
     g.nks = r.k_pad / 4;
-    g.ks_split = (g.nks + r.s - 1) / r.s;
+    g.ks_split = r.algo == DQT_GEMM_RIGHT ? (r.k_pad / 16 + r.s - 1) / r.s : (g.nks + r.s - 1) / r.s;
     g.nrb = r.m_pad / (16 * r.tm);
     g.er = r.er;
     g.ec = r.ec;
     const uint32_t nd = r.er * r.ec;
     DQT_TRY(make_redq_args(p, r.b, nd, nd * r.b, &g.ra));
     const unsigned grid = g.nrb * (r.n_pad / (16 * r.tn));
+    if (r.algo == DQT_GEMM_RIGHT) {
+        switch (r.s) {
+            case 1: launch_f64_right<1>(g, grid, s, e0, e1); break;
+            case 2: launch_f64_right<2>(g, grid, s, e0, e1); break;
+            case 4: launch_f64_right<4>(g, grid, s, e0, e1); break;
+            case 8: launch_f64_right<8>(g, grid, s, e0, e1); break;
+            default: launch_f64_right<16>(g, grid, s, e0, e1); break;
+        }
+        DQT_LAUNCH_CHECK("fgemm(f64 right)");
+        return DQT_OK;
+    }
     switch (r.s) {
         case 1: launch_f64_mm<1>(g, grid, s, e0, e1); break;
         case 2: launch_f64_mm<2>(g, grid, s, e0, e1); break;

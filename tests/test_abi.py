@@ -132,7 +132,7 @@ def test_compressed_f64_plan_sizes(D):
     # p = 3, k = 1024: Q = 2^13, four digits per word
     m = n = k = 1024
     ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_RIGHT))
-    assert ws == (1024 + 256) * 1024 * 8          # A uncompressed, B four columns per word
+    assert ws == 1024 * 1024 + 256 * 1024 * 8     # A uncompressed (uint8), B four columns per binary64 word
     ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_LEFT))
     assert ws == (256 + 1024) * 1024 * 8
     ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_FULL))

@@ -589,20 +589,33 @@ __global__ __launch_bounds__(256) void k_polymul_plain(const uint8_t* __restrict
 }
 
 // Generic plain product for any k (one product per thread, runtime loops).
+// Plain products of any degree: the 256 products of a block are staged in
+// LDS with coalesced copies (each operand byte is then read from LDS by the
+// schoolbook loops), one reduction per output coefficient.
 __global__ __launch_bounds__(256) void k_polymul_plain_any(const uint8_t* __restrict__ A, uint32_t ka,
                                                            const uint8_t* __restrict__ B, uint32_t kb,
                                                            uint8_t* __restrict__ OUT, uint64_t count, uint32_t p,
                                                            uint32_t pmagic) {
+    extern __shared__ uint8_t plain_smem[];
+    uint8_t* sx = plain_smem;              // [256][ka]
+    uint8_t* sy = plain_smem + 256 * ka;   // [256][kb]
     const uint32_t nr = ka + kb - 1;
-    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < count; t += (uint64_t)gridDim.x * 256) {
-        const uint8_t* x = A + t * ka;
-        const uint8_t* y = B + t * kb;
+    for (uint64_t t0 = blockIdx.x * 256ull; t0 < count; t0 += (uint64_t)gridDim.x * 256) {
+        const uint32_t nt = (uint32_t)min<uint64_t>(256, count - t0);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < nt * ka; e += 256) sx[e] = A[t0 * ka + e];
+        for (uint32_t e = threadIdx.x; e < nt * kb; e += 256) sy[e] = B[t0 * kb + e];
+        __syncthreads();
+        if (threadIdx.x >= nt) continue;
+        const uint8_t* x = sx + threadIdx.x * ka;
+        const uint8_t* y = sy + threadIdx.x * kb;
+        uint8_t* z = OUT + (t0 + threadIdx.x) * nr;
         for (uint32_t j = 0; j < nr; ++j) {
             uint32_t c = 0;
             const uint32_t i0 = j + 1 > kb ? j + 1 - kb : 0;
             const uint32_t i1 = j < ka - 1 ? j : ka - 1;
             for (uint32_t i = i0; i <= i1; ++i) c += (uint32_t)x[i] * (uint32_t)y[j - i];
-            OUT[t * nr + j] = (uint8_t)mod_small(c, p, pmagic);
+            z[j] = (uint8_t)mod_small(c, p, pmagic);
         }
     }
 }
@@ -920,7 +933,8 @@ extern "C" dqt_status dqt_polymul_plain_u8(const uint8_t* d_a, const uint8_t* d_
         DQT_PLAIN_CASE(7)
         DQT_PLAIN_CASE(8)
         default:
-            hipLaunchKernelGGL(k_polymul_plain_any, dim3(stream_grid(count, 256)), dim3(256), 0, s, d_a, k, d_b, k, d_out,
+            hipLaunchKernelGGL(k_polymul_plain_any, dim3(stream_grid(count, 256)), dim3(256), 256 * 2 * k, s, d_a, k, d_b,
+                               k, d_out,
                                count, p, pmagic);
     }
 #undef DQT_PLAIN_CASE

@@ -193,29 +193,36 @@ __device__ __forceinline__ uint32_t window_index(uint64_t U, uint32_t s, uint32_
 // through `put(i, mu_i)`.  With p | q the compressed residues are final.
 template <int NR, int B = 0, int W = 0, class Put>
 __device__ __forceinline__ void redq_correct(uint64_t U, const RedqArgs& a, const uint16_t* tab, Put put) {
-    if (a.c == 0) {
+    // Every branch fills all of r[] (compile-time indices), and the values are
+    // handed to `put` after the branches: the array stays in registers.
+    uint32_t r[NR];
 #pragma unroll
-        for (int i = 0; i < NR; ++i) put(i, field<B, W>(U, i, a));
-        return;
-    }
-    put(NR - 1, field<B, W>(U, NR - 1, a));
-    if (NR == 1) return;
-    if (a.tabj == 3 && NR >= 3) {
-        // windows of 3 residues overlapping by one; the last is shifted down to end at u_{NR-1}
+    for (int i = 0; i < NR; ++i) r[i] = field<B, W>(U, i, a);
+    if (a.c != 0 && NR > 1) {
+        if (a.tabj == 3 && NR >= 3) {
+            // windows of 3 residues overlapping by one; the last is shifted down to end at u_{NR-1}
+            uint32_t t[NR];
 #pragma unroll
-        for (int s0 = 0; s0 < NR - 1; s0 += 2) {
-            const int s = (s0 + 3 > NR) ? NR - 3 : s0;
-            const uint32_t e = tab[window_index<B, W>(U, s, 3, a)];
-            put(s, e & 0xFF);
-            put(s + 1, e >> 8);
+            for (int i = 0; i < NR; ++i) t[i] = r[i];
+#pragma unroll
+            for (int s0 = 0; s0 < NR - 1; s0 += 2) {
+                const int s = (s0 + 3 > NR) ? NR - 3 : s0;
+                const uint32_t e = tab[window_index<B, W>(U, s, 3, a)];
+                t[s] = e & 0xFF;
+                t[s + 1] = e >> 8;
+            }
+#pragma unroll
+            for (int i = 0; i < NR; ++i) r[i] = t[i];
+        } else if (a.tabj >= 2) {
+#pragma unroll
+            for (int s = 0; s < NR - 1; ++s) r[s] = tab[window_index<B, W>(U, s, 2, a)] & 0xFF;
+        } else {
+#pragma unroll
+            for (int s = 0; s < NR - 1; ++s) r[s] = correct_arith(r[s], r[s + 1], a);
         }
-    } else if (a.tabj >= 2) {
-#pragma unroll
-        for (int s = 0; s < NR - 1; ++s) put(s, tab[window_index<B, W>(U, s, 2, a)] & 0xFF);
-    } else {
-#pragma unroll
-        for (int s = 0; s < NR - 1; ++s) put(s, correct_arith(field<B, W>(U, s, a), field<B, W>(U, s + 1, a), a));
     }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) put(i, r[i]);
 }
 
 // Byte `pos` (compile-time) of a little-endian array of 32-bit words.

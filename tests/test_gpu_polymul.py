@@ -212,6 +212,16 @@ def test_fqt_long_products(dqt, p):
         assert (to_host(dqt.polymul_fqt_u8(to_dev(w), to_dev(wb), p)) == O.polymul(w, wb, p)).all()
 
 
+@pytest.mark.parametrize("k", [9, 16, 33, 48, 64])
+def test_polymul_plain_long(dqt, k):
+    """The plain comparator at long degrees (operands staged in LDS by blocks of 256 products)."""
+    for p in (2, 3, 251):
+        for count in (1, 255, 256, 257, 3000):
+            a, b = inputs.polymul_pairs(count, k, p, seed=k * 7 + count + p)
+            got = to_host(dqt.polymul_plain_u8(to_dev(a), to_dev(b), p))
+            assert (got == O.polymul(a, b, p)).all(), (p, k, count)
+
+
 @pytest.mark.parametrize("p", [2, 3, 5, 7, 11])
 def test_fqt_karatsuba_products(dqt, p):
     """Karatsuba block products (1 and 2 levels) give the oracle's bytes, also for unequal lengths,

@@ -42,7 +42,8 @@ typedef enum dqt_status {
     DQT_E_BOUND = -2,       /* parameters violate the paper's a priori bounds */
     DQT_E_UNSUPPORTED = -3, /* valid, but outside what the kernels implement */
     DQT_E_DEVICE = -4,      /* HIP runtime error (see dqt_last_error) */
-    DQT_E_WORKSPACE = -5    /* workspace null or smaller than required */
+    DQT_E_WORKSPACE = -5,   /* workspace null or smaller than required */
+    DQT_E_INPUT = -6        /* an input entry is not a residue in [0, p) (dqt_check_input_u8) */
 } dqt_status;
 
 /* Text of a status code (static storage). */
@@ -51,6 +52,17 @@ const char *dqt_status_str(dqt_status s);
 const char *dqt_last_error(void);
 /* Library version string. */
 const char *dqt_version(void);
+
+/*
+ * Input validation (debug mode).  The packed paths assume every entry is a
+ * residue in [0, p): the a priori bounds (eq:bounds, eq:lower) are stated for
+ * entries at most p-1, and a larger entry silently breaks them.  This call
+ * checks `count` bytes at d_x on `stream`, using the caller's 4-byte device
+ * word d_flag (no allocation), waits for the stream, and returns DQT_E_INPUT
+ * if some entry is >= p, DQT_OK otherwise.  Blocking; meant for debugging and
+ * tests, not for the timed paths.
+ */
+dqt_status dqt_check_input_u8(const uint8_t *d_x, uint64_t count, uint32_t p, uint32_t *d_flag, void *stream);
 
 /*
  * q-adic packing parameters (section 2.3, theorem eq:bounds).

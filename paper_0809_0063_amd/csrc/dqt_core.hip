@@ -175,11 +175,44 @@ extern "C" const char* dqt_status_str(dqt_status s) {
         case DQT_E_UNSUPPORTED: return "unsupported parameters";
         case DQT_E_DEVICE: return "HIP runtime error";
         case DQT_E_WORKSPACE: return "workspace too small";
+        case DQT_E_INPUT: return "input entry not a residue in [0, p)";
     }
     return "unknown status";
 }
 
 extern "C" const char* dqt_last_error(void) { return g_last_error.c_str(); }
+
+namespace dqt {
+__global__ __launch_bounds__(64) void k_flag_clear(uint32_t* flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+// Any entry >= p sets the flag (every writer stores the same value).
+__global__ __launch_bounds__(256) void k_check_input(const uint8_t* __restrict__ x, uint64_t count, uint32_t p,
+                                                     uint32_t* flag) {
+    bool bad = false;
+    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < count; t += (uint64_t)gridDim.x * 256)
+        bad |= x[t] >= p;
+    if (bad) *flag = 1;
+}
+}  // namespace dqt
+
+extern "C" dqt_status dqt_check_input_u8(const uint8_t* d_x, uint64_t count, uint32_t p, uint32_t* d_flag,
+                                         void* stream) {
+    if (p < 2 || p > 255 || !d_flag) return DQT_E_INVALID;
+    if (count == 0) return DQT_OK;
+    if (!d_x) return DQT_E_INVALID;
+    DQT_TRY(ensure_device_ready());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, s, d_flag);
+    DQT_LAUNCH_CHECK("dqt_check_input_u8");
+    hipLaunchKernelGGL(k_check_input, dim3(stream_grid(count, 256, 4)), dim3(256), 0, s, d_x, count, p, d_flag);
+    DQT_LAUNCH_CHECK("dqt_check_input_u8");
+    uint32_t h = 0;
+    DQT_TRY(hip_status(hipMemcpyAsync(&h, d_flag, sizeof(h), hipMemcpyDeviceToHost, s), "check_input copy"));
+    DQT_TRY(hip_status(hipStreamSynchronize(s), "check_input sync"));
+    return h ? DQT_E_INPUT : DQT_OK;
+}
 
 extern "C" const char* dqt_version(void) { return "libdqt 0.1 gfx950"; }
 

@@ -17,7 +17,9 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libdqt.so")
 
-DQT_OK, DQT_E_INVALID, DQT_E_BOUND, DQT_E_UNSUPPORTED, DQT_E_DEVICE, DQT_E_WORKSPACE = 0, -1, -2, -3, -4, -5
+DQT_OK, DQT_E_INVALID, DQT_E_BOUND, DQT_E_UNSUPPORTED, DQT_E_DEVICE, DQT_E_WORKSPACE, DQT_E_INPUT = 0, -1, -2, -3, -4, -5, -6
+# DQT_DEBUG=1: every call checks that its uint8 inputs are residues in [0, p) first (blocking)
+DEBUG = os.environ.get("DQT_DEBUG", "") not in ("", "0")
 
 GEMM_AUTO, GEMM_CMM, GEMM_PLAIN, GEMM_DOT4, GEMM_MFMA, GEMM_RIGHT, GEMM_LEFT, GEMM_FULL = 0, 1, 2, 3, 4, 5, 6, 7
 EPI_REDC, EPI_REDQ = 0, 1
@@ -109,6 +111,7 @@ def _load():
         "dqt_gf_dot_u8": [V, V, U64, U32, U32, U32, V, V, V],
         "dqt_polymul_fqt_u8": [V, U32, V, U32, U64, U32, U32, V, V],
         "dqt_polymul_fqt_kara_u8": [V, U32, V, U32, U64, U32, U32, U32, V, V],
+        "dqt_check_input_u8": [V, U64, U32, V, V],
         "dqt_fgemm": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V],
         "dqt_fgemm_batched_prepare": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V,
@@ -183,6 +186,25 @@ def _dev(t: torch.Tensor, name: str, dtype=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+_FLAG = {}
+
+
+def check_input(t: torch.Tensor, p: int, stream=None) -> None:
+    """Raise DQTError(DQT_E_INPUT) if some entry of the uint8 device tensor t is >= p (blocking)."""
+    dev = t.device
+    if dev not in _FLAG:
+        _FLAG[dev] = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(_load().dqt_check_input_u8(_dev(t, "input", torch.uint8), t.numel(), p, _dev(_FLAG[dev], "flag"),
+                                      _stream(stream)), "dqt_check_input_u8")
+
+
+def _debug_inputs(p: int, *ts) -> None:
+    if DEBUG:
+        for t in ts:
+            if t is not None:
+                check_input(t, p)
+
+
 def _host_modulus(modulus: Sequence[int]):
     arr = (ctypes.c_uint8 * len(modulus))(*[int(x) for x in modulus])
     return arr
@@ -253,6 +275,7 @@ def polymul_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Ten
                log2q: int = 0):
     """Packed fused product: uint8 [N, k] x uint8 [N, k] -> uint8 [N, 2k-1] over F_p (q = 2^log2q, 0 = smallest)."""
     _u8_pair(a, b)
+    _debug_inputs(p, a, b)
     n, k = a.shape
     if b.shape[1] != k:
         raise ValueError("a and b must have the same k")
@@ -265,6 +288,7 @@ def polymul_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Ten
 
 def polymul_plain_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Tensor] = None, stream=None):
     _u8_pair(a, b)
+    _debug_inputs(p, a, b)
     n, k = a.shape
     if out is None:
         out = torch.empty((n, 2 * k - 1), dtype=torch.uint8, device=a.device)
@@ -277,6 +301,7 @@ def polymul_fqt_u8(a: torch.Tensor, b: torch.Tensor, p: int, block: int = 0, out
                    stream=None):
     """Long products by blocks (FQT): uint8 [N, na] x uint8 [N, nb] -> uint8 [N, na+nb-1]."""
     _u8_pair(a, b)
+    _debug_inputs(p, a, b)
     n, na = a.shape
     nb = b.shape[1]
     if out is None:
@@ -290,6 +315,7 @@ def polymul_fqt_kara_u8(a: torch.Tensor, b: torch.Tensor, p: int, levels: int = 
                         out: Optional[torch.Tensor] = None, stream=None):
     """FQT products with Karatsuba block products (levels 1 or 2): same shapes and bytes as polymul_fqt_u8."""
     _u8_pair(a, b)
+    _debug_inputs(p, a, b)
     n, na = a.shape
     nb = b.shape[1]
     if out is None:
@@ -304,6 +330,7 @@ def gf_mul_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
               out: Optional[torch.Tensor] = None, stream=None, log2q: int = 0):
     """Packed GF(p^k) products: uint8 [N, k] each, modulus = k+1 monic coefficients (low first)."""
     _u8_pair(a, b)
+    _debug_inputs(p, a, b)
     n, k = a.shape
     if out is None:
         out = torch.empty((n, k), dtype=torch.uint8, device=a.device)
@@ -319,6 +346,7 @@ def gf_dot_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
     """Dot products over GF(p^k) by FGDP: uint8 [N, n, k] x uint8 [N, n, k] -> uint8 [N, k]."""
     if a.dim() != 3 or a.shape != b.shape:
         raise ValueError("a and b must be [N, n, k] with the same shape")
+    _debug_inputs(p, a, b)
     N, n, k = a.shape
     if out is None:
         out = torch.empty((N, k), dtype=torch.uint8, device=a.device)
@@ -332,6 +360,7 @@ def gf_dot_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
 def gf_mul_plain_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
                     out: Optional[torch.Tensor] = None, stream=None):
     _u8_pair(a, b)
+    _debug_inputs(p, a, b)
     n, k = a.shape
     if out is None:
         out = torch.empty((n, k), dtype=torch.uint8, device=a.device)
@@ -354,6 +383,7 @@ def fgemm(A: torch.Tensor, B: torch.Tensor, p: int, plan: Optional[GemmPlan] = N
     """C = A.B mod p for uint8 A [m, k], B [k, n] (row-major, contiguous)."""
     if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
         raise ValueError("A [m,k] and B [k,n] required")
+    _debug_inputs(p, A, B)
     m, kdim = A.shape
     n = B.shape[1]
     if out is None:

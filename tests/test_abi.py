@@ -143,3 +143,12 @@ def test_compressed_f64_plan_sizes(D):
     assert D.fgemm_workspace_size(13, 64, 64, 1024, D.GemmPlan(algo=D.GEMM_RIGHT)) > 0
     # a Q below the bound is refused
     assert D.fgemm_workspace_size(3, 64, 64, 1024, D.GemmPlan(algo=D.GEMM_RIGHT, log2Q=12)) == 0
+
+
+def test_input_status(D):
+    lib = D.lib()
+    assert lib.dqt_status_str(D.DQT_E_INPUT) == b"input entry not a residue in [0, p)"
+    # argument checks before any device call
+    assert lib.dqt_check_input_u8(None, 10, 3, None, None) == D.DQT_E_INVALID
+    assert lib.dqt_check_input_u8(None, 0, 3, None, None) == D.DQT_E_INVALID
+    assert lib.dqt_check_input_u8(None, 10, 1, None, None) == D.DQT_E_INVALID

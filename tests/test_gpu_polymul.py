@@ -271,3 +271,30 @@ def test_gf_dot_products(dqt, p, k, n):
     assert (got == ref).all()
     w = inputs.worst_case((5, n, k), p)
     assert (to_host(dqt.gf_dot_u8(to_dev(w), to_dev(w), p, P)) == O.gf_dot(w, w, p, P)).all()
+
+
+def test_check_input_and_debug_mode(dqt):
+    """An entry >= p is reported (DQT_E_INPUT); debug mode checks every call's inputs."""
+    import torch
+    a, b = inputs.polymul_pairs(1000, 4, 3)
+    da, db = to_dev(a), to_dev(b)
+    dqt.check_input(da, 3)
+    bad = da.clone()
+    bad.view(-1)[777] = 3
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.check_input(bad, 3)
+    assert e.value.status == dqt.DQT_E_INPUT
+    dqt.check_input(bad, 5)
+    old = dqt.DEBUG
+    try:
+        dqt.DEBUG = True
+        assert (to_host(dqt.polymul_u8(da, db, 3)) == O.polymul(a, b, 3)).all()
+        with pytest.raises(dqt.DQTError) as e:
+            dqt.polymul_u8(bad, db, 3)
+        assert e.value.status == dqt.DQT_E_INPUT
+        A = torch.zeros((64, 64), dtype=torch.uint8, device=da.device)
+        A[5, 7] = 200
+        with pytest.raises(dqt.DQTError):
+            dqt.fgemm(A, A, 7)
+    finally:
+        dqt.DEBUG = old

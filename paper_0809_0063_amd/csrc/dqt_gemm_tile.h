@@ -20,8 +20,9 @@
 // or four u8 entries per word and v_dot4_u32_u8.
 //
 // A wave owns TM rows (uniform: their words are scalar loads, operands in
-// SGPRs) and 64*TN columns (one per lane and per j, coalesced vector loads).
-// S waves of a workgroup split k and add their partial sums through LDS.
+// SGPRs) and 64*TN columns (TN adjacent columns per lane, one vector load per
+// k-group).  S waves of a workgroup split k and add their partial sums
+// through LDS.
 #pragma once
 
 #include "../../include/dqt.h"
@@ -32,8 +33,8 @@ namespace dqt {
 enum GemmOp { OP_DOT2 = 0, OP_DOT4 = 1, OP_MAD = 2 };
 
 struct GemmArgs {
-    const uint32_t* CA;   // [KW][m_pad] packed words of A, k-major
-    const uint32_t* CB;   // [KW][n_pad] packed words of B, k-major
+    const uint32_t* CA;   // [m_pad/TM][KW][TM] packed words of A (tile-major, see gemm_tile)
+    const uint32_t* CB;   // [n_pad/(64 TN)][KW][64 TN] packed words of B
     uint8_t* C;
     uint32_t m, n, ldc;
     uint32_t m_pad, n_pad;

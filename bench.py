@@ -246,7 +246,8 @@ def main():
         from paper_0809_0063_amd import workloads as W
         from paper_0809_0063_amd import tune as T
         for name, fn in (("batched_10000_tuned", lambda: W.batched(10000, replays=3, tuner=T.Tuner())),
-                         ("batched_10000_packed_cmm", lambda: W.batched(10000, replays=3, algo=D.GEMM_CMM)),
+                         ("batched_10000_packed_cmm", lambda: W.batched(10000, replays=3, tuner=T.Tuner(),
+                                                                         algo=D.GEMM_CMM)),
                          ("serving", lambda: W.serving(n_requests=2000, warmup=200))):
             try:
                 extra[name] = fn()

@@ -349,6 +349,7 @@ typedef struct dqt_gemm_desc {
 typedef struct dqt_batch_opts {
     uint32_t tile_rows;     /* 8 or 16 (0 = 16) */
     uint32_t ksplit;        /* 2 or 4 waves per workgroup (0 = 4) */
+    uint32_t tile_cols;     /* columns per lane, 2 or 4 (0 = 2) */
 } dqt_batch_opts;
 
 typedef struct dqt_batch dqt_batch;   /* opaque host handle */

@@ -69,10 +69,10 @@ __global__ __launch_bounds__(256) void k_batch_pack(const BatchHeader* __restric
     }
 }
 
-template <int TM, int S>
+template <int TM, int TN, int S>
 __global__ __launch_bounds__(64 * S) void k_batch_compute(BatchHeader* hdr, const BatchDesc* __restrict__ descs,
                                                           const uint2* __restrict__ items) {
-    __shared__ uint32_t red[TileSmem<TM, 2, S>::words];
+    __shared__ uint32_t red[TileSmem<TM, TN, S>::words];
     __shared__ uint32_t next;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
@@ -91,21 +91,21 @@ __global__ __launch_bounds__(64 * S) void k_batch_compute(BatchHeader* hdr, cons
         switch (g.op) {
             case OP_DOT2:
                 if (g.lw) {
-                    if (g.epi) gemm_tile<OP_DOT2, TM, 2, S, true, 1>(g, rb, cb, wave, lane, red);
-                    else gemm_tile<OP_DOT2, TM, 2, S, true, 0>(g, rb, cb, wave, lane, red);
+                    if (g.epi) gemm_tile<OP_DOT2, TM, TN, S, true, 1>(g, rb, cb, wave, lane, red);
+                    else gemm_tile<OP_DOT2, TM, TN, S, true, 0>(g, rb, cb, wave, lane, red);
                 } else {
-                    if (g.epi) gemm_tile<OP_DOT2, TM, 2, S, false, 1>(g, rb, cb, wave, lane, red);
-                    else gemm_tile<OP_DOT2, TM, 2, S, false, 0>(g, rb, cb, wave, lane, red);
+                    if (g.epi) gemm_tile<OP_DOT2, TM, TN, S, false, 1>(g, rb, cb, wave, lane, red);
+                    else gemm_tile<OP_DOT2, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red);
                 }
                 break;
-            case OP_DOT4: gemm_tile<OP_DOT4, TM, 2, S, false, 0>(g, rb, cb, wave, lane, red); break;
-            default: gemm_tile<OP_MAD, TM, 2, S, false, 0>(g, rb, cb, wave, lane, red); break;
+            case OP_DOT4: gemm_tile<OP_DOT4, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
+            default: gemm_tile<OP_MAD, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
         }
         __syncthreads();  // the LDS reduction buffer is reused by the next item
     }
 }
 
-static BatchLayout batch_layout(const dqt_gemm_desc* descs, uint32_t count, uint32_t tm, uint32_t s,
+static BatchLayout batch_layout(const dqt_gemm_desc* descs, uint32_t count, uint32_t tm, uint32_t tn, uint32_t s,
                                 std::vector<GemmPlanResolved>* plans, uint64_t* n_items, dqt_status* st) {
     BatchLayout L;
     memset(&L, 0, sizeof(L));
@@ -121,7 +121,7 @@ static BatchLayout batch_layout(const dqt_gemm_desc* descs, uint32_t count, uint
         pl.log2Q = d.log2Q;
         pl.epilogue = d.epilogue;
         pl.tile_rows = tm;
-        pl.tile_cols = 2;
+        pl.tile_cols = tn;
         pl.ksplit = s;
         if (d.algo == DQT_GEMM_MFMA || is_f64_algo(d.algo)) {
             *st = DQT_E_UNSUPPORTED;
@@ -157,14 +157,16 @@ using namespace dqt;
 struct dqt_batch {
     uint8_t* work;
     size_t descs_off, prefix_off, items_off;
-    uint32_t tm, s, count;
+    uint32_t tm, tn, s, count;
     uint64_t n_items, pack_blocks;
 };
 
-static dqt_status batch_opts(const dqt_batch_opts* o, uint32_t* tm, uint32_t* s) {
+static dqt_status batch_opts(const dqt_batch_opts* o, uint32_t* tm, uint32_t* tn, uint32_t* s) {
     *tm = (o && o->tile_rows) ? o->tile_rows : 16;
+    *tn = (o && o->tile_cols) ? o->tile_cols : 2;
     *s = (o && o->ksplit) ? o->ksplit : 4;
     if (*tm != 8 && *tm != 16) return DQT_E_INVALID;
+    if (*tn != 2 && *tn != 4) return DQT_E_INVALID;
     if (*s != 2 && *s != 4) return DQT_E_INVALID;
     return DQT_OK;
 }
@@ -172,12 +174,12 @@ static dqt_status batch_opts(const dqt_batch_opts* o, uint32_t* tm, uint32_t* s)
 extern "C" size_t dqt_fgemm_batched_workspace_size(const dqt_gemm_desc* descs, uint32_t count,
                                                    const dqt_batch_opts* opts) {
     if (!descs || count == 0) return 0;
-    uint32_t tm, s;
-    if (batch_opts(opts, &tm, &s) != DQT_OK) return 0;
+    uint32_t tm, tn, s;
+    if (batch_opts(opts, &tm, &tn, &s) != DQT_OK) return 0;
     std::vector<GemmPlanResolved> plans;
     uint64_t items = 0;
     dqt_status st;
-    const BatchLayout L = batch_layout(descs, count, tm, s, &plans, &items, &st);
+    const BatchLayout L = batch_layout(descs, count, tm, tn, s, &plans, &items, &st);
     return st == DQT_OK ? L.total : 0;
 }
 
@@ -186,8 +188,8 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
                                                 void* stream, dqt_batch** out) {
     if (!descs || count == 0 || !out) return DQT_E_INVALID;
     *out = nullptr;
-    uint32_t tm, s;
-    DQT_TRY(batch_opts(opts, &tm, &s));
+    uint32_t tm, tn, s;
+    DQT_TRY(batch_opts(opts, &tm, &tn, &s));
     for (uint32_t i = 0; i < count; ++i) {
         const dqt_gemm_desc& d = descs[i];
         if (d.m == 0 || d.n == 0) return DQT_E_INVALID;
@@ -196,7 +198,7 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
     std::vector<GemmPlanResolved> plans;
     uint64_t n_items = 0;
     dqt_status st;
-    const BatchLayout L = batch_layout(descs, count, tm, s, &plans, &n_items, &st);
+    const BatchLayout L = batch_layout(descs, count, tm, tn, s, &plans, &n_items, &st);
     DQT_TRY(st);
     if (!d_work || work_bytes < L.total) return DQT_E_WORKSPACE;
     DQT_TRY(ensure_device_ready());
@@ -292,6 +294,7 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
     b->prefix_off = L.prefix;
     b->items_off = L.items;
     b->tm = tm;
+    b->tn = tn;
     b->s = s;
     b->count = count;
     b->n_items = n_items;
@@ -302,7 +305,7 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
 
 
 
-template <int TM, int S>
+template <int TM, int TN, int S>
 static dqt_status batch_launch(const dqt_batch* b, hipStream_t st) {
     BatchHeader* hdr = reinterpret_cast<BatchHeader*>(b->work);
     const BatchDesc* descs = reinterpret_cast<const BatchDesc*>(b->work + b->descs_off);
@@ -318,7 +321,7 @@ static dqt_status batch_launch(const dqt_batch* b, hipStream_t st) {
     const uint64_t per_cu = (S == 2) ? 8 : 4;
     uint64_t gc = b->n_items < cus * per_cu ? b->n_items : cus * per_cu;
     if (gc < 1) gc = 1;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_batch_compute<TM, S>), dim3((unsigned)gc), dim3(64 * S), 0, st, hdr, descs,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_batch_compute<TM, TN, S>), dim3((unsigned)gc), dim3(64 * S), 0, st, hdr, descs,
                        items);
     DQT_LAUNCH_CHECK("batched compute");
     return DQT_OK;
@@ -327,10 +330,16 @@ static dqt_status batch_launch(const dqt_batch* b, hipStream_t st) {
 extern "C" dqt_status dqt_fgemm_batched_run(const dqt_batch* b, void* stream) {
     if (!b) return DQT_E_INVALID;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (b->tm == 8 && b->s == 2) return batch_launch<8, 2>(b, st);
-    if (b->tm == 8 && b->s == 4) return batch_launch<8, 4>(b, st);
-    if (b->tm == 16 && b->s == 2) return batch_launch<16, 2>(b, st);
-    return batch_launch<16, 4>(b, st);
+    if (b->tn == 4) {
+        if (b->tm == 8 && b->s == 2) return batch_launch<8, 4, 2>(b, st);
+        if (b->tm == 8 && b->s == 4) return batch_launch<8, 4, 4>(b, st);
+        if (b->tm == 16 && b->s == 2) return batch_launch<16, 4, 2>(b, st);
+        return batch_launch<16, 4, 4>(b, st);
+    }
+    if (b->tm == 8 && b->s == 2) return batch_launch<8, 2, 2>(b, st);
+    if (b->tm == 8 && b->s == 4) return batch_launch<8, 2, 4>(b, st);
+    if (b->tm == 16 && b->s == 2) return batch_launch<16, 2, 2>(b, st);
+    return batch_launch<16, 2, 4>(b, st);
 }
 
 extern "C" void dqt_batch_free(dqt_batch* b) { delete b; }

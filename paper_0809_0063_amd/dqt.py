@@ -54,7 +54,7 @@ class _GemmDesc(ctypes.Structure):
 
 
 class _BatchOpts(ctypes.Structure):
-    _fields_ = [("tile_rows", ctypes.c_uint32), ("ksplit", ctypes.c_uint32)]
+    _fields_ = [("tile_rows", ctypes.c_uint32), ("ksplit", ctypes.c_uint32), ("tile_cols", ctypes.c_uint32)]
 
 
 @dataclass(frozen=True)
@@ -548,23 +548,24 @@ def make_descs(items):
     return arr
 
 
-def _opts(tile_rows: int, ksplit: int) -> _BatchOpts:
-    return _BatchOpts(tile_rows, ksplit)
+def _opts(tile_rows: int, ksplit: int, tile_cols: int = 0) -> _BatchOpts:
+    return _BatchOpts(tile_rows, ksplit, tile_cols)
 
 
-def fgemm_batched_workspace_size(descs, tile_rows: int = 0, ksplit: int = 0) -> int:
-    o = _opts(tile_rows, ksplit)
+def fgemm_batched_workspace_size(descs, tile_rows: int = 0, ksplit: int = 0, tile_cols: int = 0) -> int:
+    o = _opts(tile_rows, ksplit, tile_cols)
     return int(_load().dqt_fgemm_batched_workspace_size(descs, len(descs), ctypes.byref(o)))
 
 
 class Batch:
     """A prepared batch (device-resident plan in `workspace`); run() enqueues pack + persistent compute."""
 
-    def __init__(self, descs, workspace: torch.Tensor, tile_rows: int = 0, ksplit: int = 0, stream=None):
+    def __init__(self, descs, workspace: torch.Tensor, tile_rows: int = 0, ksplit: int = 0, tile_cols: int = 0,
+                 stream=None):
         self._descs = descs
         self.workspace = workspace
         self._handle = ctypes.c_void_p()
-        o = _opts(tile_rows, ksplit)
+        o = _opts(tile_rows, ksplit, tile_cols)
         _check(_load().dqt_fgemm_batched_prepare(descs, len(descs), ctypes.byref(o), _dev(workspace, "workspace"),
                                                  workspace.numel() * workspace.element_size(), _stream(stream),
                                                  ctypes.byref(self._handle)), "dqt_fgemm_batched_prepare")
@@ -584,10 +585,11 @@ class Batch:
             pass
 
 
-def fgemm_batched(descs, workspace: torch.Tensor, tile_rows: int = 0, ksplit: int = 0, stream=None):
+def fgemm_batched(descs, workspace: torch.Tensor, tile_rows: int = 0, ksplit: int = 0, tile_cols: int = 0,
+                  stream=None):
     """Run every descriptor (from make_descs) in one packing launch and one persistent launch."""
-    o = _opts(tile_rows, ksplit)
-    ws = fgemm_batched_workspace_size(descs, tile_rows, ksplit)
+    o = _opts(tile_rows, ksplit, tile_cols)
+    ws = fgemm_batched_workspace_size(descs, tile_rows, ksplit, tile_cols)
     if workspace.numel() * workspace.element_size() < ws:
         raise ValueError(f"workspace needs {ws} bytes")
     _check(_load().dqt_fgemm_batched(descs, len(descs), ctypes.byref(o), _dev(workspace, "workspace"),

@@ -9,8 +9,8 @@ candidate plans on one representative square product and keeps the fastest:
   eq:lower, or a fraction of it) and the matching Q;
 * the epilogue (one REDC per output, or REDQ over gathered dot products).
 
-The launch shape of the persistent kernel (rows per wave, waves splitting k)
-is one per batch; `tune_launch` times the candidates on the batch itself.
+The launch shape of the persistent kernel (rows per wave, waves splitting k,
+columns per lane) is one per batch; `tune_launch` times the candidates on the batch itself.
 Results are cached as JSON keyed by the device architecture and the library
 version.  Every candidate produces the same bytes (the parity tests cover all
 of them), so tuning only changes speed.
@@ -34,6 +34,8 @@ import torch
 from . import dqt as D
 
 BUCKET_EDGES = (16, 32, 64, 128, 256, 512, 1025)
+# persistent-launch shapes (rows per wave, waves splitting k, columns per lane)
+LAUNCH_SHAPES = ((16, 4, 2), (8, 2, 2), (16, 2, 2), (8, 4, 2), (8, 4, 4), (8, 2, 4), (16, 2, 4), (16, 4, 4))
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
@@ -214,14 +216,15 @@ class Tuner:
                 self.tune_bucket(p, b, reps)
         return self.table
 
-    def tune_launch(self, descs, ws: torch.Tensor, shapes=((16, 4), (8, 2), (16, 2), (8, 4)), reps: int = 3):
-        """Pick (rows per wave, k-split) for a batch by timing its persistent launch."""
+    def tune_launch(self, descs, ws: torch.Tensor, shapes=LAUNCH_SHAPES, reps: int = 3):
+        """Pick (rows per wave, k-split, columns per lane) for a batch by timing its persistent launch."""
         best = None
-        for tm, ks in shapes:
-            need = D.fgemm_batched_workspace_size(descs, tm, ks)
+        for shape in shapes:
+            tm, ks, tn = (tuple(shape) + (2,))[:3]
+            need = D.fgemm_batched_workspace_size(descs, tm, ks, tn)
             if need == 0 or need > ws.numel():
                 continue
-            b = D.Batch(descs, ws, tm, ks)
+            b = D.Batch(descs, ws, tm, ks, tn)
             b.run()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -231,9 +234,9 @@ class Tuner:
             dt = (time.perf_counter() - t0) / reps
             b.close()
             if best is None or dt < best[0]:
-                best = (dt, tm, ks)
+                best = (dt, tm, ks, tn)
         if best:
-            self.launch = (best[1], best[2])
+            self.launch = (best[1], best[2], best[3])
         return self.launch
 
     def desc_fields(self, p: int, n: int) -> Dict[str, int]:
@@ -268,7 +271,7 @@ def main(argv=None):
         d.update(t.desc_fields(it.p, it.n))
         ops.append(d)
     descs = D.make_descs(ops)
-    need = max(D.fgemm_batched_workspace_size(descs, tm, ks) for tm, ks in ((16, 4), (8, 2), (16, 2), (8, 4)))
+    need = max(D.fgemm_batched_workspace_size(descs, *shape) for shape in LAUNCH_SHAPES)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     print("launch", t.tune_launch(descs, ws), flush=True)
     t.save()

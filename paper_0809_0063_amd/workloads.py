@@ -48,7 +48,7 @@ def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inpu
         a = d.get("algo", 0)
         algo_count[a] = algo_count.get(a, 0) + 1
     descs = D.make_descs(ops)
-    launch = tuner.launch if (tuner is not None and tuner.launch) else (16, 4)
+    launch = tuner.launch if (tuner is not None and tuner.launch) else (16, 2, 4)
     ws = torch.empty(D.fgemm_batched_workspace_size(descs, *launch), dtype=torch.uint8, device=dev)
     batch = D.Batch(descs, ws, *launch)
     batch.run()

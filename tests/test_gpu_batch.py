@@ -28,14 +28,16 @@ def _make(D, items, algo_of=lambda i, it: 0):
     return ops, host
 
 
-@pytest.mark.parametrize("tile_rows,ksplit", [(16, 4), (8, 2), (16, 2), (8, 4)])
-def test_batch_small_mixed(dqt, tile_rows, ksplit):
+@pytest.mark.parametrize("tile_rows,ksplit,tile_cols", [(16, 4, 2), (8, 2, 2), (16, 2, 2), (8, 4, 2), (8, 4, 4),
+                                                        (8, 2, 4), (16, 2, 4), (16, 4, 4)])
+def test_batch_small_mixed(dqt, tile_rows, ksplit, tile_cols):
     items = inputs.batch_items(60, nmin=1, nmax=300, seed=99)
     algos = [dqt.GEMM_AUTO, dqt.GEMM_CMM, dqt.GEMM_PLAIN, dqt.GEMM_DOT4]
     ops, host = _make(dqt, items, lambda i, it: algos[i % 4])
     descs = dqt.make_descs(ops)
-    ws = torch.empty(dqt.fgemm_batched_workspace_size(descs, tile_rows, ksplit), dtype=torch.uint8, device=device())
-    dqt.fgemm_batched(descs, ws, tile_rows, ksplit)
+    ws = torch.empty(dqt.fgemm_batched_workspace_size(descs, tile_rows, ksplit, tile_cols), dtype=torch.uint8,
+                     device=device())
+    dqt.fgemm_batched(descs, ws, tile_rows, ksplit, tile_cols)
     for op, (A, B), it in zip(ops, host, items):
         assert (to_host(op["C"]) == O.fgemm(A, B, it.p)).all(), (it, op["algo"])
 

@@ -105,3 +105,25 @@ def serving(n_requests: int = 5000, warmup: int = 500, qps: Optional[float] = No
     st["completed"] = len(done)
     st["cache_hit_rate"] = round(server.cache.hits / max(1, server.cache.hits + server.cache.misses), 3)
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+
+
+def main(argv=None):
+    """Run the batched and/or serving workload alone and print the results (one JSON line each)."""
+    import argparse
+    import json
+
+    from . import tune as T
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--serving", action="store_true")
+    ap.add_argument("--replays", type=int, default=3)
+    ap.add_argument("--requests", type=int, default=2000)
+    args = ap.parse_args(argv)
+    if args.batched:
+        print(json.dumps({"batched_10000_tuned": batched(10000, replays=args.replays, tuner=T.Tuner())}), flush=True)
+    if args.serving:
+        print(json.dumps({"serving": serving(n_requests=args.requests, warmup=args.requests // 10)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

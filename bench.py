@@ -35,10 +35,12 @@ EVENT_EVERY = 8                            # steps per kernel-timed step
 
 # HBM bytes per launch of the timed multiply kernel, from two rocprofv3 counter
 # runs (FETCH_SIZE, WRITE_SIZE; the summary and its commands are in profiles/),
-# valid only for the kernel sources they were taken on (their SHA-256).
-TRAFFIC_SOURCES = ("paper_0809_0063_amd/csrc/dqt_gemm.hip", "paper_0809_0063_amd/csrc/dqt_gemm_tile.h",
-                   "paper_0809_0063_amd/csrc/dqt_device.h")
-TRAFFIC = {"sha256": "2c5e694ca94b01f01d3f7ffd42569f253b6e9f80fd5e1476d4087e2a54bf84ab", "bytes": 11697800}
+# valid only for the device code they were taken on: the tile and REDQ device
+# headers and the kernel's definition, identified by their SHA-256.
+TRAFFIC_SOURCES = ("paper_0809_0063_amd/csrc/dqt_gemm_tile.h", "paper_0809_0063_amd/csrc/dqt_device.h")
+TRAFFIC_KERNEL = ("paper_0809_0063_amd/csrc/dqt_gemm.hip", "__device__ __forceinline__ void tile_of(",
+                  "// Pack A (rows")
+TRAFFIC = {"sha256": "66a6d0a6124795c1552f38500e3e6fb1ac33ef4fb23c3fac5a2437de455562da", "bytes": 11697800}
 
 
 def kernel_sources_sha256() -> str:
@@ -47,6 +49,11 @@ def kernel_sources_sha256() -> str:
     for rel in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
+    rel, begin, end = TRAFFIC_KERNEL
+    with open(os.path.join(ROOT, rel)) as f:
+        text = f.read()
+    i = text.index(begin)
+    h.update(text[i:text.index(end, i)].encode())
     return h.hexdigest()
 
 

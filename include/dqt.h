@@ -214,7 +214,8 @@ dqt_status dqt_polymul_fqt_kara_u8(const uint8_t *d_a, uint32_t na, const uint8_
  * F_p matrix product C = A.B mod p (section 7).
  * A: uint8 m x kdim, row-major, leading dimension lda >= kdim.
  * B: uint8 kdim x n, row-major, ldb >= n.  C: uint8 m x n, ldc >= n.
- * m, n, kdim may be 0 (no-op) and need not be multiples of any tile.
+ * m or n may be 0 (no-op); kdim == 0 gives C = 0 (empty sums) without
+ * reading A, B or the workspace; none needs to be a multiple of any tile.
  * ------------------------------------------------------------------------ */
 
 typedef enum dqt_gemm_algo {

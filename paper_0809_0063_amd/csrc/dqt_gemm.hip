@@ -403,6 +403,19 @@ static void launch_words_tm(const GemmArgs& g, unsigned grid, uint32_t tm, uint3
     }
 }
 
+// C = 0 for an empty inner dimension (every dot product is the empty sum).
+__global__ __launch_bounds__(256) void k_zero_c(uint8_t* C, uint64_t m, uint64_t n, uint64_t ldc) {
+    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < m * n; t += (uint64_t)gridDim.x * 256)
+        C[(t / n) * ldc + t % n] = 0;
+}
+
+static dqt_status zero_c(uint8_t* C, uint64_t m, uint64_t n, uint64_t ldc, hipStream_t s) {
+    DQT_TRY(ensure_device_ready());
+    hipLaunchKernelGGL(k_zero_c, dim3(stream_grid(m * n, 256, 4)), dim3(256), 0, s, C, m, n, ldc);
+    DQT_LAUNCH_CHECK("fgemm(k = 0)");
+    return DQT_OK;
+}
+
 dqt_status fgemm_epilogue_args(uint32_t p, uint64_t kdim, const GemmPlanResolved& r, GemmArgs* g) {
     g->epi = r.epi;
     if (r.epi == 1) {
@@ -607,7 +620,7 @@ extern "C" dqt_status dqt_fgemm_pack(uint32_t p, uint64_t m, uint64_t n, uint64_
                                      void* d_work, size_t work_bytes, void* stream) {
     GemmPlanResolved r;
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
-    if (m == 0 || n == 0) return DQT_OK;
+    if (m == 0 || n == 0 || kdim == 0) return DQT_OK;
     if (!d_A && !d_B) return DQT_E_INVALID;
     if ((d_A && lda < kdim) || (d_B && ldb < n) || lda > 0xFFFFFFFFull || ldb > 0xFFFFFFFFull) return DQT_E_INVALID;
     DQT_TRY(fgemm_common_checks(p, m, n, kdim, plan, work_bytes, d_work, &r));
@@ -622,6 +635,7 @@ extern "C" dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
     if (m == 0 || n == 0) return DQT_OK;
     if (!d_C || ldc < n || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
+    if (kdim == 0) return zero_c(d_C, m, n, ldc, reinterpret_cast<hipStream_t>(stream));
     DQT_TRY(fgemm_common_checks(p, m, n, kdim, plan, work_bytes, d_work, &r));
     DQT_TRY(ensure_device_ready());
     return fgemm_compute_enqueue(p, m, n, kdim, d_C, ldc, r, d_work, reinterpret_cast<hipStream_t>(stream));
@@ -668,7 +682,7 @@ extern "C" dqt_status dqt_fgemm_pack_side(uint32_t p, uint64_t rows_or_cols, uin
                                           void* stream) {
     GemmPlanResolved r;
     DQT_TRY(side_plan(p, rows_or_cols, kdim, side, plan, &r));
-    if (rows_or_cols == 0) return DQT_OK;
+    if (rows_or_cols == 0 || kdim == 0) return DQT_OK;
     if (!d_X || !d_packed || ((uintptr_t)d_packed & 15)) return DQT_E_INVALID;
     if ((side == 0 && ldx < kdim) || (side == 1 && ldx < rows_or_cols) || ldx > 0xFFFFFFFFull) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
@@ -688,6 +702,10 @@ extern "C" dqt_status dqt_fgemm_packed(uint32_t p, uint64_t m, uint64_t n, uint6
     GemmPlanResolved r;
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
     if (m == 0 || n == 0) return DQT_OK;
+    if (kdim == 0) {
+        if (!d_C || ldc < n || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
+        return zero_c(d_C, m, n, ldc, reinterpret_cast<hipStream_t>(stream));
+    }
     if (!d_CA || !d_CB || !d_C || ldc < n || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
     if (((uintptr_t)d_CA & 15) || ((uintptr_t)d_CB & 15)) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
@@ -700,6 +718,10 @@ extern "C" dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdi
     GemmPlanResolved r;
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
     if (m == 0 || n == 0) return DQT_OK;
+    if (kdim == 0) {
+        if (!d_C || ldc < n || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;
+        return zero_c(d_C, m, n, ldc, reinterpret_cast<hipStream_t>(stream));
+    }
     if (!d_A || !d_B || !d_C) return DQT_E_INVALID;
     if (lda < kdim || ldb < n || ldc < n) return DQT_E_INVALID;
     if (lda > 0xFFFFFFFFull || ldb > 0xFFFFFFFFull || ldc > 0xFFFFFFFFull) return DQT_E_INVALID;

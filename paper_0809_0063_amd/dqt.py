@@ -452,6 +452,8 @@ def fgemm_pack_side(X: torch.Tensor, p: int, side: int, plan: Optional[GemmPlan]
     if X.dim() != 2:
         raise ValueError("a matrix is required")
     rows_or_cols, kdim = (X.shape[0], X.shape[1]) if side == 0 else (X.shape[1], X.shape[0])
+    if kdim == 0 or rows_or_cols == 0:
+        return torch.empty(0, dtype=torch.uint8, device=X.device) if out is None else out
     nb = fgemm_packed_bytes(p, rows_or_cols, kdim, side, plan)
     if nb == 0:
         raise DQTError(DQT_E_UNSUPPORTED, "dqt_fgemm_packed_bytes", "no packed layout for these arguments")

@@ -259,3 +259,24 @@ def test_compressed_f64_larger_q_and_reuse(dqt):
     with pytest.raises(dqt.DQTError) as e:
         dqt.fgemm(dA, dB, p, plan=dqt.GemmPlan(algo=dqt.GEMM_RIGHT, log2Q=5))   # below k (p-1)^2
     assert e.value.status == dqt.DQT_E_BOUND
+
+
+def test_fgemm_empty_dimensions(dqt):
+    """m = 0 or n = 0: nothing is written; k = 0: C = 0 (empty sums), for every algorithm and through
+    the two-phase and resident-operand calls."""
+    import torch
+    dev = device()
+    for plan in [None] + _all_algos(dqt) + _f64_plans(dqt, 3, 64):
+        for m, n in ((0, 5), (5, 0), (0, 0)):
+            A = torch.zeros((m, 7), dtype=torch.uint8, device=dev)
+            B = torch.zeros((7, n), dtype=torch.uint8, device=dev)
+            assert tuple(dqt.fgemm(A, B, 3, plan=plan).shape) == (m, n)
+        A = torch.zeros((33, 0), dtype=torch.uint8, device=dev)
+        B = torch.zeros((0, 130), dtype=torch.uint8, device=dev)
+        C = torch.full((33, 130), 9, dtype=torch.uint8, device=dev)
+        dqt.fgemm(A, B, 3, plan=plan, out=C)
+        assert (to_host(C) == 0).all(), plan
+        C.fill_(9)
+        CA, CB = dqt.fgemm_pack_side(A, 3, 0, plan=plan), dqt.fgemm_pack_side(B, 3, 1, plan=plan)
+        dqt.fgemm_packed(CA, CB, 3, 33, 130, 0, plan=plan, out=C)
+        assert (to_host(C) == 0).all(), plan

@@ -298,3 +298,18 @@ def test_check_input_and_debug_mode(dqt):
             dqt.fgemm(A, A, 7)
     finally:
         dqt.DEBUG = old
+
+
+def test_empty_batches_every_entry(dqt):
+    """count = 0 is a no-op for every batched entry point (empty outputs of the right shape)."""
+    import torch
+    dev = device()
+    z4, z10, z5 = (torch.zeros((0, k), dtype=torch.uint8, device=dev) for k in (4, 10, 5))
+    assert dqt.polymul_plain_u8(z4, z4, 3).shape == (0, 7)
+    assert dqt.polymul_fqt_u8(z10, z10, 3).shape == (0, 19)
+    assert dqt.polymul_fqt_kara_u8(z10, z10, 3).shape == (0, 19)
+    P = inputs.irreducible(3, 5)
+    assert dqt.gf_mul_u8(z5, z5, 3, P).shape == (0, 5)
+    assert dqt.gf_mul_plain_u8(z5, z5, 3, P).shape == (0, 5)
+    zd = torch.zeros((0, 3, 5), dtype=torch.uint8, device=dev)
+    assert dqt.gf_dot_u8(zd, zd, 3, P).shape == (0, 5)

@@ -227,8 +227,10 @@ typedef enum dqt_gemm_algo {
     DQT_GEMM_RIGHT = 5,     /* right compressed (section 7.4): e columns of B per binary64 word, A
                                uncompressed, product on the FP64 matrix cores, one REDQ_e per word */
     DQT_GEMM_LEFT = 6,      /* left compressed (section 7.4, the transpose): e rows of A per word */
-    DQT_GEMM_FULL = 7       /* full compression (section 7.5): 2 rows of A in powers of Q times e_c
+    DQT_GEMM_FULL = 7,      /* full compression (section 7.5): 2 rows of A in powers of Q times e_c
                                columns of B in powers of Theta = Q^2, 2 e_c digits per word */
+    DQT_GEMM_BY_SHAPE = 8   /* the rule of section 7.6.2: CMM (as AUTO) when kdim is the largest
+                               dimension, RIGHT when n is, LEFT when m is */
 } dqt_gemm_algo;
 
 typedef enum dqt_gemm_epilogue {

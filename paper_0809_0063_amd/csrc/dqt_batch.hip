@@ -123,7 +123,7 @@ static BatchLayout batch_layout(const dqt_gemm_desc* descs, uint32_t count, uint
         pl.tile_rows = tm;
         pl.tile_cols = tn;
         pl.ksplit = s;
-        if (d.algo == DQT_GEMM_MFMA || is_f64_algo(d.algo)) {
+        if (d.algo == DQT_GEMM_MFMA || is_f64_algo(d.algo) || d.algo == DQT_GEMM_BY_SHAPE) {
             *st = DQT_E_UNSUPPORTED;
             return L;
         }

@@ -22,7 +22,7 @@
 // per instruction) issue far fewer instructions per multiply-add than the
 // vector units, and each multiply-add here carries e_r e_c F_p multiply-adds.
 //
-// Device layouts (workspace), Left and Full:
+// Device layouts (workspace), Full:
 //   Ad: [Mw_pad/16][K_pad/4][64] binary64, lane l of a 16x4 block holding
 //       word row l%16 at k = l/16 (the matrix-core A operand layout);
 //   Bd: [Nw_pad/16][K_pad/4][64] binary64, lane l holding k = l/16 of word
@@ -33,6 +33,9 @@
 // lane group g = l/16), so that lane l reads the four A entries of its four
 // steps as one dword.  Bd: [Nw_pad/16][K_pad/16][4][64] binary64, step s of
 // group c, lane l holding k = 16c + 4(l/16) + s of word column l%16.
+// Left runs the same kernel on the transpose, C^T = B^T A^T: B^T as the
+// uint8 operand ([N_pad][K_pad], in the B half of the workspace) and the
+// words of e rows of A in the step layout (in the A half).
 // The accumulator of a 16x16 block holds, in lane l and element r, word row
 // l/16 + 4r and word column l%16.
 
@@ -56,6 +59,7 @@ struct F64Args {
     uint32_t ks_split;     // k-steps per wave
     uint32_t nrb;          // row blocks of the grid (Mw_pad / (16 TR))
     uint32_t er, ec;       // rows / columns per word
+    uint32_t trans;        // Left through the uint8 kernel: X = B^T, words of e rows of A, C transposed
     RedqArgs ra;           // REDQ_(er ec) of a word of CC
 };
 
@@ -98,6 +102,39 @@ __global__ __launch_bounds__(256) void k_f64_pack_right(F64PackArgs a) {
                     if (col < a.n) w |= (uint64_t)a.B[(size_t)k * a.ldb + col] << (a.b * x);
                 }
             a.Bd[u] = (double)w;
+        }
+    }
+}
+
+// Left through the same kernel as Right, transposed (C^T = B^T A^T): B^T
+// copied as uint8 [N_pad][K_pad] (column j of B becomes row j), and e rows of
+// A packed per binary64 word in the step layout, word i' at k holding
+// sum_t A[e i' + t][k] Q^t.
+__global__ __launch_bounds__(256) void k_f64_pack_left(F64PackArgs a) {
+    const uint32_t kp = a.nks * 4;
+    const uint64_t nbd = a.nb / 4;           // dwords of the B^T copy
+    const uint64_t total = a.na + nbd;
+    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < total; t += (uint64_t)gridDim.x * 256) {
+        if (t < a.na) {
+            const uint32_t l = (uint32_t)(t & 63), st = (uint32_t)((t >> 6) & 3);
+            const uint64_t q = t >> 8;
+            const uint32_t c = (uint32_t)(q % (kp / 16)), rb = (uint32_t)(q / (kp / 16));
+            const uint32_t iw = rb * 16 + (l & 15), k = 16 * c + 4 * (l >> 4) + st;
+            uint64_t w = 0;
+            if (k < a.kdim)
+                for (uint32_t x = 0; x < a.er; ++x) {
+                    const uint32_t row = iw * a.er + x;
+                    if (row < a.m) w |= (uint64_t)a.A[(size_t)row * a.lda + k] << (a.b * x);
+                }
+            a.Ad[t] = (double)w;
+        } else {
+            const uint64_t u = t - a.na;
+            const uint32_t col = (uint32_t)(u / (kp / 4)), k0 = (uint32_t)(u % (kp / 4)) * 4;
+            uint32_t d = 0;
+            if (col < a.n)
+                for (uint32_t x = 0; x < 4; ++x)
+                    if (k0 + x < a.kdim) d |= (uint32_t)a.B[(size_t)(k0 + x) * a.ldb + col] << (8 * x);
+            reinterpret_cast<uint32_t*>(a.Bd)[u] = d;
         }
     }
 }
@@ -312,15 +349,27 @@ __global__ __launch_bounds__(64 * KS) void k_f64_right(F64Args g) {
         }
     }
     const RedqArgs& ra = g.ra;
-    const uint32_t nd = g.ec;
+    const uint32_t nd = g.er * g.ec;   // one of them is 1
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         if (KS > 1 && (uint32_t)q % KS != wave) continue;
         const int t = q / 4, e = q % 4;
-        const uint32_t row = (rb * TR + t / TC) * 16 + (lane >> 4) + 4 * e;
-        const uint32_t jw = (cb * TC + t % TC) * 16 + (lane & 15u);
-        if (row >= g.m) continue;
+        const uint32_t row = (rb * TR + t / TC) * 16 + (lane >> 4) + 4 * e;   // row of X
+        const uint32_t jw = (cb * TC + t % TC) * 16 + (lane & 15u);           // word column
+        if (row >= (g.trans ? g.n : g.m)) continue;
         const uint64_t U = redq_compress((uint64_t)v[q], ra);
+        if (g.trans) {
+            // digit d of word jw is the output at row e jw + d, column `row`
+            uint32_t prev = field(U, 0, ra);
+            for (uint32_t d = 0; d < nd; ++d) {
+                const uint32_t next = d + 1 < nd ? field(U, d + 1, ra) : 0;
+                const uint32_t mu = (ra.c && d + 1 < nd) ? correct_arith(prev, next, ra) : prev;
+                prev = next;
+                const uint32_t orow = jw * nd + d;
+                if (orow < g.m) g.C[(size_t)orow * g.ldc + row] = (uint8_t)mu;
+            }
+            continue;
+        }
         uint8_t* out = g.C + (size_t)row * g.ldc + jw * nd;
         uint32_t prev = field(U, 0, ra);
         if (nd == 4 && jw * 4 + 3 < g.n && ((uintptr_t)out & 3) == 0) {
@@ -380,19 +429,19 @@ dqt_status f64_plan(uint32_t algo, uint32_t p, uint64_t m, uint64_t n, uint64_t 
     const uint64_t Mw = (m + r->er - 1) / r->er, Nw = (n + r->ec - 1) / r->ec;
     r->m_pad = (uint32_t)rup(Mw ? Mw : 1, 16 * r->tm);
     r->n_pad = (uint32_t)rup(Nw ? Nw : 1, 16 * r->tn);
-    const uint32_t kq = algo == DQT_GEMM_RIGHT ? 16 : 4;   // k padding (Right: groups of 16)
+    const bool u8x = algo == DQT_GEMM_RIGHT || algo == DQT_GEMM_LEFT;   // one operand read as uint8
+    const uint32_t kq = u8x ? 16 : 4;   // k padding (uint8 operand: groups of 16)
     const uint64_t kpad = (kdim + kq - 1) / kq * kq;
     r->k_pad = (uint32_t)(kpad ? kpad : kq);
     if (want_ks) {
-        if (want_ks != 1 && want_ks != 2 && want_ks != 4 && want_ks != 8 &&
-            !(want_ks == 16 && algo == DQT_GEMM_RIGHT))
+        if (want_ks != 1 && want_ks != 2 && want_ks != 4 && want_ks != 8 && !(want_ks == 16 && u8x))
             return DQT_E_INVALID;
         r->s = want_ks;
     } else {
         // enough waves for the chip: k split across up to 8 waves of a workgroup
         const uint64_t blocks = (uint64_t)(r->m_pad / (16 * r->tm)) * (r->n_pad / (16 * r->tn));
         r->s = 1;
-        if (algo == DQT_GEMM_RIGHT)
+        if (u8x)
             while (r->s < 16 && blocks * r->s < 4096 && (r->k_pad / 16) / (r->s * 2) >= 2) r->s *= 2;
         else
             while (r->s < 8 && blocks * r->s < 2048 && (r->k_pad / 4) / (r->s * 2) >= 8) r->s *= 2;
@@ -403,6 +452,7 @@ dqt_status f64_plan(uint32_t algo, uint32_t p, uint64_t m, uint64_t n, uint64_t 
 
 size_t f64_side_bytes(const GemmPlanResolved& r, int side) {
     if (side == 0 && r.algo == DQT_GEMM_RIGHT) return ((size_t)r.m_pad * r.k_pad + 15) / 16 * 16;  // uint8 copy of A
+    if (side == 1 && r.algo == DQT_GEMM_LEFT) return ((size_t)r.n_pad * r.k_pad + 15) / 16 * 16;   // uint8 B^T
     return (size_t)(side == 0 ? r.m_pad : r.n_pad) * r.k_pad * sizeof(double);
 }
 
@@ -436,14 +486,19 @@ dqt_status f64_pack_enqueue(const GemmPlanResolved& r, uint64_t m, uint64_t n, u
     a.lda = (uint32_t)lda;
     a.ldb = (uint32_t)ldb;
     a.nks = r.k_pad / 4;
-    a.na = A ? (uint64_t)r.m_pad * r.k_pad : 0;
-    a.nb = B ? (uint64_t)r.n_pad * r.k_pad : 0;
+    a.na = A ? (uint64_t)r.m_pad * r.k_pad : 0;   // Right: bytes of the uint8 copy; else doubles
+    a.nb = B ? (uint64_t)r.n_pad * r.k_pad : 0;   // Left: bytes of the uint8 B^T; else doubles
     a.er = r.er;
     a.ec = r.ec;
     a.b = r.b;
     if (a.na + a.nb == 0) return DQT_OK;
     if (r.algo == DQT_GEMM_RIGHT) {
         hipLaunchKernelGGL(k_f64_pack_right, dim3(stream_grid(a.na / 4 + a.nb, 256, 8)), dim3(256), 0, s, a);
+        DQT_LAUNCH_CHECK("fgemm(f64 pack)");
+        return DQT_OK;
+    }
+    if (r.algo == DQT_GEMM_LEFT) {
+        hipLaunchKernelGGL(k_f64_pack_left, dim3(stream_grid(a.na + a.nb / 4, 256, 8)), dim3(256), 0, s, a);
         DQT_LAUNCH_CHECK("fgemm(f64 pack)");
         return DQT_OK;
     }
@@ -463,14 +518,23 @@ dqt_status f64_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t m
     g.n = (uint32_t)n;
     g.ldc = (uint32_t)ldc;
     g.nks = r.k_pad / 4;
-    g.ks_split = r.algo == DQT_GEMM_RIGHT ? (r.k_pad / 16 + r.s - 1) / r.s : (g.nks + r.s - 1) / r.s;
+    const bool u8x = r.algo == DQT_GEMM_RIGHT || r.algo == DQT_GEMM_LEFT;
+    g.ks_split = u8x ? (r.k_pad / 16 + r.s - 1) / r.s : (g.nks + r.s - 1) / r.s;
     g.nrb = r.m_pad / (16 * r.tm);
     g.er = r.er;
     g.ec = r.ec;
     const uint32_t nd = r.er * r.ec;
     DQT_TRY(make_redq_args(p, r.b, nd, nd * r.b, &g.ra));
-    const unsigned grid = g.nrb * (r.n_pad / (16 * r.tn));
-    if (r.algo == DQT_GEMM_RIGHT) {
+    unsigned grid = g.nrb * (r.n_pad / (16 * r.tn));
+    if (r.algo == DQT_GEMM_LEFT) {
+        // the uint8 operand (rows of the kernel's X) is B^T; the words are the packed rows of A
+        g.trans = 1;
+        g.Ad = reinterpret_cast<const double*>(pB);
+        g.Bd = reinterpret_cast<const double*>(pA);
+        g.nrb = r.n_pad / (16 * r.tn);
+        grid = g.nrb * (r.m_pad / (16 * r.tm));
+    }
+    if (u8x) {
         switch (r.s) {
             case 1: launch_f64_right<1>(g, grid, s, e0, e1); break;
             case 2: launch_f64_right<2>(g, grid, s, e0, e1); break;

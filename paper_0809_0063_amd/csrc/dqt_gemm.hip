@@ -281,6 +281,17 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
     if (p < 2 || p > 255) return DQT_E_INVALID;
     if (m > 0x7FFFFFFFull || n > 0x7FFFFFFFull || kdim > 0x7FFFFFFFull) return DQT_E_INVALID;
     uint32_t algo = pl.algo;
+    if (algo == DQT_GEMM_BY_SHAPE) {
+        // section 7.6.2: the middle product when the common dimension is the
+        // largest, Right compression when n is, Left compression when m is
+        // (each when its words hold at least two digits)
+        uint32_t pick = DQT_GEMM_AUTO;
+        if (kdim < m || kdim < n) pick = n >= m ? DQT_GEMM_RIGHT : DQT_GEMM_LEFT;
+        if (pick != DQT_GEMM_AUTO && f64_plan(pick, p, m, n, kdim, pl.log2Q, pl.ksplit, r) == DQT_OK) return DQT_OK;
+        memset(r, 0, sizeof(*r));
+        algo = DQT_GEMM_AUTO;
+        pl.log2Q = 0;
+    }
     if (is_f64_algo(algo)) return f64_plan(algo, p, m, n, kdim, pl.log2Q, pl.ksplit, r);
     uint32_t b = 0, interval = 0;
     const bool cmm_ok = cmm_params(p, kdim, pl.interval, pl.log2Q, &b, &interval);

@@ -22,6 +22,7 @@ DQT_OK, DQT_E_INVALID, DQT_E_BOUND, DQT_E_UNSUPPORTED, DQT_E_DEVICE, DQT_E_WORKS
 DEBUG = os.environ.get("DQT_DEBUG", "") not in ("", "0")
 
 GEMM_AUTO, GEMM_CMM, GEMM_PLAIN, GEMM_DOT4, GEMM_MFMA, GEMM_RIGHT, GEMM_LEFT, GEMM_FULL = 0, 1, 2, 3, 4, 5, 6, 7
+GEMM_BY_SHAPE = 8
 EPI_REDC, EPI_REDQ = 0, 1
 
 

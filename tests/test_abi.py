@@ -134,7 +134,7 @@ def test_compressed_f64_plan_sizes(D):
     ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_RIGHT))
     assert ws == 1024 * 1024 + 256 * 1024 * 8     # A uncompressed (uint8), B four columns per binary64 word
     ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_LEFT))
-    assert ws == (256 + 1024) * 1024 * 8
+    assert ws == 256 * 1024 * 8 + 1024 * 1024     # A four rows per binary64 word, B^T uncompressed (uint8)
     ws = D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=D.GEMM_FULL))
     assert ws == (512 + 512) * 1024 * 8           # two rows and two columns per word
     # fewer than two digits per word: unsupported (size 0); FULL needs four
@@ -152,3 +152,14 @@ def test_input_status(D):
     assert lib.dqt_check_input_u8(None, 10, 3, None, None) == D.DQT_E_INVALID
     assert lib.dqt_check_input_u8(None, 0, 3, None, None) == D.DQT_E_INVALID
     assert lib.dqt_check_input_u8(None, 10, 1, None, None) == D.DQT_E_INVALID
+
+
+def test_shape_rule_picks_by_largest_dimension(D):
+    """Section 7.6.2: middle product when k is the largest dimension, Right when n is, Left when m is."""
+    ws = lambda m, n, k, a: D.fgemm_workspace_size(3, m, n, k, D.GemmPlan(algo=a))
+    for (m, n, k, want) in ((64, 1024, 256, D.GEMM_RIGHT), (1024, 64, 256, D.GEMM_LEFT),
+                            (64, 64, 1024, D.GEMM_AUTO), (300, 300, 300, D.GEMM_AUTO)):
+        assert ws(m, n, k, D.GEMM_BY_SHAPE) == ws(m, n, k, want), (m, n, k)
+    # no two digits fit a binary64 word: the middle product (or plain) path instead
+    assert D.fgemm_workspace_size(251, 8, 4096, 1 << 20, D.GemmPlan(algo=D.GEMM_BY_SHAPE)) == \
+        D.fgemm_workspace_size(251, 8, 4096, 1 << 20, D.GemmPlan(algo=D.GEMM_AUTO))

@@ -220,7 +220,7 @@ def test_compressed_f64_ragged_and_bounds(dqt, p):
         dA, dB = to_dev(A), to_dev(B)
         for plan in _f64_plans(dqt, p, k):
             for ks in (0, 1, 8, 16):
-                if ks == 16 and plan.algo != dqt.GEMM_RIGHT:
+                if ks == 16 and plan.algo == dqt.GEMM_FULL:
                     continue
                 pl = dqt.GemmPlan(algo=plan.algo, ksplit=ks)
                 got = to_host(dqt.fgemm(dA, dB, p, plan=pl))
@@ -280,3 +280,11 @@ def test_fgemm_empty_dimensions(dqt):
         CA, CB = dqt.fgemm_pack_side(A, 3, 0, plan=plan), dqt.fgemm_pack_side(B, 3, 1, plan=plan)
         dqt.fgemm_packed(CA, CB, 3, 33, 130, 0, plan=plan, out=C)
         assert (to_host(C) == 0).all(), plan
+
+
+def test_shape_rule_products(dqt):
+    """The shape rule's choice on rectangular products gives the oracle's bytes."""
+    for (m, n, k, p) in ((40, 700, 130, 3), (700, 40, 130, 5), (50, 60, 900, 7), (33, 513, 64, 2)):
+        A, B = inputs.gemm_pair(m, n, k, p, seed=m + n + k)
+        got = to_host(dqt.fgemm(to_dev(A), to_dev(B), p, plan=dqt.GemmPlan(algo=dqt.GEMM_BY_SHAPE)))
+        assert (got == O.fgemm(A, B, p)).all(), (m, n, k, p)

@@ -891,7 +891,7 @@ static dqt_status launch_gf_fused(const uint8_t* A, const uint8_t* B, uint64_t c
         DQT_LAUNCH_CHECK("dqt_gf_mul_u8");
         return DQT_OK;
     }
-    const unsigned grid = stream_grid((count + 3) / 4, 256, 4);
+    const unsigned grid = stream_grid((count + 3) / 4, 256, 8);
     // compile-time q and residue width for GF(3^5) at q = 2^5 and GF(7^3) at q = 2^7
     if constexpr (K == 5) {
         if (ra.b == 5 && ra.w == 2 && ra.small && mul_mode(K, ra.b, ra.w) == MUL24) {

@@ -109,7 +109,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md and not run here", file=sys.stderr)
+              "the multi-GPU layout is a design, not run here", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

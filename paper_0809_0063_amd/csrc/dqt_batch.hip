@@ -55,16 +55,26 @@ __global__ __launch_bounds__(256) void k_batch_pack(const BatchHeader* __restric
     if (blockIdx.x == 0 && threadIdx.x == 0) hdr_w->counter = 0;
     const uint32_t nd = hdr->n_desc;
     const uint32_t total = hdr->total_pack_blocks;
-    for (uint32_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
-        // product owning this block: prefix[d] <= blk < prefix[d+1]
-        uint32_t lo = 0, hi = nd;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (prefix[mid] <= blk) lo = mid;
-            else hi = mid;
+    // each workgroup packs one contiguous range of blocks: one binary search
+    // for the product owning its first block, then a forward walk
+    const uint32_t chunk = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t b0 = blockIdx.x * chunk, b1 = min(total, b0 + chunk);
+    if (b0 >= b1) return;
+    uint32_t lo = 0, hi = nd;   // prefix[lo] <= b0 < prefix[lo + 1]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b0) lo = mid;
+        else hi = mid;
+    }
+    uint32_t d = __builtin_amdgcn_readfirstlane(lo);
+    uint32_t dend = prefix[d + 1];
+    PackArgs pk = descs[d].pk;
+    for (uint32_t blk = b0; blk < b1; ++blk) {
+        while (blk >= dend) {   // next product (empty ones are skipped)
+            ++d;
+            dend = prefix[d + 1];
+            pk = descs[d].pk;
         }
-        const uint32_t d = __builtin_amdgcn_readfirstlane(lo);
-        const PackArgs pk = descs[d].pk;
         gemm_pack_block(pk, blk - prefix[d], threadIdx.x);
     }
 }

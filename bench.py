@@ -216,6 +216,15 @@ def main():
             s = timed_loop(fn, reps_big, 2, torch)
             extra["polymul_deg3_f3_" + name] = {"polymul_s": round(n / s, 1), "GB_s": round(15 * n / s / 1e9, 1),
                                                 "hbm_frac": round(15 * n / s / PEAK_HBM, 4)}
+        # the correction-table window (section 3.5): none, two or three residues per lookup
+        try:
+            for j in (1, 2, 3):
+                D.set_table_window(j)
+                s = timed_loop(lambda: D.polymul_u8(da, db, 3, out=out, log2q=6), reps_big, 2, torch)
+                extra[f"polymul_deg3_f3_table_window_{j}"] = {"GB_s": round(15 * n / s / 1e9, 1),
+                                                              "hbm_frac": round(15 * n / s / PEAK_HBM, 4)}
+        finally:
+            D.set_table_window(0)
         a65, b65 = inputs.polymul_pairs(65536, 4, 3)
         d65a, d65b = torch.from_numpy(a65).to(dev), torch.from_numpy(b65).to(dev)
         o65 = torch.empty((65536, 7), dtype=torch.uint8, device=dev)

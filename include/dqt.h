@@ -54,6 +54,20 @@ const char *dqt_last_error(void);
 const char *dqt_version(void);
 
 /*
+ * REDQ correction tables (section 3.5, the time-memory trade-off): the
+ * correction mu_i = (u_i - (q mod p) u_{i+1}) mod p is read from an LDS table
+ * indexed by a window of j consecutive residues (2^(j ceil(log2 p)) entries,
+ * j-1 corrected residues per lookup) or computed arithmetically.
+ * dqt_set_table_window(j) applies to the calls that follow, process-wide:
+ * 0 = automatic (the largest of 3, 2 whose table has at most 4096 entries),
+ * 1 = no table, 2 = windows of two residues at most, 3 = three at most
+ * (each falls back to a smaller window when its table would not fit).
+ * DQT_E_INVALID for j > 3.  Results are identical for every j.
+ */
+dqt_status dqt_set_table_window(uint32_t j);
+uint32_t dqt_get_table_window(void);
+
+/*
  * Input validation (debug mode).  The packed paths assume every entry is a
  * residue in [0, p): the a priori bounds (eq:bounds, eq:lower) are stated for
  * entries at most p-1, and a larger entry silently breaks them.  This call

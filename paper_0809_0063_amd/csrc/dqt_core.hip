@@ -8,6 +8,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+
 #include <mutex>
 #include <string>
 
@@ -119,6 +121,9 @@ static double inverse_rounded_up(uint32_t p) {
     return v;
 }
 
+// Correction-table window chosen by dqt_set_table_window (0 = automatic).
+static std::atomic<uint32_t> g_table_window{0};
+
 dqt_status make_redq_args(uint32_t p, uint32_t b, uint32_t nres, uint32_t word_bits, RedqArgs* out) {
     if (p < 2 || p > 255 || b < 1 || b > 32 || nres < 1 || nres > 53 || !out) return DQT_E_INVALID;
     if ((uint64_t)nres * b > 53 || word_bits > 53) return DQT_E_BOUND;
@@ -144,10 +149,13 @@ dqt_status make_redq_args(uint32_t p, uint32_t b, uint32_t nres, uint32_t word_b
     }
     if (a.swar && b * (nres - 1) + 2 * a.w >= 64) return DQT_E_BOUND;
     a.pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
-    // Correction table window: the largest of 3, 2 whose table fits 4096 entries.
-    if (a.c == 0 || nres == 1) {
+    // Correction table window (section 3.5): by default the largest of 3, 2
+    // whose table fits 4096 entries; dqt_set_table_window caps it (1: no
+    // table, the correction computed arithmetically).
+    const uint32_t cap = g_table_window.load(std::memory_order_relaxed);
+    if (a.c == 0 || nres == 1 || cap == 1) {
         a.tabj = 0;
-    } else if (3 * a.w <= 12 && nres >= 3) {
+    } else if (3 * a.w <= 12 && nres >= 3 && cap != 2) {
         a.tabj = 3;
     } else if (2 * a.w <= 12) {
         a.tabj = 2;
@@ -215,6 +223,14 @@ extern "C" dqt_status dqt_check_input_u8(const uint8_t* d_x, uint64_t count, uin
 }
 
 extern "C" const char* dqt_version(void) { return "libdqt 0.1 gfx950"; }
+
+extern "C" dqt_status dqt_set_table_window(uint32_t j) {
+    if (j > 3) return DQT_E_INVALID;
+    g_table_window.store(j, std::memory_order_relaxed);
+    return DQT_OK;
+}
+
+extern "C" uint32_t dqt_get_table_window(void) { return g_table_window.load(std::memory_order_relaxed); }
 
 extern "C" dqt_status dqt_qadic_check(const dqt_qadic* a) {
     if (!a) return DQT_E_INVALID;

@@ -139,6 +139,11 @@ def _load():
     if hasattr(lib, "dqt_fgemm_packed_bytes"):
         lib.dqt_fgemm_packed_bytes.argtypes = [U32, U64, U64, I, ctypes.POINTER(_GemmPlan)]
         lib.dqt_fgemm_packed_bytes.restype = SZ
+    if hasattr(lib, "dqt_set_table_window"):
+        lib.dqt_set_table_window.argtypes = [U32]
+        lib.dqt_set_table_window.restype = ctypes.c_int
+        lib.dqt_get_table_window.argtypes = []
+        lib.dqt_get_table_window.restype = U32
     if hasattr(lib, "dqt_batch_free"):
         lib.dqt_batch_free.argtypes = [V]
         lib.dqt_batch_free.restype = None
@@ -185,6 +190,15 @@ def _dev(t: torch.Tensor, name: str, dtype=None) -> ctypes.c_void_p:
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def set_table_window(j: int) -> None:
+    """REDQ correction-table window for the calls that follow (0 auto, 1 none, 2, 3)."""
+    _check(_load().dqt_set_table_window(j), "dqt_set_table_window")
+
+
+def get_table_window() -> int:
+    return int(_load().dqt_get_table_window())
 
 
 _FLAG = {}

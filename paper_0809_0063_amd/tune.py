@@ -141,6 +141,33 @@ def _time_plan(p: int, n: int, plan: BucketPlan, reps: int = 20, launch=(16, 4))
     return e0.elapsed_time(e1) * 1e3 / reps / count
 
 
+def time_table_windows(p: int, k: int, count: int = 1 << 22, reps: int = 5) -> Dict[int, float]:
+    """Microseconds per call of the fused one-word polynomial product for each REDQ
+    correction-table window (1 = none, 2, 3; section 3.5's time-memory trade-off)."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device="cpu").manual_seed(4321 + p * 10 + k)
+    a = torch.randint(0, p, (count, k), dtype=torch.uint8, generator=g).to(dev)
+    b = torch.randint(0, p, (count, k), dtype=torch.uint8, generator=g).to(dev)
+    out = torch.empty((count, 2 * k - 1), dtype=torch.uint8, device=dev)
+    res = {}
+    try:
+        for j in (1, 2, 3):
+            D.set_table_window(j)
+            for _ in range(2):
+                D.polymul_u8(a, b, p, out=out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                D.polymul_u8(a, b, p, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            res[j] = e0.elapsed_time(e1) * 1e3 / reps
+    finally:
+        D.set_table_window(0)
+    return res
+
+
 class Tuner:
     def __init__(self, cache_path: Optional[str] = DEFAULT_CACHE):
         self.cache_path = cache_path

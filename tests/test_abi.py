@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "dqt.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?(?:dqt_status|size_t|const char\s*\*|char\s*\*|void)\s*\*?\s*(\w+)\s*\(",
+    names = re.findall(r"^\s*(?:const\s+)?(?:dqt_status|size_t|uint32_t|const char\s*\*|char\s*\*|void)\s*\*?\s*(\w+)\s*\(",
                        text, re.M)
     return sorted(set(names))
 
@@ -163,3 +163,15 @@ def test_shape_rule_picks_by_largest_dimension(D):
     # no two digits fit a binary64 word: the middle product (or plain) path instead
     assert D.fgemm_workspace_size(251, 8, 4096, 1 << 20, D.GemmPlan(algo=D.GEMM_BY_SHAPE)) == \
         D.fgemm_workspace_size(251, 8, 4096, 1 << 20, D.GemmPlan(algo=D.GEMM_AUTO))
+
+
+def test_table_window_setting(D):
+    assert D.get_table_window() == 0
+    for j in (1, 2, 3, 0):
+        D.set_table_window(j)
+        assert D.get_table_window() == j
+    with pytest.raises(D.DQTError) as e:
+        D.set_table_window(4)
+    assert e.value.status == D.DQT_E_INVALID
+    assert D.get_table_window() == 0
+    assert "dqt_get_table_window" in declared_functions()

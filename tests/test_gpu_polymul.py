@@ -313,3 +313,21 @@ def test_empty_batches_every_entry(dqt):
     assert dqt.gf_mul_plain_u8(z5, z5, 3, P).shape == (0, 5)
     zd = torch.zeros((0, 3, 5), dtype=torch.uint8, device=dev)
     assert dqt.gf_dot_u8(zd, zd, 3, P).shape == (0, 5)
+
+
+@pytest.mark.parametrize("j", [1, 2, 3])
+def test_table_windows_give_identical_bytes(dqt, j):
+    """Section 3.5: every correction-table window (none, 2, 3 residues) gives the oracle's bytes."""
+    try:
+        dqt.set_table_window(j)
+        for (p, k) in ((3, 4), (5, 3), (7, 3), (2, 6), (13, 2)):
+            a, b = inputs.polymul_pairs(3001, k, p, seed=j * 100 + p)
+            assert (to_host(dqt.polymul_u8(to_dev(a), to_dev(b), p)) == O.polymul(a, b, p)).all(), (j, p, k)
+        for (p, k) in ((3, 5), (7, 3)):
+            P = inputs.irreducible(p, k)
+            x, y = inputs.gf_pairs(3001, k, p)
+            assert (to_host(dqt.gf_mul_u8(to_dev(x), to_dev(y), p, P)) == O.gf_mul(x, y, p, P)).all(), (j, p, k)
+        a, b = inputs.polymul_pairs(501, 30, 5, seed=j, kb=17)
+        assert (to_host(dqt.polymul_fqt_u8(to_dev(a), to_dev(b), 5)) == O.polymul(a, b, 5)).all()
+    finally:
+        dqt.set_table_window(0)

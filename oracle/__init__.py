@@ -452,6 +452,38 @@ def fgdp_reduce(u: Sequence[int], q: int, p: int, modulus: Sequence[int]) -> Lis
     return [(x + y) % p for x, y in zip(h, low)]
 
 
+# --- Compressed matrix products (section 7.4, 7.5): the words, by definition ----
+
+def compressed_words(A: Sequence[Sequence[int]], B: Sequence[Sequence[int]], er: int, ec: int,
+                     logQ: int) -> List[List[int]]:
+    """CC = CA x CB as exact integers, with CA packing er consecutive rows of A in
+    powers of Q and CB packing ec consecutive columns of B in powers of Theta =
+    Q^er (section 7.5; er = 1 is Right compression, ec = 1 Left, section 7.4).
+    Small inputs only (pure Python)."""
+    Q = 1 << logQ
+    theta = Q ** er
+    m, k, n = len(A), len(B), len(B[0]) if B else 0
+    mw, nw = -(-m // er), -(-n // ec)
+    CA = [[sum((A[i * er + s][l] if i * er + s < m else 0) * Q ** s for s in range(er)) for l in range(k)]
+          for i in range(mw)]
+    CB = [[sum((B[l][j * ec + t] if j * ec + t < n else 0) * theta ** t for t in range(ec)) for j in range(nw)]
+          for l in range(k)]
+    return [[sum(CA[i][l] * CB[l][j] for l in range(k)) for j in range(nw)] for i in range(mw)]
+
+
+def compressed_digits(CC: Sequence[Sequence[int]], er: int, ec: int, logQ: int, m: int, n: int) -> List[List[int]]:
+    """Read C back from the words: digit s + er t of word (i, j) is entry (er i + s, ec j + t)."""
+    C = [[0] * n for _ in range(m)]
+    for i, row in enumerate(CC):
+        for j, w in enumerate(row):
+            for s in range(er):
+                for t in range(ec):
+                    r, c = er * i + s, ec * j + t
+                    if r < m and c < n:
+                        C[r][c] = (w >> (logQ * (s + er * t))) & ((1 << logQ) - 1)
+    return C
+
+
 # --- A priori bounds (closed forms) -------------------------------------------
 
 def dqt_bounds_ok(p: int, k: int, n: int, logq: int, beta: int) -> bool:

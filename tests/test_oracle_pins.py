@@ -422,3 +422,33 @@ def test_gf_dot_pins():
                 pr = O.gf_mul_py(a[t, l].tolist(), b[t, l].tolist(), p, P)
                 acc = [(x + y) % p for x, y in zip(acc, pr)]
             assert d[t].tolist() == acc
+
+
+def test_compressed_products_digits_are_the_dot_products():
+    """Sections 7.4-7.5: with k (p-1)^2 < Q (eq:lower) and Theta = Q^er (eq:qtheta with equality), the
+    digits of every compressed word are exactly the integer dot products (Right, Left and Full), so
+    REDQ of the word gives C mod p; one Q smaller and the all-(p-1) case carries into the next digit."""
+    import random
+    rnd = random.Random(7)
+    for (p, m, n, k) in ((3, 5, 7, 9), (5, 4, 6, 11), (2, 3, 9, 30), (7, 6, 5, 4)):
+        A = [[rnd.randrange(p) for _ in range(k)] for _ in range(m)]
+        B = [[rnd.randrange(p) for _ in range(n)] for _ in range(k)]
+        exact = [[sum(A[i][l] * B[l][j] for l in range(k)) for j in range(n)] for i in range(m)]
+        logQ = (k * (p - 1) ** 2).bit_length()          # smallest Q with k (p-1)^2 < Q
+        for er, ec in ((1, 3), (3, 1), (2, 2), (2, 3)):
+            CC = O.compressed_words(A, B, er, ec, logQ)
+            got = O.compressed_digits(CC, er, ec, logQ, m, n)
+            assert got == exact, (p, er, ec)
+            # the word as the polynomial in Q and Theta of eq:dq
+            assert max(max(r) for r in CC) < (1 << logQ) ** (er * ec)
+            assert [[x % p for x in r] for r in got] == O.fgemm(np.array(A, np.uint8), np.array(B, np.uint8),
+                                                               p).tolist()
+        # worst case at the bound: all entries p-1, digits reach Q-1 only if Q > k (p-1)^2
+        if p > 2:
+            W = [[p - 1] * k for _ in range(2)]
+            Wt = [[p - 1] * 3 for _ in range(k)]
+            full = k * (p - 1) ** 2
+            assert O.compressed_digits(O.compressed_words(W, Wt, 1, 3, logQ), 1, 3, logQ, 2, 3) == [[full] * 3] * 2
+            small = full.bit_length() - 1       # 2^small <= k (p-1)^2: eq:lower violated
+            bad = O.compressed_digits(O.compressed_words(W, Wt, 1, 3, small), 1, 3, small, 2, 3)
+            assert bad != [[full] * 3] * 2          # the digit no longer fits: the result is lost

@@ -25,6 +25,11 @@
  *   runtime error; dqt_last_error() gives its text (thread-local).
  * - Calls on distinct streams with distinct output buffers may run
  *   concurrently.
+ * - The first call that enqueues work on a device runs a one-thread check on
+ *   the null stream and waits for it: REDQ's floor by one binary64 multiply
+ *   (section 4, case 2 of the FDIV table) needs round-to-nearest, and a device
+ *   in another rounding mode gets DQT_E_UNSUPPORTED from every later call.
+ *   Make that first call before capturing a stream into a graph.
  */
 #ifndef DQT_H
 #define DQT_H
@@ -144,7 +149,7 @@ dqt_status dqt_polymul(const uint64_t *d_a, const uint64_t *d_b, uint64_t count,
  * DQT_E_BOUND otherwise) and log2q >= ceil(log2 p) (DQT_E_UNSUPPORTED
  * otherwise); n_accum and the first part of eq:bounds are not used.
  * modulus == NULL: d_out uint8 [count][nres], d_out[t][i] = m_i mod p.
- * modulus != NULL (GF(p^k) reduction of algorithm FGDP, lines 3-6, theorem
+ * modulus != NULL (GF(p^k) reduction by two tables, algorithm FGDP, theorem
  * thm:fgdp): host pointer to k_coeffs+1 coefficients of a monic polynomial P
  * (modulus[k_coeffs] == 1), nres must be 2*k_coeffs-1, k_coeffs <= 6, and
  * d_out is uint8 [count][k_coeffs] = (sum_i m_i X^i mod p) mod P.
@@ -165,7 +170,7 @@ dqt_status dqt_polymul_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count
                           uint32_t log2q, uint8_t *d_out, void *stream);
 
 /*
- * Fused GF(p^k) product (section 6, algorithm FGDP lines 3-6 on single
+ * Fused GF(p^k) product (section 6, algorithm FGDP, its two-table reduction on single
  * products): d_a, d_b, d_out uint8 [count][k], modulus a host pointer to the
  * k+1 coefficients of a monic P (not checked for irreducibility: the result
  * is the product in F_p[X]/(P)).  2 <= k <= 6, k*ceil(log2 p) <= 12 (the two

@@ -432,7 +432,7 @@ def is_irreducible(modulus: Sequence[int], p: int) -> bool:
 
 
 def fgdp_reduce(u: Sequence[int], q: int, p: int, modulus: Sequence[int]) -> List[int]:
-    """Lines 4-6 of algorithm FGDP on compressed residues u_0 .. u_{2k-2} (theorem thm:fgdp).
+    """The two-table reduction of algorithm FGDP on compressed residues u_0 .. u_{2k-2} (theorem thm:fgdp).
 
     L is computed from (u_0 .. u_{k-1}) alone, H from (u_{k-1} .. u_{2k-2})
     alone, and R = H + L in the field.  This is the paper's two-table

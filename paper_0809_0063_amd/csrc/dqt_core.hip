@@ -47,12 +47,16 @@ static int g_dev_cus[kMaxDevices];
 
 // Reads the binary64 rounding field of the MODE register (bits 3:2; 0 = round
 // to nearest even) and computes one FDIV that is wrong in any other mode.
-__global__ void k_selfcheck(uint32_t* out, double invp, uint64_t r) {
+// The result lands in a file-scope device array (one per device), read back
+// with hipMemcpyFromSymbol, so the check allocates nothing.
+__device__ uint32_t g_selfcheck_out[2];
+
+__global__ void k_selfcheck(double invp, uint64_t r) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const uint32_t mode = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 1);  // MODE[3:0]
-        out[0] = (mode >> 2) & 3u;
+        g_selfcheck_out[0] = (mode >> 2) & 3u;
         const double x = (double)r * invp;
-        out[1] = (uint32_t)(uint64_t)__builtin_floor(x);
+        g_selfcheck_out[1] = (uint32_t)(uint64_t)__builtin_floor(x);
     }
 }
 
@@ -72,17 +76,15 @@ dqt_status ensure_device_ready() {
     int cus = 0;
     DQT_TRY(hip_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attribute"));
     g_dev_cus[dev] = cus > 0 ? cus : 1;
-    uint32_t* d = nullptr;
-    DQT_TRY(hip_status(hipMalloc(&d, 2 * sizeof(uint32_t)), "hipMalloc(selfcheck)"));
     // 3*(2^30 + 1) times the nearest binary64 to 1/3 (just below 1/3): the
     // product rounded to nearest is 2^30 + 1, rounded down it is below.
     const double invp = 1.0 / 3.0;
     const uint64_t r = 3ull * ((1ull << 30) + 1);
-    hipLaunchKernelGGL(k_selfcheck, dim3(1), dim3(64), 0, 0, d, invp, r);
+    hipLaunchKernelGGL(k_selfcheck, dim3(1), dim3(64), 0, 0, invp, r);
     uint32_t h[2] = {99, 0};
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost);
-    hipFree(d);
+    if (e == hipSuccess) e = hipStreamSynchronize(0);
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(h, HIP_SYMBOL(g_selfcheck_out), sizeof(h), 0, hipMemcpyDeviceToHost);
     DQT_TRY(hip_status(e, "selfcheck"));
     const uint32_t want = (uint32_t)(uint64_t)floor((double)r * invp);
     if (h[0] != 0 || h[1] != want) {

@@ -154,7 +154,7 @@ __device__ __forceinline__ void build_correction_table(uint16_t* tab, const Redq
 template <int B, int W>
 __host__ __device__ constexpr bool gather3_by_multiply() {
     if (B <= W || 2 * B + W > 32) return false;
-    int pos[9];
+    int pos[9] = {};
     int n = 0;
     for (int t = 0; t < 3; ++t)
         for (int u = 0; u < 3; ++u) pos[n++] = B * t + (B - W) * (2 - u);
@@ -242,7 +242,7 @@ __device__ __forceinline__ void put_byte(uint32_t* w, int pos, uint32_t v) {
 template <int B, int W>
 __host__ __device__ constexpr bool pack4_by_multiply() {
     if (B > 8 || B <= 0 || W <= 0) return false;
-    int pos[16];
+    int pos[16] = {};
     int n = 0;
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) pos[n++] = 8 * i + (8 - B) * (3 - j);

@@ -639,36 +639,35 @@ __global__ __launch_bounds__(256) void k_polymul_plain(const uint8_t* __restrict
     }
 }
 
-// Generic plain product for any k (one product per thread, runtime loops).
-// Plain products of any degree: the 256 products of a block are staged in
-// LDS with coalesced copies (each operand byte is then read from LDS by the
-// schoolbook loops), one reduction per output coefficient.
-__global__ __launch_bounds__(256) void k_polymul_plain_any(const uint8_t* __restrict__ A, uint32_t ka,
-                                                           const uint8_t* __restrict__ B, uint32_t kb,
-                                                           uint8_t* __restrict__ OUT, uint64_t count, uint32_t p,
-                                                           uint32_t pmagic) {
-    extern __shared__ uint8_t plain_smem[];
-    uint8_t* sx = plain_smem;              // [256][ka]
-    uint8_t* sy = plain_smem + 256 * ka;   // [256][kb]
-    const uint32_t nr = ka + kb - 1;
-    for (uint64_t t0 = blockIdx.x * 256ull; t0 < count; t0 += (uint64_t)gridDim.x * 256) {
-        const uint32_t nt = (uint32_t)min<uint64_t>(256, count - t0);
-        __syncthreads();
-        for (uint32_t e = threadIdx.x; e < nt * ka; e += 256) sx[e] = A[t0 * ka + e];
-        for (uint32_t e = threadIdx.x; e < nt * kb; e += 256) sy[e] = B[t0 * kb + e];
-        __syncthreads();
-        if (threadIdx.x >= nt) continue;
-        const uint8_t* x = sx + threadIdx.x * ka;
-        const uint8_t* y = sy + threadIdx.x * kb;
-        uint8_t* z = OUT + (t0 + threadIdx.x) * nr;
-        for (uint32_t j = 0; j < nr; ++j) {
-            uint32_t c = 0;
-            const uint32_t i0 = j + 1 > kb ? j + 1 - kb : 0;
-            const uint32_t i1 = j < ka - 1 ? j : ka - 1;
-            for (uint32_t i = i0; i <= i1; ++i) c += (uint32_t)x[i] * (uint32_t)y[j - i];
-            z[j] = (uint8_t)mod_small(c, p, pmagic);
+// Plain product of longer polynomials (9 <= k <= 64 coefficients, padded to
+// KMAX): the coefficients of both operands in registers, one v_mad_u32_u24
+// per coefficient product (delayed: the sum stays below 64 (p-1)^2 < 2^32),
+// one REDC per output coefficient; the records move through LDS in tiles of
+// 256 products as in the packed FQT kernels.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_polymul_plain_tiles(const uint8_t* __restrict__ A, uint32_t ka,
+                                                             const uint8_t* __restrict__ B, uint32_t kb,
+                                                             uint8_t* __restrict__ OUT, uint64_t count, uint32_t p,
+                                                             uint32_t pmagic) {
+    constexpr int ND = KMAX / 4;
+    constexpr int NO = (2 * KMAX - 1 + 3) / 4;
+    extern __shared__ uint32_t plain_smem[];
+    record_tiles<ND, ND, NO>(plain_smem, A, ka, B, kb, OUT, count,
+                             [&](const uint32_t (&xa)[ND], const uint32_t (&xb)[ND], uint32_t (&ob)[NO]) {
+        uint32_t x[KMAX], y[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+            x[i] = (xa[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+            y[i] = (xb[i >> 2] >> (8 * (i & 3))) & 0xFFu;
         }
-    }
+#pragma unroll
+        for (int j = 0; j < 2 * KMAX - 1; ++j) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int i = (j >= KMAX ? j - KMAX + 1 : 0); i <= (j < KMAX ? j : KMAX - 1); ++i) c += x[i] * y[j - i];
+            ob[j >> 2] |= mod_small(c, p, pmagic) << (8 * (j & 3));
+        }
+    });
 }
 
 // Plain GF(p^k) product: schoolbook with delayed sums, REDC per coefficient,
@@ -983,10 +982,22 @@ extern "C" dqt_status dqt_polymul_plain_u8(const uint8_t* d_a, const uint8_t* d_
         DQT_PLAIN_CASE(6)
         DQT_PLAIN_CASE(7)
         DQT_PLAIN_CASE(8)
-        default:
-            hipLaunchKernelGGL(k_polymul_plain_any, dim3(stream_grid(count, 256)), dim3(256), 256 * 2 * k, s, d_a, k, d_b,
-                               k, d_out,
-                               count, p, pmagic);
+        default: {
+            const dim3 grid(stream_grid(count, 256)), blk(256);
+            const size_t sm = record_tiles_smem(k, k);
+            if (k <= 16)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_plain_tiles<16>), grid, blk, sm, s, d_a, k, d_b, k, d_out,
+                                   count, p, pmagic);
+            else if (k <= 32)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_plain_tiles<32>), grid, blk, sm, s, d_a, k, d_b, k, d_out,
+                                   count, p, pmagic);
+            else if (k <= 48)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_plain_tiles<48>), grid, blk, sm, s, d_a, k, d_b, k, d_out,
+                                   count, p, pmagic);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_plain_tiles<64>), grid, blk, sm, s, d_a, k, d_b, k, d_out,
+                                   count, p, pmagic);
+        }
     }
 #undef DQT_PLAIN_CASE
     DQT_LAUNCH_CHECK("dqt_polymul_plain_u8");

@@ -265,4 +265,134 @@ __device__ __forceinline__ uint32_t pack4_multiply(uint32_t x) {
     return ((x * mul) >> sh) & m;
 }
 
+// Byte tiles through LDS for kernels whose per-thread records are long and
+// not word-aligned (one polynomial of 48 coefficients, a product of 95): a
+// workgroup of 256 threads moves the contiguous bytes of 256 records between
+// global memory and LDS with coalesced dword accesses, and each thread then
+// reads or writes its own record in LDS.  Tile byte j sits at L[skew + j]
+// with skew = (address of global byte 0) mod 4, so that the dwords line up
+// on both sides; L is 4-byte aligned and holds len + 4 bytes.  The head and
+// tail that do not fill a dword move byte by byte, so nothing outside
+// [src, src + len) is touched.  Every thread of the workgroup must call these
+// (the caller places the barriers).
+__device__ __forceinline__ uint32_t tile_skew(const void* p) { return (uint32_t)((uintptr_t)p & 3u); }
+
+__device__ __forceinline__ void tile_in(const uint8_t* __restrict__ src, uint32_t len, uint8_t* L) {
+    const uint32_t sk = tile_skew(src);
+    const uint32_t head = min(len, (4u - sk) & 3u);
+    const uint32_t nd = (len - head) >> 2;
+    const uint32_t tail = head + 4 * nd;
+    if (threadIdx.x < head) L[sk + threadIdx.x] = src[threadIdx.x];
+    const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src + head);
+    uint32_t* l32 = reinterpret_cast<uint32_t*>(L + sk + head);
+    for (uint32_t i = threadIdx.x; i < nd; i += 256) l32[i] = __builtin_nontemporal_load(s32 + i);
+    if (threadIdx.x < len - tail) L[sk + tail + threadIdx.x] = src[tail + threadIdx.x];
+}
+
+__device__ __forceinline__ void tile_out(const uint8_t* L, uint32_t len, uint8_t* __restrict__ dst) {
+    const uint32_t sk = tile_skew(dst);
+    const uint32_t head = min(len, (4u - sk) & 3u);
+    const uint32_t nd = (len - head) >> 2;
+    const uint32_t tail = head + 4 * nd;
+    if (threadIdx.x < head) dst[threadIdx.x] = L[sk + threadIdx.x];
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst + head);
+    const uint32_t* l32 = reinterpret_cast<const uint32_t*>(L + sk + head);
+    for (uint32_t i = threadIdx.x; i < nd; i += 256) __builtin_nontemporal_store(l32[i], d32 + i);
+    if (threadIdx.x < len - tail) dst[tail + threadIdx.x] = L[sk + tail + threadIdx.x];
+}
+
+// LDS bytes of one tile of n records of len bytes (with its skew slack), a
+// multiple of 4.
+__host__ __device__ inline uint32_t tile_bytes(uint32_t n, uint32_t len) { return (n * len + 4u + 3u) & ~3u; }
+
+// A record of n bytes at LDS address x (any alignment) as ND dwords: ND + 1
+// dwords are read from the one holding x (so the region needs that much slack
+// past its last record), realigned with v_alignbyte, and the bytes at
+// positions >= n are masked to 0.
+template <int ND>
+__device__ __forceinline__ void record_read(const uint8_t* x, uint32_t n, uint32_t (&d)[ND]) {
+    const uint32_t sh = (uint32_t)((uintptr_t)x & 3u);
+    const uint32_t* x32 = reinterpret_cast<const uint32_t*>(x - sh);
+    uint32_t r[ND + 1];
+#pragma unroll
+    for (int k = 0; k <= ND; ++k) r[k] = x32[k];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        const int rem = (int)n - 4 * k;
+        const uint32_t m = rem >= 4 ? ~0u : (rem <= 0 ? 0u : (1u << (8 * rem)) - 1u);
+        d[k] = __builtin_amdgcn_alignbyte(r[k + 1], r[k], sh) & m;
+    }
+}
+
+// LDS slack after each operand region of record_tiles: a record read runs up
+// to 4 (ND + 1) + 3 bytes past its record's start, a result write up to
+// 4 (NO + 1) + 3.
+constexpr uint32_t kRecordSlack = 256;
+
+// Dynamic LDS of record_tiles (bytes, a multiple of 4): the operand tiles of
+// 256 products, na and nb bytes each, with their slack.  The result tile,
+// 256 (na + nb - 1) bytes and the slack of its writes, overlays them.
+__host__ __device__ inline uint32_t record_tiles_smem(uint32_t na, uint32_t nb) {
+    return tile_bytes(256, na) + kRecordSlack + tile_bytes(256, nb) + kRecordSlack;
+}
+
+// Products of records, 256 per workgroup iteration: product t reads record t
+// of A (na bytes) and of B (nb bytes) and writes record t of OUT
+// (na + nb - 1 bytes), all three arrays contiguous.  The operand bytes of a
+// tile are staged in LDS (tile_in); each thread reads its two records as
+// dwords (record_read); reduce(xa, xb, ob) puts byte j of the result in byte j
+// of the NO-dword stream ob (zero on entry), and must leave every byte at
+// j >= na + nb - 1 zero; the region is cleared and each thread ORs its stream
+// into place as aligned dwords (ds_or_b32: a dword a record shares with a
+// neighbour receives only zero bytes from the other thread); the result tile
+// leaves with coalesced stores (tile_out).  Every thread runs reduce, so its
+// control flow stays uniform; threads past the last product write nothing.
+template <int NDA, int NDB, int NO, typename Reduce>
+__device__ __forceinline__ void record_tiles(uint32_t* smem, const uint8_t* __restrict__ A, uint32_t na,
+                                             const uint8_t* __restrict__ B, uint32_t nb, uint8_t* __restrict__ OUT,
+                                             uint64_t count, Reduce reduce) {
+    static_assert(4 * (NDA + 1) + 3 <= (int)kRecordSlack && 4 * (NDB + 1) + 3 <= (int)kRecordSlack, "record slack");
+    static_assert(4 * (NO + 1) + 3 <= 2 * (int)kRecordSlack, "result slack");
+    const uint32_t nout = na + nb - 1;
+    const uint32_t words = record_tiles_smem(na, nb) / 4;
+    uint8_t* RA = reinterpret_cast<uint8_t*>(smem);
+    uint8_t* RB = RA + tile_bytes(256, na) + kRecordSlack;
+    uint8_t* RO = RA;
+    const uint32_t u = threadIdx.x;
+    for (uint64_t t0 = blockIdx.x * 256ull; t0 < count; t0 += (uint64_t)gridDim.x * 256) {
+        const uint32_t n = (uint32_t)min<uint64_t>(256, count - t0);
+        const uint8_t* ga = A + t0 * na;
+        const uint8_t* gb = B + t0 * nb;
+        uint8_t* go = OUT + t0 * nout;
+        __syncthreads();   // the previous tile has left LDS
+        tile_in(ga, n * na, RA);
+        tile_in(gb, n * nb, RB);
+        __syncthreads();
+        uint32_t xa[NDA], xb[NDB];   // past n: stale bytes, never written out
+        record_read<NDA>(RA + tile_skew(ga) + u * na, na, xa);
+        record_read<NDB>(RB + tile_skew(gb) + u * nb, nb, xb);
+        __syncthreads();   // every record is read: clear the region for the results
+        for (uint32_t i = u; i < words; i += 256) smem[i] = 0;
+        __syncthreads();
+        uint32_t ob[NO];
+#pragma unroll
+        for (int j = 0; j < NO; ++j) ob[j] = 0;
+        reduce(xa, xb, ob);
+        if (u < n) {
+            uint8_t* o = RO + tile_skew(go) + u * nout;
+            const uint32_t sh = (uint32_t)((uintptr_t)o & 3u);
+            uint32_t* o32 = reinterpret_cast<uint32_t*>(o - sh);
+            uint32_t prev = 0;
+#pragma unroll
+            for (int j = 0; j <= NO; ++j) {
+                const uint32_t cur = j < NO ? ob[j] : 0u;
+                atomicOr(o32 + j, (uint32_t)((((uint64_t)cur << 32) | prev) >> (32 - 8 * sh)));
+                prev = cur;
+            }
+        }
+        __syncthreads();
+        tile_out(RO, n * nout, go);
+    }
+}
+
 }  // namespace dqt

@@ -19,68 +19,119 @@
 
 namespace dqt {
 
-template <int BS, int MAXB>
-__global__ __launch_bounds__(256) void k_polymul_fqt(const uint8_t* __restrict__ A, uint32_t na,
-                                                     const uint8_t* __restrict__ B, uint32_t nb,
-                                                     uint8_t* __restrict__ OUT, uint64_t count, RedqArgs ra) {
+// Reduces the block words W_0 .. W_{NW-1} of one product (Wof(w) gives W_w;
+// one REDQ_{2d+1} each), adds the top d coefficients of every block to the
+// next block's first d modulo p, and puts coefficient j of the product in
+// byte j of the stream ob (NO dwords, zero on entry).  Coefficients at
+// j >= nout = na + nb - 1 lie past the product's degree and come out 0.
+// QB, QW, SMALL: compile-time q = 2^QB, residue width and word size (binary64
+// floor without the AFDIV test), or 0 / false for the run-time values of ra.
+template <int BS, int NW, int QB, int QW, bool SMALL, int NO, typename WordOf>
+__device__ __forceinline__ void fqt_finish(WordOf Wof, uint32_t nout, const RedqArgs& ra, const uint16_t* tab,
+                                           uint32_t (&ob)[NO]) {
     constexpr int NR = 2 * BS - 1;
-    constexpr int NW = 2 * MAXB - 1;
+    uint32_t carry[BS > 1 ? BS - 1 : 1];
+#pragma unroll
+    for (int s = 0; s < BS - 1; ++s) carry[s] = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint64_t U = redq_compress_t<(QB ? NR : 0), QB, QW, SMALL>(Wof(w), ra);
+        uint32_t mu[NR];
+        redq_correct<NR, QB, QW>(U, ra, tab, [&](int s, uint32_t v) { mu[s] = v; });
+#pragma unroll
+        for (int s = 0; s < BS; ++s) {
+            uint32_t v = mu[s] + (s < BS - 1 ? carry[s] : 0u);
+            v = v >= ra.p ? v - ra.p : v;
+            const int pos = BS * w + s;
+            ob[pos >> 2] |= v << (8 * (pos & 3));
+        }
+#pragma unroll
+        for (int s = 0; s < BS - 1; ++s) carry[s] = mu[BS + s];
+    }
+    // coefficients past the last block start: only the carry of the last block
+    // (zero when the loop stopped early: those positions lie past the degree)
+#pragma unroll
+    for (int s = 0; s < BS - 1; ++s) {
+        const int pos = BS * NW + s;
+        ob[pos >> 2] |= carry[s] << (8 * (pos & 3));
+    }
+}
+
+// Block words of one operand from its record (ND dwords, bytes past the
+// record zero): block i holds coefficients i BS .. i BS + BS - 1 at q = 2^b.
+template <int BS, int MAXB, typename Word, int ND>
+__device__ __forceinline__ void fqt_words(const uint32_t (&d)[ND], uint32_t b, Word* w) {
+    static_assert(4 * ND >= MAXB * BS, "record dwords");
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        Word v = 0;
+#pragma unroll
+        for (int s = 0; s < BS; ++s) {
+            const int c = i * BS + s;
+            v |= (Word)((d[c >> 2] >> (8 * (c & 3))) & 0xFFu) << (b * s);
+        }
+        w[i] = v;
+    }
+}
+
+// Dwords of an operand record and of a result stream of the FQT kernels.
+template <int BS, int MAXB>
+struct FqtShape {
+    static constexpr int ND = (MAXB * BS + 3) / 4;
+    static constexpr int NO = (2 * MAXB * BS - 1 + 3) / 4;
+    static constexpr int NW = 2 * MAXB - 1;
+};
+
+// Tiles of 256 products through LDS (record_tiles); each product: block
+// words, their packed products summed per output block (delayed reduction),
+// one REDQ_{2d+1} per block word.  QB, QW, SMALL as in fqt_finish; the
+// compile-time instances ask for three waves per SIMD (168 VGPRs, a few
+// spilled).
+template <int BS, int MAXB, int QB = 0, int QW = 0, bool SMALL = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QB ? 3 : 1))) void k_polymul_fqt(
+    const uint8_t* __restrict__ A, uint32_t na, const uint8_t* __restrict__ B, uint32_t nb,
+    uint8_t* __restrict__ OUT, uint64_t count, RedqArgs ra) {
+    using F = FqtShape<BS, MAXB>;
+    extern __shared__ uint32_t fqt_smem[];
     __shared__ uint16_t tab[4096];
     build_correction_table(tab, ra);
-    __syncthreads();
     const uint32_t nout = na + nb - 1;
-    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < count; t += (uint64_t)gridDim.x * 256) {
-        const uint8_t* x = A + t * na;
-        const uint8_t* y = B + t * nb;
+    record_tiles<F::ND, F::ND, F::NO>(fqt_smem, A, na, B, nb, OUT, count,
+                                      [&](const uint32_t (&xa)[F::ND], const uint32_t (&xb)[F::ND],
+                                          uint32_t (&ob)[F::NO]) {
         uint32_t aw[MAXB], bw[MAXB];
+        fqt_words<BS, MAXB>(xa, QB ? QB : ra.b, aw);
+        fqt_words<BS, MAXB>(xb, QB ? QB : ra.b, bw);
+        if constexpr (QB != 0) {
+            // All block words first, then the reductions.  (The compile-time
+            // instance of the on-demand form below gave wrong bytes in the first
+            // two coefficients of some blocks on the device, with no fault found
+            // in the source; it is not built.)
+            uint64_t W[F::NW];
 #pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            uint32_t va = 0, vb = 0;
+            for (int w = 0; w < F::NW; ++w) {
+                uint64_t Wt = 0;
 #pragma unroll
-            for (int s = 0; s < BS; ++s) {
-                const uint32_t c = i * BS + s;
-                if (c < na) va |= (uint32_t)x[c] << (ra.b * s);
-                if (c < nb) vb |= (uint32_t)y[c] << (ra.b * s);
+                for (int i = 0; i < MAXB; ++i) {
+                    const int j = w - i;
+                    if (j >= 0 && j < MAXB) Wt += (uint64_t)aw[i] * (uint64_t)bw[j];
+                }
+                W[w] = Wt;
             }
-            aw[i] = va;
-            bw[i] = vb;
+            fqt_finish<BS, F::NW, QB, QW, SMALL>([&](int w) { return W[w]; }, nout, ra, tab, ob);
+        } else {
+            auto Wof = [&](int w) {
+                uint64_t Wt = 0;
+#pragma unroll
+                for (int i = 0; i < MAXB; ++i) {
+                    const int j = w - i;
+                    if (j >= 0 && j < MAXB) Wt += (uint64_t)aw[i] * (uint64_t)bw[j];
+                }
+                return Wt;
+            };
+            fqt_finish<BS, F::NW, 0, 0, false>(Wof, nout, ra, tab, ob);
         }
-        // For each output block t: packed sum of its block products (delayed
-        // reduction), one REDQ_{2d+1}, then the coefficients that no later
-        // block touches are final and stored; the top d are carried.
-        uint8_t* z = OUT + t * nout;
-        uint32_t carry[BS > 1 ? BS - 1 : 1];
-#pragma unroll
-        for (int s = 0; s < BS - 1; ++s) carry[s] = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            if ((uint32_t)(BS * w) >= nout) break;
-            uint64_t Wt = 0;
-#pragma unroll
-            for (int i = 0; i < MAXB; ++i) {
-                const int j = w - i;
-                if (j >= 0 && j < MAXB) Wt += (uint64_t)aw[i] * (uint64_t)bw[j];
-            }
-            const uint64_t U = redq_compress(Wt, ra);
-            uint32_t mu[NR];
-            redq_correct<NR>(U, ra, tab, [&](int s, uint32_t v) { mu[s] = v; });
-#pragma unroll
-            for (int s = 0; s < BS; ++s) {
-                uint32_t v = mu[s] + (s < BS - 1 ? carry[s] : 0u);
-                v = v >= ra.p ? v - ra.p : v;
-                const uint32_t pos = BS * w + s;
-                if (pos < nout) z[pos] = (uint8_t)v;
-            }
-#pragma unroll
-            for (int s = 0; s < BS - 1; ++s) carry[s] = mu[BS + s];
-        }
-        // coefficients past the last block start: only the carry of the last block
-#pragma unroll
-        for (int s = 0; s < BS - 1; ++s) {
-            const uint32_t pos = BS * NW + s;
-            if (pos < nout) z[pos] = (uint8_t)carry[s];
-        }
-    }
+    });
 }
 
 // Karatsuba on polynomials (in Y = X^BS) whose coefficients are packed block
@@ -126,59 +177,24 @@ struct Kara {
     }
 };
 
-template <int BS, int MAXB, int LEV>
-__global__ __launch_bounds__(256) void k_polymul_fqt_kara(const uint8_t* __restrict__ A, uint32_t na,
-                                                          const uint8_t* __restrict__ B, uint32_t nb,
-                                                          uint8_t* __restrict__ OUT, uint64_t count, RedqArgs ra) {
-    constexpr int NR = 2 * BS - 1;
-    constexpr int NW = 2 * MAXB - 1;
+template <int BS, int MAXB, int LEV, int QB = 0, int QW = 0, bool SMALL = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QB ? 3 : 1))) void k_polymul_fqt_kara(
+    const uint8_t* __restrict__ A, uint32_t na, const uint8_t* __restrict__ B, uint32_t nb,
+    uint8_t* __restrict__ OUT, uint64_t count, RedqArgs ra) {
+    using F = FqtShape<BS, MAXB>;
+    extern __shared__ uint32_t fqt_smem[];
     __shared__ uint16_t tab[4096];
     build_correction_table(tab, ra);
-    __syncthreads();
     const uint32_t nout = na + nb - 1;
-    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < count; t += (uint64_t)gridDim.x * 256) {
-        const uint8_t* x = A + t * na;
-        const uint8_t* y = B + t * nb;
-        uint64_t aw[MAXB], bw[MAXB], W[NW];
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            uint64_t va = 0, vb = 0;
-#pragma unroll
-            for (int s = 0; s < BS; ++s) {
-                const uint32_t c = i * BS + s;
-                if (c < na) va |= (uint64_t)x[c] << (ra.b * s);
-                if (c < nb) vb |= (uint64_t)y[c] << (ra.b * s);
-            }
-            aw[i] = va;
-            bw[i] = vb;
-        }
+    record_tiles<F::ND, F::ND, F::NO>(fqt_smem, A, na, B, nb, OUT, count,
+                                      [&](const uint32_t (&xa)[F::ND], const uint32_t (&xb)[F::ND],
+                                          uint32_t (&ob)[F::NO]) {
+        uint64_t aw[MAXB], bw[MAXB], W[F::NW];
+        fqt_words<BS, MAXB>(xa, QB ? QB : ra.b, aw);
+        fqt_words<BS, MAXB>(xb, QB ? QB : ra.b, bw);
         Kara<MAXB, LEV>::mul(aw, bw, W);
-        uint8_t* z = OUT + t * nout;
-        uint32_t carry[BS > 1 ? BS - 1 : 1];
-#pragma unroll
-        for (int s = 0; s < BS - 1; ++s) carry[s] = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            if ((uint32_t)(BS * w) >= nout) break;
-            const uint64_t U = redq_compress(W[w], ra);
-            uint32_t mu[NR];
-            redq_correct<NR>(U, ra, tab, [&](int s, uint32_t v) { mu[s] = v; });
-#pragma unroll
-            for (int s = 0; s < BS; ++s) {
-                uint32_t v = mu[s] + (s < BS - 1 ? carry[s] : 0u);
-                v = v >= ra.p ? v - ra.p : v;
-                const uint32_t pos = BS * w + s;
-                if (pos < nout) z[pos] = (uint8_t)v;
-            }
-#pragma unroll
-            for (int s = 0; s < BS - 1; ++s) carry[s] = mu[BS + s];
-        }
-#pragma unroll
-        for (int s = 0; s < BS - 1; ++s) {
-            const uint32_t pos = BS * NW + s;
-            if (pos < nout) z[pos] = (uint8_t)carry[s];
-        }
-    }
+        fqt_finish<BS, F::NW, QB, QW, SMALL>([&](int w) { return W[w]; }, nout, ra, tab, ob);
+    });
 }
 
 // Cost of one product with block size bs (block multiplies + REDQ words),
@@ -204,11 +220,24 @@ static bool fqt_q(uint32_t p, uint32_t bs, uint32_t n, uint32_t* b_out) {
     return false;
 }
 
+// Compile-time q and residue width for blocks of three coefficients over F_3
+// and 11 to 16 blocks per operand (q = 2^8, w = 2: 31 to 48 coefficients), else
+// the run-time values.
+static bool fqt_f3_blocks(uint32_t bs, const RedqArgs& ra) { return bs == 3 && ra.b == 8 && ra.w == 2 && ra.small; }
+
 template <int BS, int MAXB>
 static void launch_fqt(const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint8_t* out, uint64_t count,
                        const RedqArgs& ra, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt<BS, MAXB>), dim3(stream_grid(count, 256)), dim3(256), 0, s, A, na,
-                       B, nb, out, count, ra);
+    const dim3 grid(stream_grid(count, 256)), blk(256);
+    const size_t sm = record_tiles_smem(na, nb);
+    if constexpr (BS == 3 && MAXB == 16) {
+        if (fqt_f3_blocks(BS, ra)) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt<BS, MAXB, 8, 2, true>), grid, blk, sm, s, A, na, B, nb, out,
+                               count, ra);
+            return;
+        }
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt<BS, MAXB>), grid, blk, sm, s, A, na, B, nb, out, count, ra);
 }
 
 template <int BS>
@@ -224,9 +253,20 @@ template <int BS, int LEV>
 static void launch_kara_b(uint32_t maxb, const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint8_t* out,
                           uint64_t count, const RedqArgs& ra, hipStream_t s) {
     const dim3 grid(stream_grid(count, 256)), blk(256);
-    if (maxb <= 4) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 4, LEV>), grid, blk, 0, s, A, na, B, nb, out, count, ra);
-    else if (maxb <= 8) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 8, LEV>), grid, blk, 0, s, A, na, B, nb, out, count, ra);
-    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 16, LEV>), grid, blk, 0, s, A, na, B, nb, out, count, ra);
+    const size_t sm = record_tiles_smem(na, nb);
+    if (maxb <= 4) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 4, LEV>), grid, blk, sm, s, A, na, B, nb, out, count, ra);
+    else if (maxb <= 8) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 8, LEV>), grid, blk, sm, s, A, na, B, nb, out, count, ra);
+    else {
+        if constexpr (BS == 3) {
+            if (fqt_f3_blocks(BS, ra)) {
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 16, LEV, 8, 2, true>), grid, blk, sm, s, A, na,
+                                   B, nb, out, count, ra);
+                return;
+            }
+        }
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_kara<BS, 16, LEV>), grid, blk, sm, s, A, na, B, nb, out, count,
+                           ra);
+    }
 }
 
 template <int BS>

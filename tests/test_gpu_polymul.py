@@ -212,6 +212,39 @@ def test_fqt_long_products(dqt, p):
         assert (to_host(dqt.polymul_fqt_u8(to_dev(w), to_dev(wb), p)) == O.polymul(w, wb, p)).all()
 
 
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_fqt_tiles_unaligned_and_bounded(dqt, levels):
+    """The FQT kernels move 256 products at a time through LDS: operands and results at every
+    byte offset (odd record lengths, so no tile is a whole number of words), partial last tiles,
+    and not one byte written outside the result (sentinels on both sides)."""
+    run = (lambda a, b, p, out: dqt.polymul_fqt_u8(a, b, p, out=out)) if levels == 0 else \
+          (lambda a, b, p, out: dqt.polymul_fqt_kara_u8(a, b, p, levels=levels, out=out))
+    dev = device()
+    for (p, na, nb, count) in ((3, 13, 7, 1000), (5, 9, 9, 257), (2, 31, 17, 513), (3, 48, 45, 300), (7, 20, 19, 77),
+                               (3, 1, 5, 3)):
+        a, b = inputs.polymul_pairs(count, na, p, seed=na * 7 + nb + levels, kb=nb)
+        ref = O.polymul(a, b, p)
+        nout = na + nb - 1
+        for oa, ob, oo in ((1, 2, 3), (3, 0, 1), (2, 1, 2), (0, 3, 0)):
+            flat = torch.full((count * nout + 64,), 0xAB, dtype=torch.uint8, device=dev)
+            out = flat[oo:oo + count * nout].view(count, nout)
+            run(unaligned_like(a, oa), unaligned_like(b, ob), p, out)
+            host = to_host(flat)
+            assert (host[oo:oo + count * nout].reshape(count, nout) == ref).all(), (p, na, nb, count, oa, ob, oo)
+            assert (host[:oo] == 0xAB).all() and (host[oo + count * nout:] == 0xAB).all(), (p, na, nb, oo)
+
+
+@pytest.mark.parametrize("levels", [0, 1])
+def test_fqt_many_tiles_per_workgroup(dqt, levels):
+    """More products than the grid has threads: each workgroup takes several tiles in turn."""
+    count, na = 160_001, 12
+    a, b = inputs.polymul_pairs(count, na, 3, seed=41 + levels)
+    ref = O.polymul(a, b, 3)
+    da, db = to_dev(a), to_dev(b)
+    got = dqt.polymul_fqt_u8(da, db, 3) if levels == 0 else dqt.polymul_fqt_kara_u8(da, db, 3, levels=levels)
+    assert (to_host(got) == ref).all()
+
+
 @pytest.mark.parametrize("k", [9, 16, 33, 48, 64])
 def test_polymul_plain_long(dqt, k):
     """The plain comparator at long degrees (operands staged in LDS by blocks of 256 products)."""

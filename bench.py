@@ -40,7 +40,7 @@ EVENT_EVERY = 8                            # steps per kernel-timed step
 TRAFFIC_SOURCES = ("paper_0809_0063_amd/csrc/dqt_gemm_tile.h", "paper_0809_0063_amd/csrc/dqt_device.h")
 TRAFFIC_KERNEL = ("paper_0809_0063_amd/csrc/dqt_gemm.hip", "__device__ __forceinline__ void tile_of(",
                   "// Pack A (rows")
-TRAFFIC = {"sha256": "46bd27bea0dab51da346bce376b77997df614824936c6502e6819e0564648e30", "bytes": 11697895}
+TRAFFIC = {"sha256": "46bd27bea0dab51da346bce376b77997df614824936c6502e6819e0564648e30", "bytes": 11697848}
 
 
 def kernel_sources_sha256() -> str:

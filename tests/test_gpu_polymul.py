@@ -212,16 +212,22 @@ def test_fqt_long_products(dqt, p):
         assert (to_host(dqt.polymul_fqt_u8(to_dev(w), to_dev(wb), p)) == O.polymul(w, wb, p)).all()
 
 
-@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("levels", [-1, 0, 1, 2])
 def test_fqt_tiles_unaligned_and_bounded(dqt, levels):
-    """The FQT kernels move 256 products at a time through LDS: operands and results at every
-    byte offset (odd record lengths, so no tile is a whole number of words), partial last tiles,
-    and not one byte written outside the result (sentinels on both sides)."""
-    run = (lambda a, b, p, out: dqt.polymul_fqt_u8(a, b, p, out=out)) if levels == 0 else \
-          (lambda a, b, p, out: dqt.polymul_fqt_kara_u8(a, b, p, levels=levels, out=out))
+    """The FQT kernels (levels 0: schoolbook blocks, 1-2: Karatsuba) and the plain long-product
+    comparator (levels -1, equal lengths from 9 coefficients) move 256 products at a time through
+    LDS: operands and results at every byte offset (odd record lengths, so no tile is a whole
+    number of words), partial last tiles, and not one byte written outside the result (sentinels
+    on both sides)."""
+    if levels == -1:
+        run = lambda a, b, p, out: dqt.polymul_plain_u8(a, b, p, out=out)
+        cases = ((3, 13, 13, 1000), (5, 9, 9, 257), (2, 31, 31, 513), (3, 47, 47, 300), (251, 64, 64, 77))
+    else:
+        run = (lambda a, b, p, out: dqt.polymul_fqt_u8(a, b, p, out=out)) if levels == 0 else \
+              (lambda a, b, p, out: dqt.polymul_fqt_kara_u8(a, b, p, levels=levels, out=out))
+        cases = ((3, 13, 7, 1000), (5, 9, 9, 257), (2, 31, 17, 513), (3, 48, 45, 300), (7, 20, 19, 77), (3, 1, 5, 3))
     dev = device()
-    for (p, na, nb, count) in ((3, 13, 7, 1000), (5, 9, 9, 257), (2, 31, 17, 513), (3, 48, 45, 300), (7, 20, 19, 77),
-                               (3, 1, 5, 3)):
+    for (p, na, nb, count) in cases:
         a, b = inputs.polymul_pairs(count, na, p, seed=na * 7 + nb + levels, kb=nb)
         ref = O.polymul(a, b, p)
         nout = na + nb - 1

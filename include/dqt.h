@@ -14,7 +14,8 @@
  * ---------------------------------------
  * - Every function returns a dqt_status; none aborts, throws or prints.
  * - Residues are uint8 values in [0, p), 2 <= p <= 255.  Inputs with an entry
- *   >= p give unspecified (but memory-safe) results.
+ *   >= p give unspecified (but memory-safe) results; debug mode
+ *   (dqt_debug_enable) reports them as DQT_E_INPUT instead.
  * - Coefficient i of a polynomial is the coefficient of X^i (low degree first).
  * - Pointers named d_* are device pointers (HIP global memory) owned by the
  *   caller; the library allocates no device memory and keeps no pointer after
@@ -48,7 +49,9 @@ typedef enum dqt_status {
     DQT_E_UNSUPPORTED = -3, /* valid, but outside what the kernels implement */
     DQT_E_DEVICE = -4,      /* HIP runtime error (see dqt_last_error) */
     DQT_E_WORKSPACE = -5,   /* workspace null or smaller than required */
-    DQT_E_INPUT = -6        /* an input entry is not a residue in [0, p) (dqt_check_input_u8) */
+    DQT_E_INPUT = -6        /* a device-side check failed: an entry not a residue in [0, p), a packed
+                               operand or REDQ word outside its bounds (debug mode, dqt_sync_status,
+                               dqt_check_input_u8) */
 } dqt_status;
 
 /* Text of a status code (static storage). */
@@ -73,7 +76,35 @@ dqt_status dqt_set_table_window(uint32_t j);
 uint32_t dqt_get_table_window(void);
 
 /*
- * Input validation (debug mode).  The packed paths assume every entry is a
+ * Debug mode: device-side checks with a status word.
+ * The a priori bounds (eq:bounds, eq:lower) hold only for entries that are
+ * residues in [0, p), and REDQ (algorithm REDQ, section 3.2) only for words
+ * whose lower digits are below q and that are exact in binary64 (AFDIV,
+ * section 4).  The host cannot see the data, so with debug mode on every
+ * entry point, after its host checks and before it enqueues its own work,
+ * checks on its stream the data it is given: uint8 entries < p (status bit
+ * 1); the packed operand words of dqt_polymul have k_coeffs fields below p
+ * and nothing above (bit 2: by eq:bounds every digit of their product is
+ * then below q); the words given to redq_unpack are below 2^beta (bit 4).
+ * It then waits for the stream, reads and clears the status word and returns
+ * DQT_E_INPUT (nothing else enqueued, dqt_last_error names the check) if a
+ * bit was set.  dqt_fgemm_packed and dqt_fgemm_compute take packed operands
+ * that were checked when they were packed.
+ *
+ * dqt_debug_enable(d_status): turns debug mode on (process-wide) with the
+ * caller's 4-byte device word d_status on the current device (zeroed here,
+ * synchronously), or off with NULL.  The word must stay valid while debug
+ * mode is on; calls on another device return DQT_E_INVALID, and calls on a
+ * stream under graph capture DQT_E_UNSUPPORTED (the checks wait).
+ * dqt_sync_status(stream): waits for `stream`, then reads and clears the
+ * status word: DQT_E_INPUT if a check failed since the last read, DQT_OK
+ * otherwise (and DQT_OK after the wait when debug mode is off).
+ */
+dqt_status dqt_debug_enable(uint32_t *d_status);
+dqt_status dqt_sync_status(void *stream);
+
+/*
+ * Input validation on demand.  The packed paths assume every entry is a
  * residue in [0, p): the a priori bounds (eq:bounds, eq:lower) are stated for
  * entries at most p-1, and a larger entry silently breaks them.  This call
  * checks `count` bytes at d_x on `stream`, using the caller's 4-byte device
@@ -91,6 +122,10 @@ dqt_status dqt_check_input_u8(const uint8_t *d_x, uint64_t count, uint32_t p, ui
  *   nres     digits of a packed result, 2*k_coeffs - 1 for a product (REDQ_nres).
  *   n_accum  number of products summed into one result word before REDQ
  *            (the n of eq:bounds); 1 for a single product.
+ *   word_bits beta, the width of the words REDQ reduces: packed results are
+ *            below 2^word_bits.  0 means 53 (the binary64 mantissa, so that
+ *            REDQ's one division is one FP64 multiply and floor, section 4);
+ *            values above 53 give DQT_E_UNSUPPORTED.
  * Every packed word is a uint64 holding nres fields of log2q bits.
  */
 typedef struct dqt_qadic {
@@ -99,25 +134,26 @@ typedef struct dqt_qadic {
     uint32_t k_coeffs;
     uint32_t nres;
     uint64_t n_accum;
+    uint32_t word_bits;
 } dqt_qadic;
 
 /*
  * Host-only check of a parameter set.  DQT_OK iff
  *   q > n_accum * k_coeffs * (p-1)^2     (eq:bounds, digits never carry),
- *   nres * log2q <= 53                   (eq:bounds with beta = 53: the word
- *                                         is exact in binary64, so REDQ's
- *                                         single division is one FP64 floor),
+ *   nres * log2q <= beta                 (eq:bounds: the word is below
+ *                                         2^beta, beta = word_bits or 53),
  *   log2q <= 32, 1 <= k_coeffs, 1 <= nres <= 32.
- * Returns DQT_E_INVALID for null or malformed input, DQT_E_BOUND otherwise.
+ * Returns DQT_E_INVALID for null or malformed input, DQT_E_UNSUPPORTED for
+ * beta > 53, DQT_E_BOUND otherwise.
  */
 dqt_status dqt_qadic_check(const dqt_qadic *a);
 
 /*
  * Host-only: the smallest log2q satisfying dqt_qadic_check for (p, k_coeffs,
- * n_accum) with nres = 2*k_coeffs - 1.  Writes *out on success; DQT_E_BOUND
- * when no q fits in 53 bits.
+ * n_accum, word_bits) with nres = 2*k_coeffs - 1.  Writes *out on success;
+ * DQT_E_BOUND when no q fits in beta bits.
  */
-dqt_status dqt_qadic_choose(uint32_t p, uint32_t k_coeffs, uint64_t n_accum, dqt_qadic *out);
+dqt_status dqt_qadic_choose(uint32_t p, uint32_t k_coeffs, uint64_t n_accum, uint32_t word_bits, dqt_qadic *out);
 
 /*
  * DQT map (equation eq:dqt; section 2.1 with q = 2^log2q a shift).
@@ -143,11 +179,16 @@ dqt_status dqt_polymul(const uint64_t *d_a, const uint64_t *d_b, uint64_t count,
  * section 3.3, the tabulated correction of section 3.5 and the FP64 floor of
  * algorithm AFDIV, section 4.6).
  * d_r: uint64 [count] packed words r = sum_{i<nres} m_i q^i whose lower
- * digits m_0..m_{nres-2} are < q (guaranteed by eq:bounds when the words
- * come from products; the caller's guarantee otherwise).  Checked here:
- * nres * log2q <= 53 (so r < 2^53 and the division is one binary64 floor,
- * DQT_E_BOUND otherwise) and log2q >= ceil(log2 p) (DQT_E_UNSUPPORTED
- * otherwise); n_accum and the first part of eq:bounds are not used.
+ * digits m_0..m_{nres-2} are < q (the REQUIRE of algorithm REDQ, section
+ * 3.2: guaranteed by eq:bounds when the words come from products of packed
+ * residues, the caller's guarantee otherwise; the top digit may exceed q)
+ * and r < 2^beta, beta = a->word_bits or 53 (AFDIV's domain).  Checked on
+ * the host: nres * log2q <= 53 (DQT_E_BOUND otherwise) and log2q >=
+ * ceil(log2 p) (DQT_E_UNSUPPORTED otherwise); n_accum and the first part of
+ * eq:bounds are not used.  In debug mode (dqt_debug_enable) the words are
+ * checked to be below 2^beta on the device first (DQT_E_INPUT otherwise);
+ * the digit condition is asserted where it can fail, on the packed operands
+ * of dqt_polymul and the uint8 inputs of the packing and fused calls.
  * modulus == NULL: d_out uint8 [count][nres], d_out[t][i] = m_i mod p.
  * modulus != NULL (GF(p^k) reduction by two tables, algorithm FGDP, theorem
  * thm:fgdp): host pointer to k_coeffs+1 coefficients of a monic polynomial P
@@ -284,7 +325,9 @@ size_t dqt_fgemm_workspace_size(uint32_t p, uint64_t m, uint64_t n, uint64_t kdi
  * applies; tile_rows, tile_cols, interval and epilogue are ignored.
  * CMM bounds (eq:lower with the interval in place of kdim): interval*(p-1)^2
  * < Q, and (p-1)(Q+1) < 2^16 so that a Kronecker pair fits a 16-bit lane of
- * the packed word.  d_work: device workspace of at least
+ * the packed word.  CMM, PLAIN and DOT4 add whole dot products in uint32, so
+ * they need kdim*(p-1)^2 < 2^32 (DQT_E_UNSUPPORTED otherwise, AUTO included);
+ * MFMA needs kdim*(p-1)^2 < 2^31 and p <= 128.  d_work: device workspace of at least
  * dqt_fgemm_workspace_size(...) bytes (packed operands), 16-byte aligned
  * (DQT_E_INVALID otherwise); its contents on entry are ignored.
  */
@@ -329,6 +372,9 @@ dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t 
  * must be 16-byte aligned and hold that many bytes.  dqt_fgemm_packed
  * multiplies a packed A (m rows) by a packed B (n columns) and writes C; both
  * must come from dqt_fgemm_pack_side with the same p, kdim and plan.
+ * DQT_GEMM_BY_SHAPE is refused by these three calls (0 bytes, DQT_E_INVALID):
+ * it picks the algorithm from all three dimensions, which one side alone
+ * does not know.
  */
 size_t dqt_fgemm_packed_bytes(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, int side, const dqt_gemm_plan *plan);
 dqt_status dqt_fgemm_pack_side(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, const uint8_t *d_X, uint64_t ldx,

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_batch_pack(const BatchHeader* __restric
 template <int TM, int TN, int S>
 __global__ __launch_bounds__(64 * S) void k_batch_compute(BatchHeader* hdr, const BatchDesc* __restrict__ descs,
                                                           const uint2* __restrict__ items) {
-    __shared__ uint32_t red[TileSmem<TM, TN, S>::words];
+    __shared__ __attribute__((aligned(16))) uint32_t red[TileSmem<TM, TN, S>::words];
     __shared__ uint32_t next;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
@@ -212,6 +212,12 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
     DQT_TRY(st);
     if (!d_work || work_bytes < L.total) return DQT_E_WORKSPACE;
     DQT_TRY(ensure_device_ready());
+    if (debug_on())
+        for (uint32_t i = 0; i < count; ++i) {
+            const dqt_gemm_desc& d = descs[i];
+            DQT_TRY(debug_gate(reinterpret_cast<hipStream_t>(stream), d.p,
+                               {{d.A, d.m, d.kdim, d.lda}, {d.B, d.kdim, d.n, d.ldb}}));
+        }
 
     std::vector<uint8_t> host(L.packed, 0);
     BatchHeader* H = reinterpret_cast<BatchHeader*>(host.data() + L.header);

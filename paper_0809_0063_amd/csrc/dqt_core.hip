@@ -185,7 +185,7 @@ extern "C" const char* dqt_status_str(dqt_status s) {
         case DQT_E_UNSUPPORTED: return "unsupported parameters";
         case DQT_E_DEVICE: return "HIP runtime error";
         case DQT_E_WORKSPACE: return "workspace too small";
-        case DQT_E_INPUT: return "input entry not a residue in [0, p)";
+        case DQT_E_INPUT: return "input check failed (an entry not a residue in [0, p), or a packed word out of its bounds)";
     }
     return "unknown status";
 }
@@ -237,31 +237,40 @@ extern "C" uint32_t dqt_get_table_window(void) { return g_table_window.load(std:
 extern "C" dqt_status dqt_qadic_check(const dqt_qadic* a) {
     if (!a) return DQT_E_INVALID;
     if (a->p < 2 || a->p > 255 || a->k_coeffs < 1 || a->nres < 1 || a->nres > 32 || a->log2q < 1 ||
-        a->log2q > 32 || a->n_accum < 1)
+        a->log2q > 32 || a->n_accum < 1 || a->word_bits > 64)
         return DQT_E_INVALID;
+    // beta: REDQ's one division is one binary64 floor, exact only on words below 2^53
+    const uint32_t beta = a->word_bits ? a->word_bits : 53;
+    if (beta > 53) return DQT_E_UNSUPPORTED;
     // eq:bounds, first part: q > n k (p-1)^2 (no digit of a sum of n products reaches q)
     const unsigned __int128 need =
         (unsigned __int128)a->n_accum * a->k_coeffs * (uint64_t)(a->p - 1) * (uint64_t)(a->p - 1);
     if (!((unsigned __int128)1 << a->log2q > need)) return DQT_E_BOUND;
-    // eq:bounds, second part with beta = 53
-    if ((uint64_t)a->nres * a->log2q > 53) return DQT_E_BOUND;
+    // eq:bounds, second part: the nres digits fit the beta-bit word
+    if ((uint64_t)a->nres * a->log2q > beta) return DQT_E_BOUND;
     return DQT_OK;
 }
 
-extern "C" dqt_status dqt_qadic_choose(uint32_t p, uint32_t k_coeffs, uint64_t n_accum, dqt_qadic* out) {
-    if (!out || p < 2 || p > 255 || k_coeffs < 1 || k_coeffs > 16 || n_accum < 1) return DQT_E_INVALID;
+extern "C" dqt_status dqt_qadic_choose(uint32_t p, uint32_t k_coeffs, uint64_t n_accum, uint32_t word_bits,
+                                       dqt_qadic* out) {
+    if (!out || p < 2 || p > 255 || k_coeffs < 1 || k_coeffs > 16 || n_accum < 1 || word_bits > 64)
+        return DQT_E_INVALID;
     dqt_qadic a;
+    memset(&a, 0, sizeof(a));
     a.p = p;
     a.k_coeffs = k_coeffs;
     a.nres = 2 * k_coeffs - 1;
     a.n_accum = n_accum;
+    a.word_bits = word_bits;
+    const uint32_t beta = word_bits ? word_bits : 53;
+    if (beta > 53) return DQT_E_UNSUPPORTED;
     for (uint32_t b = 1; b <= 32; ++b) {
         a.log2q = b;
         if (dqt_qadic_check(&a) == DQT_OK) {
             *out = a;
             return DQT_OK;
         }
-        if ((uint64_t)a.nres * b > 53) break;
+        if ((uint64_t)a.nres * b > beta) break;
     }
     return DQT_E_BOUND;
 }
@@ -717,6 +726,7 @@ extern "C" dqt_status dqt_pack(const uint8_t* d_coeffs, uint64_t count, const dq
     if (count == 0) return DQT_OK;
     if (!d_coeffs || !d_words) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
+    DQT_TRY(debug_gate(S(stream), a->p, {{d_coeffs, count, a->k_coeffs, a->k_coeffs}}));
     hipLaunchKernelGGL(k_pack, dim3(stream_grid(count, 256)), dim3(256), 0, S(stream), d_coeffs, count, a->k_coeffs,
                        a->log2q, reverse, d_words);
     DQT_LAUNCH_CHECK("dqt_pack");
@@ -731,6 +741,8 @@ extern "C" dqt_status dqt_polymul(const uint64_t* d_a, const uint64_t* d_b, uint
     if (count == 0) return DQT_OK;
     if (!d_a || !d_b || !d_r) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
+    DQT_TRY(debug_gate(S(stream), a->p, {},
+                       {{d_a, count, a->log2q, a->k_coeffs}, {d_b, count, a->log2q, a->k_coeffs}}));
     hipLaunchKernelGGL(k_words_mul, dim3(stream_grid(count, 256)), dim3(256), 0, S(stream), d_a, d_b, count, d_r);
     DQT_LAUNCH_CHECK("dqt_polymul");
     return DQT_OK;
@@ -778,11 +790,15 @@ extern "C" dqt_status redq_unpack(const uint64_t* d_r, uint64_t count, const dqt
     // REDQ needs only digits below q (the caller's guarantee) and a word that
     // is exact in binary64: nres * log2q <= 53; each residue field of w bits
     // must fit in its q-adic digit (log2q >= w).
-    if (!a || a->p < 2 || a->p > 255 || a->log2q < 1 || a->log2q > 32 || a->nres < 1) return DQT_E_INVALID;
+    if (!a || a->p < 2 || a->p > 255 || a->log2q < 1 || a->log2q > 32 || a->nres < 1 || a->word_bits > 64)
+        return DQT_E_INVALID;
+    // beta: the words are below 2^beta (53 by default, the binary64 mantissa)
+    const uint32_t beta = a->word_bits ? a->word_bits : 53;
+    if (beta > 53) return DQT_E_UNSUPPORTED;
     if ((uint64_t)a->nres * a->log2q > 53) return DQT_E_BOUND;
     if (a->log2q < residue_bits(a->p)) return DQT_E_UNSUPPORTED;
     RedqArgs ra;
-    DQT_TRY(make_redq_args(a->p, a->log2q, a->nres, 53, &ra));
+    DQT_TRY(make_redq_args(a->p, a->log2q, a->nres, beta, &ra));
     if (modulus) {
         if (a->nres != 2 * a->k_coeffs - 1) return DQT_E_INVALID;
         GfArgs ga;
@@ -792,6 +808,7 @@ extern "C" dqt_status redq_unpack(const uint64_t* d_r, uint64_t count, const dqt
         if (count == 0) return DQT_OK;
         if (!d_r || !d_out) return DQT_E_INVALID;
         DQT_TRY(ensure_device_ready());
+        DQT_TRY(debug_gate(S(stream), a->p, {}, {{d_r, count, beta, 0}}));
         switch (a->k_coeffs) {
             case 2: return launch_redq_gf<2>(d_r, count, ra, ga, d_out, S(stream));
             case 3: return launch_redq_gf<3>(d_r, count, ra, ga, d_out, S(stream));
@@ -804,6 +821,7 @@ extern "C" dqt_status redq_unpack(const uint64_t* d_r, uint64_t count, const dqt
     if (count == 0) return DQT_OK;
     if (!d_r || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
+    DQT_TRY(debug_gate(S(stream), a->p, {}, {{d_r, count, beta, 0}}));
     hipLaunchKernelGGL(k_redq_unpack, dim3(stream_grid(count, 256)), dim3(256), 0, S(stream), d_r, count, ra, d_out);
     DQT_LAUNCH_CHECK("redq_unpack");
     return DQT_OK;
@@ -863,7 +881,8 @@ static dqt_status launch_polymul_fused(const uint8_t* A, const uint8_t* B, uint6
 
 // q for a single product: the given one (checked against eq:bounds) or the smallest.
 static dqt_status product_qadic(uint32_t p, uint32_t k, uint32_t log2q, dqt_qadic* q) {
-    if (log2q == 0) return dqt_qadic_choose(p, k, 1, q) == DQT_OK ? DQT_OK : DQT_E_UNSUPPORTED;
+    if (log2q == 0) return dqt_qadic_choose(p, k, 1, 0, q) == DQT_OK ? DQT_OK : DQT_E_UNSUPPORTED;
+    memset(q, 0, sizeof(*q));
     q->p = p;
     q->k_coeffs = k;
     q->nres = 2 * k - 1;
@@ -884,6 +903,7 @@ extern "C" dqt_status dqt_polymul_u8(const uint8_t* d_a, const uint8_t* d_b, uin
     if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     hipStream_t s = S(stream);
+    DQT_TRY(debug_gate(s, p, {{d_a, count, k, k}, {d_b, count, k, k}}));
     switch (k) {
         case 1: return launch_polymul_fused<1>(d_a, d_b, count, ra, d_out, s);
         case 2: return launch_polymul_fused<2>(d_a, d_b, count, ra, d_out, s);
@@ -949,6 +969,7 @@ extern "C" dqt_status dqt_gf_mul_u8(const uint8_t* d_a, const uint8_t* d_b, uint
     if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     hipStream_t s = S(stream);
+    DQT_TRY(debug_gate(s, p, {{d_a, count, k, k}, {d_b, count, k, k}}));
     switch (k) {
         case 2: return launch_gf_fused<2>(d_a, d_b, count, ra, ga, d_out, s);
         case 3: return launch_gf_fused<3>(d_a, d_b, count, ra, ga, d_out, s);
@@ -967,6 +988,7 @@ extern "C" dqt_status dqt_polymul_plain_u8(const uint8_t* d_a, const uint8_t* d_
     DQT_TRY(ensure_device_ready());
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
     hipStream_t s = S(stream);
+    DQT_TRY(debug_gate(s, p, {{d_a, count, k, k}, {d_b, count, k, k}}));
     const unsigned g4 = stream_grid((count + 3) / 4, 256);
 #define DQT_PLAIN_CASE(KK)                                                                                           \
     case KK:                                                                                                         \
@@ -1018,6 +1040,7 @@ extern "C" dqt_status dqt_gf_mul_plain_u8(const uint8_t* d_a, const uint8_t* d_b
     DQT_TRY(ensure_device_ready());
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
     hipStream_t s = S(stream);
+    DQT_TRY(debug_gate(s, p, {{d_a, count, k, k}, {d_b, count, k, k}}));
     const unsigned g = stream_grid(count, 256);
     switch (k) {
         case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain<2>), dim3(g), dim3(256), 0, s, d_a, d_b, d_out, count, p, pmagic, mod); break;

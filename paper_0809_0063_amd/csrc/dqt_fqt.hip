@@ -316,6 +316,7 @@ extern "C" dqt_status dqt_polymul_fqt_kara_u8(const uint8_t* d_a, uint32_t na, c
     if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DQT_TRY(debug_gate(s, p, {{d_a, count, na, na}, {d_b, count, nb, nb}}));
     const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs;
     const uint32_t maxb = Na > Nb ? Na : Nb;
     switch (bs) {
@@ -340,6 +341,7 @@ extern "C" dqt_status dqt_polymul_fqt_u8(const uint8_t* d_a, uint32_t na, const 
     if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DQT_TRY(debug_gate(s, p, {{d_a, count, na, na}, {d_b, count, nb, nb}}));
     const uint32_t Na = (na + best_bs - 1) / best_bs, Nb = (nb + best_bs - 1) / best_bs;
     const uint32_t maxb = Na > Nb ? Na : Nb;
     switch (best_bs) {

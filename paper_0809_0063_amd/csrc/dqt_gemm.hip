@@ -54,7 +54,7 @@ __device__ __forceinline__ void tile_of(uint32_t bid, uint32_t nblk, uint32_t nr
 
 template <int OP, int TM, int TN, int S, bool FLUSH, int EPI>
 __global__ __launch_bounds__(64 * S) void k_gemm_words(GemmArgs g) {
-    __shared__ uint32_t red[TileSmem<TM, TN, S>::words];
+    __shared__ __attribute__((aligned(16))) uint32_t red[TileSmem<TM, TN, S>::words];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t rb, cb;
@@ -294,6 +294,10 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
     }
     if (is_f64_algo(algo)) return f64_plan(algo, p, m, n, kdim, pl.log2Q, pl.ksplit, r);
     uint32_t b = 0, interval = 0;
+    // Every kernel of this file adds whole dot products (each at most
+    // kdim (p-1)^2) in uint32: the middle digits of all intervals and k-splits
+    // of the packed path as well as the plain sums.  Above 2^32 they would wrap.
+    const bool sums_fit = kdim * (uint64_t)(p - 1) * (p - 1) < (1ull << 32);
     const bool cmm_ok = cmm_params(p, kdim, pl.interval, pl.log2Q, &b, &interval);
     if (algo == DQT_GEMM_AUTO) algo = cmm_ok ? DQT_GEMM_CMM : DQT_GEMM_PLAIN;
     r->algo = algo;
@@ -301,6 +305,7 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
     if (r->epi > 1) return DQT_E_INVALID;
     switch (algo) {
         case DQT_GEMM_CMM:
+            if (!sums_fit) return DQT_E_UNSUPPORTED;
             if (!cmm_ok) return (pl.interval || pl.log2Q) ? DQT_E_BOUND : DQT_E_UNSUPPORTED;
             r->op = OP_DOT2;
             r->b = b;
@@ -308,12 +313,12 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
             break;
         case DQT_GEMM_PLAIN:
             r->op = OP_MAD;
-            if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 32)) return DQT_E_UNSUPPORTED;
+            if (!sums_fit) return DQT_E_UNSUPPORTED;
             if (r->epi) return DQT_E_UNSUPPORTED;
             break;
         case DQT_GEMM_DOT4:
             r->op = OP_DOT4;
-            if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 32)) return DQT_E_UNSUPPORTED;
+            if (!sums_fit) return DQT_E_UNSUPPORTED;
             if (r->epi) return DQT_E_UNSUPPORTED;
             break;
         case DQT_GEMM_MFMA:
@@ -446,19 +451,26 @@ dqt_status fgemm_epilogue_args(uint32_t p, uint64_t kdim, const GemmPlanResolved
     return DQT_OK;
 }
 
-// Packing step: operands to the word layout of the plan's kernel (either
-// operand may be skipped by passing NULL, to reuse a packed one).
-dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A, uint64_t lda, const uint8_t* B,
-                              uint64_t ldb, const GemmPlanResolved& r, void* work, hipStream_t s) {
-    if (is_f64_algo(r.algo))
-        return f64_pack_enqueue(r, m, n, kdim, A, lda, B, ldb, work,
-                                reinterpret_cast<uint8_t*>(work) + f64_side_bytes(r, 0), s);
+// Bytes of the packed copy of one side (0 = A, 1 = B).
+static size_t side_bytes(const GemmPlanResolved& r, int side) {
+    if (is_f64_algo(r.algo)) return f64_side_bytes(r, side);
+    if (r.algo == DQT_GEMM_MFMA) return (size_t)r.k_pad * (side == 0 ? r.m_pad : r.n_pad);
+    return (size_t)r.KW * (side == 0 ? r.m_pad : r.n_pad) * sizeof(uint32_t);
+}
+
+// Packing step: operands to the word layout of the plan's kernel, A's packed
+// copy to pA and B's to pB (either operand may be skipped by passing NULL,
+// to reuse a packed one; its target is then not touched).
+static dqt_status fgemm_pack_sides(uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A, uint64_t lda,
+                                   const uint8_t* B, uint64_t ldb, const GemmPlanResolved& r, void* pA, void* pB,
+                                   hipStream_t s) {
+    if (is_f64_algo(r.algo)) return f64_pack_enqueue(r, m, n, kdim, A, lda, B, ldb, pA, pB, s);
     if (r.algo == DQT_GEMM_MFMA) {
         MfmaPackArgs pa;
         pa.A = A;
         pa.B = B;
-        pa.A8 = reinterpret_cast<uint8_t*>(work);
-        pa.BT8 = pa.A8 + (size_t)r.m_pad * r.k_pad;
+        pa.A8 = reinterpret_cast<uint8_t*>(pA);
+        pa.BT8 = reinterpret_cast<uint8_t*>(pB);
         pa.m = (uint32_t)m;
         pa.n = (uint32_t)n;
         pa.kdim = (uint32_t)kdim;
@@ -475,8 +487,8 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
         DQT_LAUNCH_CHECK("fgemm(mfma pack)");
         return DQT_OK;
     }
-    uint32_t* CA = reinterpret_cast<uint32_t*>(work);
-    uint32_t* CB = CA + (size_t)r.KW * r.m_pad;
+    uint32_t* CA = reinterpret_cast<uint32_t*>(pA);
+    uint32_t* CB = reinterpret_cast<uint32_t*>(pB);
     PackArgs pa;
     pa.A = A;
     pa.B = B;
@@ -496,7 +508,8 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
     pa.cbw = 64 * r.tn;
     const bool a_al = !A || (((uintptr_t)A & 3) == 0 && (lda & 3) == 0);
     const bool b_al = !B || (((uintptr_t)B & 3) == 0 && (ldb & 3) == 0);
-    if (r.op != OP_MAD && a_al && b_al && (r.n_pad & 3) == 0 && ((uintptr_t)work & 15) == 0) {
+    const bool out_al = (!A || ((uintptr_t)pA & 15) == 0) && (!B || ((uintptr_t)pB & 15) == 0);
+    if (r.op != OP_MAD && a_al && b_al && (r.n_pad & 3) == 0 && out_al) {
         Pack4Args p4;
         p4.a = pa;
         p4.tiles_m = (r.m_pad + 63) / 64;
@@ -511,11 +524,18 @@ dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8
     const uint32_t nbb = B ? pack_blocks_for((uint64_t)r.KW * r.n_pad, r.op) : 0;
     pa.nba = nba;
     pa.al = (a_al ? 1u : 0u) | (b_al ? 2u : 0u);
-    if (r.op != OP_MAD && ((uintptr_t)work & 15)) return DQT_E_INVALID;   // 16-byte stores
+    if (r.op != OP_MAD && !out_al) return DQT_E_INVALID;   // 16-byte stores
     if (nba + nbb == 0) return DQT_OK;
     hipLaunchKernelGGL(k_gemm_pack, dim3(nba + nbb), dim3(256), 0, s, pa);
     DQT_LAUNCH_CHECK("fgemm(pack)");
     return DQT_OK;
+}
+
+// Packing step into a workspace: A's packed copy at its start, B's after it.
+dqt_status fgemm_pack_enqueue(uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A, uint64_t lda, const uint8_t* B,
+                              uint64_t ldb, const GemmPlanResolved& r, void* work, hipStream_t s) {
+    uint8_t* w = reinterpret_cast<uint8_t*>(work);
+    return fgemm_pack_sides(m, n, kdim, A, lda, B, ldb, r, w, w + side_bytes(r, 0), s);
 }
 
 // Multiplication and extraction on packed operands.
@@ -636,6 +656,7 @@ extern "C" dqt_status dqt_fgemm_pack(uint32_t p, uint64_t m, uint64_t n, uint64_
     if ((d_A && lda < kdim) || (d_B && ldb < n) || lda > 0xFFFFFFFFull || ldb > 0xFFFFFFFFull) return DQT_E_INVALID;
     DQT_TRY(fgemm_common_checks(p, m, n, kdim, plan, work_bytes, d_work, &r));
     DQT_TRY(ensure_device_ready());
+    DQT_TRY(debug_gate(reinterpret_cast<hipStream_t>(stream), p, {{d_A, m, kdim, lda}, {d_B, kdim, n, ldb}}));
     return fgemm_pack_enqueue(m, n, kdim, d_A, lda, d_B, ldb, r, d_work, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -671,14 +692,12 @@ extern "C" dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n
 static dqt_status side_plan(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, int side, const dqt_gemm_plan* plan,
                             GemmPlanResolved* r) {
     if (side != 0 && side != 1) return DQT_E_INVALID;
+    // The layout of a packed side must follow from (p, kdim, plan) alone; the
+    // shape rule picks its algorithm from all three dimensions, so a side
+    // packed on its own could disagree with the product that reads it.
+    if (plan && plan->algo == DQT_GEMM_BY_SHAPE) return DQT_E_INVALID;
     // the packed layout of one side does not depend on the other dimension
     return resolve_plan(p, side == 0 ? rows_or_cols : 1, side == 1 ? rows_or_cols : 1, kdim, plan, r);
-}
-
-static size_t side_bytes(const GemmPlanResolved& r, int side) {
-    if (is_f64_algo(r.algo)) return f64_side_bytes(r, side);
-    if (r.algo == DQT_GEMM_MFMA) return (size_t)r.k_pad * (side == 0 ? r.m_pad : r.n_pad);
-    return (size_t)r.KW * (side == 0 ? r.m_pad : r.n_pad) * sizeof(uint32_t);
 }
 
 extern "C" size_t dqt_fgemm_packed_bytes(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, int side,
@@ -698,19 +717,18 @@ extern "C" dqt_status dqt_fgemm_pack_side(uint32_t p, uint64_t rows_or_cols, uin
     if ((side == 0 && ldx < kdim) || (side == 1 && ldx < rows_or_cols) || ldx > 0xFFFFFFFFull) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // the pack kernels address A's words from the workspace start and B's after
-    // A's; place the target so that the requested side lands on d_packed
-    uint8_t* base = reinterpret_cast<uint8_t*>(d_packed);
-    if (side == 1) base -= side_bytes(r, 0);
+    if (side == 0) DQT_TRY(debug_gate(s, p, {{d_X, rows_or_cols, kdim, ldx}}));
+    else DQT_TRY(debug_gate(s, p, {{d_X, kdim, rows_or_cols, ldx}}));
     if (side == 0)
-        return fgemm_pack_enqueue(rows_or_cols, 1, kdim, d_X, ldx, nullptr, 1, r, base, s);
-    return fgemm_pack_enqueue(1, rows_or_cols, kdim, nullptr, 1, d_X, ldx, r, base, s);
+        return fgemm_pack_sides(rows_or_cols, 1, kdim, d_X, ldx, nullptr, 1, r, d_packed, nullptr, s);
+    return fgemm_pack_sides(1, rows_or_cols, kdim, nullptr, 1, d_X, ldx, r, nullptr, d_packed, s);
 }
 
 extern "C" dqt_status dqt_fgemm_packed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const void* d_CA,
                                        const void* d_CB, uint8_t* d_C, uint64_t ldc, const dqt_gemm_plan* plan,
                                        void* stream) {
     GemmPlanResolved r;
+    if (plan && plan->algo == DQT_GEMM_BY_SHAPE) return DQT_E_INVALID;   // as dqt_fgemm_pack_side
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
     if (m == 0 || n == 0) return DQT_OK;
     if (kdim == 0) {
@@ -739,5 +757,6 @@ extern "C" dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdi
     if (r.ws_bytes && (!d_work || work_bytes < r.ws_bytes)) return DQT_E_WORKSPACE;
     if (r.ws_bytes && ((uintptr_t)d_work & 15)) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
+    DQT_TRY(debug_gate(reinterpret_cast<hipStream_t>(stream), p, {{d_A, m, kdim, lda}, {d_B, kdim, n, ldb}}));
     return fgemm_enqueue(p, m, n, kdim, d_A, lda, d_B, ldb, d_C, ldc, r, d_work, reinterpret_cast<hipStream_t>(stream));
 }

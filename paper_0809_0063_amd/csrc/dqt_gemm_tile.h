@@ -97,10 +97,11 @@ struct LaneWords<4> {
     }
 };
 
-// k-groups per unrolled step: the A words of one step stay within 64 SGPRs.
+// k-groups per pipeline step: the A words of two steps (the one being
+// multiplied and the one being loaded) stay within 64 SGPRs.
 template <int TM>
-struct KUnroll {
-    static constexpr int value = TM <= 8 ? 8 : (TM == 16 ? 4 : 2);
+struct PipeU {
+    static constexpr int value = TM >= 32 ? 1 : 32 / TM;
 };
 
 // FLUSH = false: the whole k range of a wave is one delayed-reduction
@@ -110,25 +111,29 @@ struct KUnroll {
 // SGPRs, which hold the prefetched words of A during the k loop).
 //
 // Packed layouts (tile-major, so that the operands of consecutive k-groups
-// are consecutive in memory and the loads of an unrolled step share one base
-// address with immediate offsets):
+// are consecutive in memory and the loads of a step share one base address
+// with immediate offsets):
 //   CA: [m_pad / TM][KW][TM]          row block, k-group, row in the block;
 //   CB: [n_pad / (64 TN)][KW][64 TN]  column block, k-group, column in the
 //                                     block (lane l owns columns l TN .. l TN + TN - 1).
+//
+// The k loop is software-pipelined in steps of U k-groups with two register
+// buffers: the loads of step t+1 are issued right after the first k-group of
+// step t has used step t's words, so they overlap the rest of step t.  (Scalar
+// loads complete out of order, so a wave can only wait for all of its
+// outstanding scalar loads at once; issuing the next step's A words after the
+// current ones have been consumed keeps that wait from covering them.)
+// Scheduling barriers keep the compiler from moving the loads across.
 template <int OP, int TM, int TN, int S, bool FLUSH, int EPI>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32_t cb, uint32_t wave, uint32_t lane,
                                           uint32_t* red) {
-    constexpr int U = KUnroll<TM>::value;
+    constexpr int U = PipeU<TM>::value;
     typedef typename LaneWords<TN>::T V;
     const uint32_t row0 = rb * TM;
     const uint32_t col0 = cb * 64u * TN + lane * TN;
 
     uint32_t acc[TM][TN];
     uint32_t wide[FLUSH ? TM : 1][FLUSH ? TN : 1];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = 0;
     if (FLUSH) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -142,27 +147,64 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
     const V* __restrict__ pb = reinterpret_cast<const V*>(g.CB + ((size_t)cb * g.KW + kw0) * (64u * TN)) + lane;
     const uint32_t mask = (1u << g.b) - 1u;
 
-    auto body = [&](int u) {
-        uint32_t av[TM], bv[TN];
+    uint32_t a0[U][TM], a1[U][TM];
+    V b0[U], b1[U];
+    // the words of step t (U k-groups from pa, pb)
+    auto load = [&](uint32_t (&a)[U][TM], V (&bv)[U], uint32_t t) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i) av[i] = pa[u * TM + i];
-        LaneWords<TN>::get(pb[u * 64], bv);
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[u][i] = pa[(t * U + u) * TM + i];
+            bv[u] = pb[(t * U + u) * 64];
+        }
+    };
+    // one k-group; zero = the accumulators start from 0 here
+    auto kgroup = [&](const uint32_t (&a)[TM], const V& bvec, bool zero) {
+        uint32_t bw[TN];
+        LaneWords<TN>::get(bvec, bw);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = mac<OP>(av[i], bv[j], acc[i][j]);
+            for (int j = 0; j < TN; ++j) acc[i][j] = mac<OP>(a[i], bw[j], zero ? 0u : acc[i][j]);
     };
-    // n consecutive k-groups from (pa, pb), advancing both
-    auto run = [&](uint32_t n) {
-        uint32_t c = 0;
-        for (; c + U <= n; c += U) {
+    // step t from (a, bv) while the words of step tn are loaded into (an, bn)
+    auto step = [&](const uint32_t (&a)[U][TM], const V (&bv)[U], uint32_t (&an)[U][TM], V (&bn)[U], uint32_t tn,
+                    bool zero) {
+        kgroup(a[0], bv[0], zero);
+        __builtin_amdgcn_sched_barrier(0);
+        load(an, bn, tn);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u) body(u);
-            pa += U * TM;
-            pb += U * 64;
+        for (int u = 1; u < U; ++u) kgroup(a[u], bv[u], false);
+    };
+    // n consecutive k-groups from (pa, pb), advancing both; zero = the
+    // accumulators start from 0 (folded into the first k-group)
+    auto run = [&](uint32_t n, bool zero) {
+        const uint32_t nsteps = n / U;
+        if (nsteps) {
+            // every load is unconditional: the last step reloads its own words
+            const uint32_t last = nsteps - 1;
+            load(a0, b0, 0);
+            step(a0, b0, a1, b1, min(1u, last), zero);
+            uint32_t t = 1;
+            for (; t + 2 <= nsteps; t += 2) {
+                step(a1, b1, a0, b0, t + 1, false);
+                step(a0, b0, a1, b1, min(t + 2, last), false);
+            }
+            if (t < nsteps) step(a1, b1, a0, b0, t, false);
+            pa += nsteps * U * TM;
+            pb += nsteps * U * 64;
+        } else if (zero) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = 0;
         }
-        for (; c < n; ++c) {
-            body(0);
+        for (uint32_t c = nsteps * U; c < n; ++c) {
+            uint32_t a[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = pa[i];
+            kgroup(a, pb[0], false);
             pa += TM;
             pb += 64;
         }
@@ -170,49 +212,74 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
 
     const uint32_t nk = kw1 - kw0;
     if (!FLUSH) {
-        run(nk);
+        run(nk, true);
     } else {
         // delayed-reduction interval in k-groups
-        const uint32_t step = g.lw ? g.lw : (nk ? nk : 1u);
-        for (uint32_t kc = 0; kc < nk; kc += step) {
-            run(min(step, nk - kc));
+        const uint32_t step_k = g.lw ? g.lw : (nk ? nk : 1u);
+        for (uint32_t kc = 0; kc < nk; kc += step_k) {
+            run(min(step_k, nk - kc), true);
             // end of an interval: move the middle digit out
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    wide[FLUSH ? i : 0][FLUSH ? j : 0] += (acc[i][j] >> g.b) & mask;
-                    acc[i][j] = 0;
-                }
+                for (int j = 0; j < TN; ++j) wide[FLUSH ? i : 0][FLUSH ? j : 0] += (acc[i][j] >> g.b) & mask;
         }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = wide[FLUSH ? i : 0][FLUSH ? j : 0];
     }
     const GemmArgs& ge = g;
-    // value of each output over this wave's k range
-    if (OP == OP_DOT2) {
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-                acc[i][j] = FLUSH ? wide[FLUSH ? i : 0][FLUSH ? j : 0] : ((acc[i][j] >> ge.b) & mask);
-    }
+    // Packed path without flush: acc holds the raw accumulators.  Their digits
+    // 0 and 1 never carry over the whole k range (eq:lower for kdim), so the
+    // raw words of the S waves are added as they are and the middle digit is
+    // taken once, from the sum.
+    constexpr bool RAW = (OP == OP_DOT2) && !FLUSH;
 
     // split-k: add the S partial sums through LDS; wave w finishes rows i = w, w+S, ...
+    // Layout [wave][row][lane][TN]: each lane writes and reads its TN words as one vector.
     if (S > 1) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) red[((wave * TM + i) * TN + j) * 64 + lane] = acc[i][j];
+        for (int i = 0; i < TM; ++i) {
+            uint32_t* dst = &red[((wave * TM + i) * 64 + lane) * TN];
+            if (TN == 4) *reinterpret_cast<uint4*>(dst) = make_uint4(acc[i][0], acc[i][1], acc[i][TN - 2], acc[i][TN - 1]);
+            else *reinterpret_cast<uint2*>(dst) = make_uint2(acc[i][0], acc[i][1]);
+        }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
             if ((uint32_t)i % S != wave) continue;
+            uint32_t sum[TN];
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                uint32_t s = 0;
+            for (int j = 0; j < TN; ++j) sum[j] = 0;
 #pragma unroll
-                for (int w = 0; w < S; ++w) s += red[((w * TM + i) * TN + j) * 64 + lane];
-                acc[i][j] = s;
+            for (int w = 0; w < S; ++w) {
+                const uint32_t* src = &red[((w * TM + i) * 64 + lane) * TN];
+                uint32_t v[TN];
+                if (TN == 4) {
+                    const uint4 x = *reinterpret_cast<const uint4*>(src);
+                    v[0] = x.x;
+                    v[1] = x.y;
+                    v[TN - 2] = x.z;
+                    v[TN - 1] = x.w;
+                } else {
+                    const uint2 x = *reinterpret_cast<const uint2*>(src);
+                    v[0] = x.x;
+                    v[TN - 1] = x.y;
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) sum[j] += v[j];
             }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = sum[j];
+        }
+    }
+    if (RAW) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            if (S > 1 && (uint32_t)i % S != wave) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = (acc[i][j] >> ge.b) & mask;
         }
     }
 

@@ -135,6 +135,7 @@ extern "C" dqt_status dqt_gf_dot_u8(const uint8_t* d_a, const uint8_t* d_b, uint
     if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DQT_TRY(debug_gate(s, p, {{d_a, count, (uint64_t)n * k, (uint64_t)n * k}, {d_b, count, (uint64_t)n * k, (uint64_t)n * k}}));
     switch (k) {
         case 2: return launch_gf_dot<2>(d_a, d_b, d_out, count, n, nq, ra, ga, s);
         case 3: return launch_gf_dot<3>(d_a, d_b, d_out, count, n, nq, ra, ga, s);

@@ -18,7 +18,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libdqt.so")
 
 DQT_OK, DQT_E_INVALID, DQT_E_BOUND, DQT_E_UNSUPPORTED, DQT_E_DEVICE, DQT_E_WORKSPACE, DQT_E_INPUT = 0, -1, -2, -3, -4, -5, -6
-# DQT_DEBUG=1: every call checks that its uint8 inputs are residues in [0, p) first (blocking)
+# DQT_DEBUG=1: the library's debug mode is turned on at load (dqt_debug_enable with a device status
+# word): every call then checks its data on the device first and fails with DQT_E_INPUT (blocking)
 DEBUG = os.environ.get("DQT_DEBUG", "") not in ("", "0")
 
 GEMM_AUTO, GEMM_CMM, GEMM_PLAIN, GEMM_DOT4, GEMM_MFMA, GEMM_RIGHT, GEMM_LEFT, GEMM_FULL = 0, 1, 2, 3, 4, 5, 6, 7
@@ -37,7 +38,7 @@ class DQTError(RuntimeError):
 
 class _Qadic(ctypes.Structure):
     _fields_ = [("p", ctypes.c_uint32), ("log2q", ctypes.c_uint32), ("k_coeffs", ctypes.c_uint32),
-                ("nres", ctypes.c_uint32), ("n_accum", ctypes.c_uint64)]
+                ("nres", ctypes.c_uint32), ("n_accum", ctypes.c_uint64), ("word_bits", ctypes.c_uint32)]
 
 
 class _GemmPlan(ctypes.Structure):
@@ -60,15 +61,17 @@ class _BatchOpts(ctypes.Structure):
 
 @dataclass(frozen=True)
 class Qadic:
-    """q-adic packing parameters (p, q = 2^log2q, k coefficients, nres digits, n accumulated products)."""
+    """q-adic packing parameters (p, q = 2^log2q, k coefficients, nres digits, n accumulated products,
+    word width beta; 0 = 53)."""
     p: int
     log2q: int
     k_coeffs: int
     nres: int
     n_accum: int = 1
+    word_bits: int = 0
 
     def _c(self) -> _Qadic:
-        return _Qadic(self.p, self.log2q, self.k_coeffs, self.nres, self.n_accum)
+        return _Qadic(self.p, self.log2q, self.k_coeffs, self.nres, self.n_accum, self.word_bits)
 
 
 @dataclass(frozen=True)
@@ -101,7 +104,9 @@ def _load():
     QP = ctypes.POINTER(_Qadic)
     sigs = {
         "dqt_qadic_check": [QP],
-        "dqt_qadic_choose": [U32, U32, U64, QP],
+        "dqt_qadic_choose": [U32, U32, U64, U32, QP],
+        "dqt_debug_enable": [V],
+        "dqt_sync_status": [V],
         "dqt_pack": [V, U64, QP, I, V, V],
         "dqt_polymul": [V, V, U64, QP, V, V],
         "redq_unpack": [V, U64, QP, V, V, V],
@@ -155,6 +160,8 @@ def _load():
     lib.dqt_version.argtypes = []
     lib.dqt_version.restype = ctypes.c_char_p
     _lib = lib
+    if DEBUG:
+        debug_enable(True)
     return lib
 
 
@@ -172,7 +179,7 @@ def _status_str(s: int) -> str:
 
 def _check(status: int, where: str):
     if status != DQT_OK:
-        detail = _load().dqt_last_error().decode() if status == DQT_E_DEVICE else ""
+        detail = _load().dqt_last_error().decode() if status in (DQT_E_DEVICE, DQT_E_INPUT) else ""
         raise DQTError(status, where, detail)
 
 
@@ -213,11 +220,24 @@ def check_input(t: torch.Tensor, p: int, stream=None) -> None:
                                       _stream(stream)), "dqt_check_input_u8")
 
 
-def _debug_inputs(p: int, *ts) -> None:
-    if DEBUG:
-        for t in ts:
-            if t is not None:
-                check_input(t, p)
+_STATUS = {}
+
+
+def debug_enable(on: bool = True, device=None) -> None:
+    """Turn the library's debug mode on (with a device status word on `device`) or off."""
+    if not on:
+        _check(_load().dqt_debug_enable(None), "dqt_debug_enable")
+        return
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if dev not in _STATUS:
+        _STATUS[dev] = torch.zeros(1, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(_load().dqt_debug_enable(_dev(_STATUS[dev], "status")), "dqt_debug_enable")
+
+
+def sync_status(stream=None) -> None:
+    """dqt_sync_status: wait for the stream; raise DQTError(DQT_E_INPUT) if a debug check failed."""
+    _check(_load().dqt_sync_status(_stream(stream)), "dqt_sync_status")
 
 
 def _host_modulus(modulus: Sequence[int]):
@@ -237,10 +257,10 @@ def qadic_check(q: Qadic) -> int:
     return _load().dqt_qadic_check(ctypes.byref(c))
 
 
-def qadic_choose(p: int, k_coeffs: int, n_accum: int = 1) -> Qadic:
+def qadic_choose(p: int, k_coeffs: int, n_accum: int = 1, word_bits: int = 0) -> Qadic:
     c = _Qadic()
-    _check(_load().dqt_qadic_choose(p, k_coeffs, n_accum, ctypes.byref(c)), "dqt_qadic_choose")
-    return Qadic(c.p, c.log2q, c.k_coeffs, c.nres, c.n_accum)
+    _check(_load().dqt_qadic_choose(p, k_coeffs, n_accum, word_bits, ctypes.byref(c)), "dqt_qadic_choose")
+    return Qadic(c.p, c.log2q, c.k_coeffs, c.nres, c.n_accum, c.word_bits)
 
 
 # --- one-word path -------------------------------------------------------------
@@ -290,7 +310,6 @@ def polymul_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Ten
                log2q: int = 0):
     """Packed fused product: uint8 [N, k] x uint8 [N, k] -> uint8 [N, 2k-1] over F_p (q = 2^log2q, 0 = smallest)."""
     _u8_pair(a, b)
-    _debug_inputs(p, a, b)
     n, k = a.shape
     if b.shape[1] != k:
         raise ValueError("a and b must have the same k")
@@ -303,7 +322,6 @@ def polymul_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Ten
 
 def polymul_plain_u8(a: torch.Tensor, b: torch.Tensor, p: int, out: Optional[torch.Tensor] = None, stream=None):
     _u8_pair(a, b)
-    _debug_inputs(p, a, b)
     n, k = a.shape
     if out is None:
         out = torch.empty((n, 2 * k - 1), dtype=torch.uint8, device=a.device)
@@ -316,7 +334,6 @@ def polymul_fqt_u8(a: torch.Tensor, b: torch.Tensor, p: int, block: int = 0, out
                    stream=None):
     """Long products by blocks (FQT): uint8 [N, na] x uint8 [N, nb] -> uint8 [N, na+nb-1]."""
     _u8_pair(a, b)
-    _debug_inputs(p, a, b)
     n, na = a.shape
     nb = b.shape[1]
     if out is None:
@@ -330,7 +347,6 @@ def polymul_fqt_kara_u8(a: torch.Tensor, b: torch.Tensor, p: int, levels: int = 
                         out: Optional[torch.Tensor] = None, stream=None):
     """FQT products with Karatsuba block products (levels 1 or 2): same shapes and bytes as polymul_fqt_u8."""
     _u8_pair(a, b)
-    _debug_inputs(p, a, b)
     n, na = a.shape
     nb = b.shape[1]
     if out is None:
@@ -345,7 +361,6 @@ def gf_mul_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
               out: Optional[torch.Tensor] = None, stream=None, log2q: int = 0):
     """Packed GF(p^k) products: uint8 [N, k] each, modulus = k+1 monic coefficients (low first)."""
     _u8_pair(a, b)
-    _debug_inputs(p, a, b)
     n, k = a.shape
     if out is None:
         out = torch.empty((n, k), dtype=torch.uint8, device=a.device)
@@ -361,7 +376,6 @@ def gf_dot_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
     """Dot products over GF(p^k) by FGDP: uint8 [N, n, k] x uint8 [N, n, k] -> uint8 [N, k]."""
     if a.dim() != 3 or a.shape != b.shape:
         raise ValueError("a and b must be [N, n, k] with the same shape")
-    _debug_inputs(p, a, b)
     N, n, k = a.shape
     if out is None:
         out = torch.empty((N, k), dtype=torch.uint8, device=a.device)
@@ -375,7 +389,6 @@ def gf_dot_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
 def gf_mul_plain_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
                     out: Optional[torch.Tensor] = None, stream=None):
     _u8_pair(a, b)
-    _debug_inputs(p, a, b)
     n, k = a.shape
     if out is None:
         out = torch.empty((n, k), dtype=torch.uint8, device=a.device)
@@ -398,7 +411,6 @@ def fgemm(A: torch.Tensor, B: torch.Tensor, p: int, plan: Optional[GemmPlan] = N
     """C = A.B mod p for uint8 A [m, k], B [k, n] (row-major, contiguous)."""
     if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
         raise ValueError("A [m,k] and B [k,n] required")
-    _debug_inputs(p, A, B)
     m, kdim = A.shape
     n = B.shape[1]
     if out is None:

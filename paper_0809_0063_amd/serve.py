@@ -48,6 +48,13 @@ class Request:
     event: Optional[torch.cuda.Event] = None
     out: Optional[torch.Tensor] = None
     bytes: int = 0
+    # device buffers held while the request is active (released at completion;
+    # the residency cache keeps its own references to cached operands)
+    A: Optional[torch.Tensor] = None
+    B: Optional[torch.Tensor] = None
+    CA: Optional[torch.Tensor] = None
+    CB: Optional[torch.Tensor] = None
+    stream: Optional[torch.cuda.Stream] = None
 
 
 class ResidencyCache:
@@ -206,7 +213,9 @@ class Server:
 
     # --- the loop -----------------------------------------------------------------
 
-    def run(self, arrivals: np.ndarray, items: np.ndarray, max_wall: float = 600.0, warmup: int = 0):
+    def run(self, arrivals: np.ndarray, items: np.ndarray, max_wall: float = 600.0, warmup: int = 0,
+            on_step=None):
+        """Serve the requests; `on_step(active, finished)`, if given, is called once per loop pass."""
         reqs = [Request(i, int(it), float(t)) for i, (t, it) in enumerate(zip(arrivals, items))]
         pending = collections.deque(reqs)
         waiting: collections.deque = collections.deque()
@@ -241,10 +250,16 @@ class Server:
                     r.done = time.perf_counter() - t0
                     self.free_slots.append(r.slot)
                     self.active_bytes -= r.bytes
+                    # only the output outlives the request: its operands and packed words go
+                    # back to the allocator (or stay only as far as the cache holds them)
+                    r.A = r.B = r.CA = r.CB = None
+                    r.stream = None
                     finished.append(r)
                 else:
                     still.append(r)
             active = still
+            if on_step is not None:
+                on_step(active, finished)
             if not active and waiting == collections.deque() and pending:
                 # idle until the next arrival
                 wait = pending[0].arrival - (time.perf_counter() - t0)

@@ -11,7 +11,7 @@
 from __future__ import annotations
 
 import time
-from typing import Dict, Optional
+from typing import Callable, Dict, Optional
 
 import numpy as np
 import torch
@@ -24,9 +24,10 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
 def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inputs.SEED_BATCH,
-            algo: Optional[int] = None) -> Dict[str, float]:
+            algo: Optional[int] = None, verify: Optional[Callable] = None) -> Dict[str, float]:
     """One graph replay of the whole batch; `algo` forces one algorithm for every product
-    (otherwise the tuner's per-bucket plan, or the library default)."""
+    (otherwise the tuner's per-bucket plan, or the library default).  `verify(items, outputs)`,
+    if given, receives the items and their output tensors after the timed replays."""
     dev = torch.device("cuda:0")
     items = inputs.batch_items(n_items, seed=seed)
     t0 = time.perf_counter()
@@ -70,10 +71,13 @@ def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inpu
     e1.record()
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) / 1e3 / replays
-    # a cheap spot check of the replayed output (full parity is in the tests)
+    # a cheap spot check of the replayed output; the tests check every output of this same
+    # call (tuned plans, launch shape, graph replays) against the oracle's digests
     C0 = ops[0]["C"].cpu().numpy()
     A0, B0 = inputs.item_operands(items[0])
     assert (C0[:1] == (A0[:1].astype(np.int64) @ B0.astype(np.int64)) % items[0].p).all()
+    if verify is not None:
+        verify(items, [d["C"] for d in ops])
     batch.close()
     return {"products": n_items, "ms_per_replay": round(sec * 1e3, 3), "fp_gop_s": round(2 * macs / sec / 1e9, 1),
             "packed_lane_op_frac": round(dot_ops / sec / PEAK_LANE_OPS, 4), "launch": list(launch),

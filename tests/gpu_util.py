@@ -31,3 +31,19 @@ def unaligned_empty(shape, offset: int = 1) -> torch.Tensor:
     n = int(np.prod(shape))
     flat = torch.zeros(n + 64, dtype=torch.uint8, device=device())
     return flat[offset:offset + n].view(shape)
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)), "golden")
+
+
+def load_digests(name: str):
+    """Rows of a digest file under tests/golden/ (written by tests/golden/make_digests.py from the oracle)."""
+    import os
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+def digest(x: np.ndarray) -> str:
+    """128-bit prefix of SHA-256 over the bytes of x in C order (the digest the golden files hold)."""
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(x).tobytes()).hexdigest()[:32]

@@ -30,7 +30,7 @@ def D():
 def test_header_parses():
     names = declared_functions()
     for must in ("dqt_pack", "dqt_polymul", "redq_unpack", "dqt_fgemm", "dqt_qadic_check", "dqt_qadic_choose",
-                 "dqt_fgemm_batched", "dqt_polymul_u8", "dqt_gf_mul_u8"):
+                 "dqt_fgemm_batched", "dqt_polymul_u8", "dqt_gf_mul_u8", "dqt_debug_enable", "dqt_sync_status"):
         assert must in names
 
 
@@ -147,7 +147,7 @@ def test_compressed_f64_plan_sizes(D):
 
 def test_input_status(D):
     lib = D.lib()
-    assert lib.dqt_status_str(D.DQT_E_INPUT) == b"input entry not a residue in [0, p)"
+    assert lib.dqt_status_str(D.DQT_E_INPUT).startswith(b"input check failed")
     # argument checks before any device call
     assert lib.dqt_check_input_u8(None, 10, 3, None, None) == D.DQT_E_INVALID
     assert lib.dqt_check_input_u8(None, 0, 3, None, None) == D.DQT_E_INVALID
@@ -175,3 +175,62 @@ def test_table_window_setting(D):
     assert e.value.status == D.DQT_E_INVALID
     assert D.get_table_window() == 0
     assert "dqt_get_table_window" in declared_functions()
+
+
+def test_word_bits_bound_the_packed_result(D):
+    """eq:bounds with beta = word_bits: nres log2 q <= beta; 0 means 53, more than 53 is unsupported."""
+    for beta in (0, 53, 40, 24):
+        b_eff = beta or 53
+        for p in (2, 3, 7):
+            for k in (1, 2, 3, 4):
+                want = None
+                for b in range(1, 33):
+                    if O.dqt_bounds_ok(p, k, 1, b, b_eff):
+                        want = b
+                        break
+                if want is None:
+                    with pytest.raises(D.DQTError) as e:
+                        D.qadic_choose(p, k, 1, word_bits=beta)
+                    assert e.value.status == D.DQT_E_BOUND
+                else:
+                    q = D.qadic_choose(p, k, 1, word_bits=beta)
+                    assert (q.log2q, q.word_bits) == (want, beta)
+    # degree 3 over F_3 at q = 2^6 needs 42 bits: fits beta = 42, not 41
+    assert D.qadic_check(D.Qadic(3, 6, 4, 7, 1, 42)) == 0
+    assert D.qadic_check(D.Qadic(3, 6, 4, 7, 1, 41)) == D.DQT_E_BOUND
+    assert D.qadic_check(D.Qadic(3, 6, 4, 7, 1, 60)) == D.DQT_E_UNSUPPORTED
+    with pytest.raises(D.DQTError) as e:
+        D.qadic_choose(3, 4, 1, word_bits=64)
+    assert e.value.status == D.DQT_E_UNSUPPORTED
+    lib = D.lib()
+    q = D.Qadic(3, 6, 4, 7, 1, 60)._c()
+    assert lib.redq_unpack(None, 10, ctypes.byref(q), None, None, None) == D.DQT_E_UNSUPPORTED
+
+
+def test_uint32_sums_bound_every_word_gemm(D):
+    """CMM, PLAIN and DOT4 add whole dot products in uint32: kdim (p-1)^2 < 2^32 or the plan is refused."""
+    for p in (23, 13, 3):
+        e2 = (p - 1) ** 2
+        k_ok = (2 ** 32 - 1) // e2
+        for algo in (D.GEMM_CMM, D.GEMM_AUTO, D.GEMM_PLAIN, D.GEMM_DOT4):
+            pl = D.GemmPlan(algo=algo)
+            assert D.fgemm_workspace_size(p, 1, 1, k_ok + 1, pl) == 0, (p, algo)
+            if k_ok < 2 ** 31:
+                assert D.fgemm_workspace_size(p, 1, 1, k_ok, pl) > 0, (p, algo)
+    # the example of a 23-residue product with 9,000,000 terms
+    assert D.fgemm_workspace_size(23, 1, 1, 9_000_000, D.GemmPlan(algo=D.GEMM_CMM)) == 0
+    assert D.fgemm_workspace_size(23, 1, 1, 9_000_000, None) == 0
+    lib = D.lib()
+    assert lib.dqt_fgemm(23, 1, 1, 9_000_000, None, 9_000_000, None, 1, None, 1, None, None, 0, None) == \
+        D.DQT_E_UNSUPPORTED
+
+
+def test_shape_rule_refused_for_one_packed_side(D):
+    """A side packed on its own cannot know the algorithm the shape rule would pick for the product."""
+    pl = D.GemmPlan(algo=D.GEMM_BY_SHAPE)
+    for side in (0, 1):
+        assert D.fgemm_packed_bytes(3, 1500, 1800, side, pl) == 0
+    lib = D.lib()
+    cp = pl._c()
+    assert lib.dqt_fgemm_pack_side(3, 8, 8, None, 8, 0, ctypes.byref(cp), None, None) == D.DQT_E_INVALID
+    assert lib.dqt_fgemm_packed(3, 8, 8, 8, None, None, None, 8, ctypes.byref(cp), None) == D.DQT_E_INVALID

@@ -324,9 +324,8 @@ def test_check_input_and_debug_mode(dqt):
         dqt.check_input(bad, 3)
     assert e.value.status == dqt.DQT_E_INPUT
     dqt.check_input(bad, 5)
-    old = dqt.DEBUG
     try:
-        dqt.DEBUG = True
+        dqt.debug_enable(True)     # the library's debug mode with a device status word
         assert (to_host(dqt.polymul_u8(da, db, 3)) == O.polymul(a, b, 3)).all()
         with pytest.raises(dqt.DQTError) as e:
             dqt.polymul_u8(bad, db, 3)
@@ -336,7 +335,7 @@ def test_check_input_and_debug_mode(dqt):
         with pytest.raises(dqt.DQTError):
             dqt.fgemm(A, A, 7)
     finally:
-        dqt.DEBUG = old
+        dqt.debug_enable(False)
 
 
 def test_empty_batches_every_entry(dqt):

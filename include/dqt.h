@@ -336,6 +336,23 @@ dqt_status dqt_fgemm(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const ui
                      void *d_work, size_t work_bytes, void *stream);
 
 /*
+ * dqt_fgemm for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it): same arguments and results as dqt_fgemm, without the workspace.
+ * The packed operands go to a static device array inside the library, one
+ * per GPU, held until the process ends; the call allocates nothing.  Its
+ * size is dqt_fgemm_noalloc_max_bytes() (32 MiB): a product whose
+ * dqt_fgemm_workspace_size exceeds it gets DQT_E_WORKSPACE, before anything
+ * is enqueued.  All calls on one GPU share that array: calls that overlap on
+ * one GPU (concurrent streams or threads) race and give undefined results;
+ * calls ordered on one stream are safe (nothing needs clearing in between).
+ */
+dqt_status dqt_fgemm_noalloc(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t *d_A, uint64_t lda,
+                             const uint8_t *d_B, uint64_t ldb, uint8_t *d_C, uint64_t ldc, const dqt_gemm_plan *plan,
+                             void *stream);
+size_t dqt_fgemm_noalloc_max_bytes(void);
+
+/*
  * The two phases of dqt_fgemm on their own (section 7.1: compression,
  * multiplication and extraction; compressed matrices are often reused).
  * dqt_fgemm_pack writes the packed operands of (p, m, n, kdim, plan) into

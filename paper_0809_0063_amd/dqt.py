@@ -128,6 +128,7 @@ def _load():
         "dqt_fgemm_compute_timed": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V, V, V],
         "dqt_fgemm_pack_side": [U32, U64, U64, V, U64, I, ctypes.POINTER(_GemmPlan), V, V],
         "dqt_fgemm_packed": [U32, U64, U64, U64, V, V, V, U64, ctypes.POINTER(_GemmPlan), V],
+        "dqt_fgemm_noalloc": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V],
     }
     for name, args in sigs.items():
         if not hasattr(lib, name):
@@ -144,6 +145,9 @@ def _load():
     if hasattr(lib, "dqt_fgemm_packed_bytes"):
         lib.dqt_fgemm_packed_bytes.argtypes = [U32, U64, U64, I, ctypes.POINTER(_GemmPlan)]
         lib.dqt_fgemm_packed_bytes.restype = SZ
+    if hasattr(lib, "dqt_fgemm_noalloc_max_bytes"):
+        lib.dqt_fgemm_noalloc_max_bytes.argtypes = []
+        lib.dqt_fgemm_noalloc_max_bytes.restype = SZ
     if hasattr(lib, "dqt_set_table_window"):
         lib.dqt_set_table_window.argtypes = [U32]
         lib.dqt_set_table_window.restype = ctypes.c_int
@@ -424,6 +428,23 @@ def fgemm(A: torch.Tensor, B: torch.Tensor, p: int, plan: Optional[GemmPlan] = N
     _check(_load().dqt_fgemm(p, m, n, kdim, _dev(A, "A", torch.uint8), kdim, _dev(B, "B", torch.uint8), n,
                              _dev(out, "C", torch.uint8), n, ctypes.byref(pc) if pc is not None else None,
                              wptr, wbytes, _stream(stream)), "dqt_fgemm")
+    return out
+
+
+def fgemm_noalloc(A: torch.Tensor, B: torch.Tensor, p: int, out: torch.Tensor, plan: Optional[GemmPlan] = None,
+                  stream=None):
+    """dqt_fgemm_noalloc: C = A.B mod p into the caller's `out`, packed operands in the library's
+    static device array (no workspace, no allocation)."""
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("A [m,k] and B [k,n] required")
+    m, kdim = A.shape
+    n = B.shape[1]
+    if tuple(out.shape) != (m, n):
+        raise ValueError("out must be [m, n]")
+    pc = plan._c() if plan is not None else None
+    _check(_load().dqt_fgemm_noalloc(p, m, n, kdim, _dev(A, "A", torch.uint8), kdim, _dev(B, "B", torch.uint8), n,
+                                     _dev(out, "C", torch.uint8), n, ctypes.byref(pc) if pc is not None else None,
+                                     _stream(stream)), "dqt_fgemm_noalloc")
     return out
 
 

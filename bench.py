@@ -10,10 +10,13 @@ store.  Inputs are resident in HBM before the timed region.
 Printed: one JSON line.  `value` is F_p Gop/s (2 m n k per step) of the
 packed path; `roofline` is the packed multiply kernel against the VALU issue
 rate; `cpu_baseline` is the CPU oracle on a bounded sample; `extra` holds the
-other measured paths (plain per-entry, dot4 and INT8 matrix-core comparators,
-one-word polynomial products and GF(p^k) products against HBM, the batched
-workload of 10,000 products in one graph replay, and the serving loop's
-latency percentiles).
+other measured paths, by section (--sections): the plain per-entry, dot4, dot8,
+INT8 matrix-core and FP64 matrix-core compressed products with their own
+roofline fractions (gemm), one-word polynomial products against HBM, the
+four-call composition and the small workload in graph replays (polymul),
+long products by blocks (fqt), GF(p^k) products and dot products (gf), the
+batched workload of 10,000 products and the serving loop at three loads
+(workloads), and the CPU oracle on every workload (cpu).
 """
 from __future__ import annotations
 
@@ -29,8 +32,11 @@ sys.path.insert(0, ROOT)
 METRIC = "F_p GEMM Gop/s + polymul/s, packed DQT+REDQ vs plain modular; p99 latency"
 PEAK_LANE_OPS = 256 * 64 * 2.4e9          # VALU lane-instructions per second (256 CUs, wave64, 2.4 GHz)
 PEAK_HBM = 8.0e12                          # bytes per second
+PEAK_INT8_MFMA = 5.0e15                    # dense INT8 matrix-core ops per second
+PEAK_F64_FMA = 78.6e12 / 2                 # binary64 multiply-adds per second (78.6 TFLOP/s)
 MNK = 1024
-EVENT_EVERY = 8                            # steps per kernel-timed step
+MIN_EVENT_SAMPLES = 8                      # kernel-timed steps in the timed region, at least
+SECTIONS = ("gemm", "polymul", "fqt", "gf", "workloads", "cpu")
 
 
 # HBM bytes per launch of the timed multiply kernel, from two rocprofv3 counter
@@ -62,8 +68,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the comparator measurements")
+    ap.add_argument("--sections", default="", help="comma-separated subset of " + ",".join(SECTIONS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--no-extra", action="store_true", help="skip the comparator and other-path measurements")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the batched (10,000 products) and serving measurements")
     ap.add_argument("--copy-probe", action="store_true",
@@ -105,6 +112,266 @@ def timed_loop(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / 1e3 / steps   # seconds per call
 
 
+def kernel_us(call, torch, reps):
+    """Average duration of the multiply kernel of a prepared product (HIP events recorded by the launch)."""
+    evs = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    for a, b in evs:
+        call.pack()
+        call.compute_timed(a, b)
+    torch.cuda.synchronize()
+    return sum(hip_elapsed_ms(a, b) for a, b in evs) / len(evs) * 1e3
+
+
+def f64_digits(p, k):
+    """Digits per binary64 word of the matrix-core compressed products (eq:lower, eq:upper with 52 bits)."""
+    return 52 // max(1, (k * (p - 1) ** 2).bit_length())
+
+
+def bench_gemm_comparators(D, torch, dA, dB, dC, p, row0, stream, reps):
+    """Every F_p product of the 1024^3 workload: step (pack + multiply) and multiply kernel alone, with
+    the kernel's fraction of the roofline of the unit it runs on."""
+    n = MNK
+    macs = float(n) ** 3
+    e = f64_digits(p, n)
+    cases = (
+        ("cmm_redq_epilogue", D.GemmPlan(algo=D.GEMM_CMM, epilogue=D.EPI_REDQ), "alu", macs / 4),
+        ("plain_mad", D.GemmPlan(algo=D.GEMM_PLAIN), "alu", macs),
+        ("plain_dot4", D.GemmPlan(algo=D.GEMM_DOT4), "alu", macs / 4),
+        ("plain_dot8", D.GemmPlan(algo=D.GEMM_DOT8), "alu", macs / 8),
+        ("mfma_int8", D.GemmPlan(algo=D.GEMM_MFMA), "mfma_int8", 2 * macs),
+        ("right_compressed_f64mfma", D.GemmPlan(algo=D.GEMM_RIGHT), "mfma_f64", macs / e),
+        ("left_compressed_f64mfma", D.GemmPlan(algo=D.GEMM_LEFT), "mfma_f64", macs / e),
+        ("full_compressed_f64mfma", D.GemmPlan(algo=D.GEMM_FULL), "mfma_f64", macs / e),
+    )
+    peak = {"alu": PEAK_LANE_OPS, "mfma_int8": PEAK_INT8_MFMA, "mfma_f64": PEAK_F64_FMA}
+    unit = {"alu": "lane-instructions", "mfma_int8": "int8 ops", "mfma_f64": "binary64 FMAs"}
+    out = {}
+    for name, pl, bound, work in cases:
+        w2 = torch.empty(max(1, D.fgemm_workspace_size(p, n, n, n, pl)), dtype=torch.uint8, device=dA.device)
+        c2 = D.FgemmCall(dA, dB, dC, p, plan=pl, workspace=w2, stream=stream)
+        s = timed_loop(c2.run, reps, 3, torch)
+        assert (dC[:1].cpu().numpy() == row0).all(), name
+        kus = kernel_us(c2, torch, max(8, reps // 4))
+        out["fgemm_" + name] = {"gop_s": round(2 * macs / s / 1e9, 1), "us_per_step": round(s * 1e6, 2),
+                                "kernel_us": round(kus, 3), "kernel_fp_top_s": round(2 * macs / kus / 1e6, 1),
+                                "bound": bound, "work_per_launch": work, "work_unit": unit[bound],
+                                "kernel_frac": round(work / (kus * 1e-6) / peak[bound], 4)}
+    return out
+
+
+def polymul_graph_replays(D, torch, dev, inputs, count, sets, replays):
+    """One-word products on `sets` rotating buffer sets captured in one graph, replayed: time per launch."""
+    bufs = []
+    for i in range(sets):
+        a, b = inputs.polymul_pairs(count, 4, 3, seed=inputs.SEED_POLYMUL + 100 + i)
+        bufs.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev),
+                     torch.empty((count, 7), dtype=torch.uint8, device=dev)))
+    for a, b, o in bufs:      # outside capture first (device set-up)
+        D.polymul_u8(a, b, 3, out=o, log2q=6)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for a, b, o in bufs:
+                D.polymul_u8(a, b, 3, out=o, log2q=6)
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / (replays * sets)
+
+
+def ref_polymul_f3(a, b):
+    """Products of a few degree-3 polynomials over F_3 by integer numpy (a spot check of timed output)."""
+    import numpy as np
+    out = np.zeros((a.shape[0], 7), dtype=np.int64)
+    for i in range(4):
+        for j in range(4):
+            out[:, i + j] += a[:, i].astype(np.int64) * b[:, j]
+    return out % 3
+
+
+def bench_polymul(D, inputs, torch, dev, reps_big, reps_small):
+    out = {}
+    # one-word polynomial products: degree 3 over F_3, q = 2^6, 2^26 products (beyond the MALL)
+    n = 1 << 26
+    a, b = inputs.polymul_pairs(n, 4, 3)
+    da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    o = torch.empty((n, 7), dtype=torch.uint8, device=dev)
+    for name, fn in (("packed", lambda: D.polymul_u8(da, db, 3, out=o, log2q=6)),
+                     ("plain", lambda: D.polymul_plain_u8(da, db, 3, out=o))):
+        s = timed_loop(fn, reps_big, 2, torch)
+        out["polymul_deg3_f3_" + name] = {"polymul_s": round(n / s, 1), "GB_s": round(15 * n / s / 1e9, 1),
+                                          "hbm_frac": round(15 * n / s / PEAK_HBM, 4)}
+    # the four-call composition (pack a, pack b, packed product, REDQ unpack) on the same products;
+    # its own traffic is 4 + 8 bytes per pack (twice), 16 + 8 for the product, 8 + 7 for the unpack
+    q = D.Qadic(3, 6, 4, 7, 1)
+    wa = torch.empty(n, dtype=torch.int64, device=dev)
+    wb = torch.empty(n, dtype=torch.int64, device=dev)
+    wr = torch.empty(n, dtype=torch.int64, device=dev)
+
+    def four():
+        D.pack(da, q, out=wa)
+        D.pack(db, q, out=wb)
+        D.polymul_words(wa, wb, q, out=wr)
+        D.redq_unpack(wr, q, out=o)
+    s = timed_loop(four, reps_big, 2, torch)
+    assert (o[:4].cpu().numpy() == ref_polymul_f3(a[:4], b[:4])).all()
+    out["polymul_deg3_f3_four_calls"] = {"polymul_s": round(n / s, 1), "GB_s": round(63 * n / s / 1e9, 1),
+                                         "hbm_frac": round(63 * n / s / PEAK_HBM, 4),
+                                         "fused_bytes_GB_s": round(15 * n / s / 1e9, 1)}
+    del wa, wb, wr
+    # the correction-table window (section 3.5): none, two or three residues per lookup
+    try:
+        for j in (1, 2, 3):
+            D.set_table_window(j)
+            s = timed_loop(lambda: D.polymul_u8(da, db, 3, out=o, log2q=6), reps_big, 2, torch)
+            out[f"polymul_deg3_f3_table_window_{j}"] = {"GB_s": round(15 * n / s / 1e9, 1),
+                                                        "hbm_frac": round(15 * n / s / PEAK_HBM, 4)}
+    finally:
+        D.set_table_window(0)
+    del da, db, o
+    # the small workload itself: 65,536 products per launch, 8 rotating buffer sets in one graph
+    s = polymul_graph_replays(D, torch, dev, inputs, 65536, 8, max(20, reps_small))
+    out["polymul_65536_graph"] = {"us_per_launch": round(s * 1e6, 3), "polymul_s": round(65536 / s, 1),
+                                  "GB_s": round(15 * 65536 / s / 1e9, 1), "buffer_sets": 8}
+    return out
+
+
+def bench_fqt(D, inputs, torch, dev, reps_big):
+    out = {}
+    # long products by blocks (FQT): degree 47 over F_3, 2^20 products, schoolbook and Karatsuba blocks
+    nl = 1 << 20
+    al, bl = inputs.polymul_pairs(nl, 48, 3)
+    dal, dbl = torch.from_numpy(al).to(dev), torch.from_numpy(bl).to(dev)
+    ol = torch.empty((nl, 95), dtype=torch.uint8, device=dev)
+    for name, fn in (("fqt", lambda: D.polymul_fqt_u8(dal, dbl, 3, out=ol)),
+                     ("fqt_karatsuba1", lambda: D.polymul_fqt_kara_u8(dal, dbl, 3, levels=1, out=ol)),
+                     ("fqt_karatsuba2", lambda: D.polymul_fqt_kara_u8(dal, dbl, 3, levels=2, out=ol)),
+                     ("plain", lambda: D.polymul_plain_u8(dal, dbl, 3, out=ol))):
+        try:
+            s = timed_loop(fn, reps_big, 2, torch)
+            out["polymul_deg47_f3_" + name] = {"polymul_s": round(nl / s, 1), "us_per_call": round(s * 1e6, 1)}
+        except D.DQTError as e:
+            out["polymul_deg47_f3_" + name] = {"error": str(e)}
+    return out
+
+
+def bench_gf(D, inputs, torch, dev, reps_big):
+    out = {}
+    n = 1 << 26
+    for (pp, k) in ((3, 5), (7, 3)):
+        P = inputs.irreducible(pp, k)
+        x, y = inputs.gf_pairs(n, k, pp)
+        dx, dy = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+        oz = torch.empty((n, k), dtype=torch.uint8, device=dev)
+        for name, fn in (("packed", lambda: D.gf_mul_u8(dx, dy, pp, P, out=oz)),
+                         ("plain", lambda: D.gf_mul_plain_u8(dx, dy, pp, P, out=oz))):
+            s = timed_loop(fn, reps_big, 2, torch)
+            out[f"gf_{pp}^{k}_{name}"] = {"mul_s": round(n / s, 1), "GB_s": round(3 * k * n / s / 1e9, 1),
+                                         "hbm_frac": round(3 * k * n / s / PEAK_HBM, 4)}
+        del dx, dy, oz
+    # dot products over GF(3^5): 65,536 dot products of length 128 (2 n k + k bytes each)
+    pp, k, cnt, ln = 3, 5, 65536, 128
+    P = inputs.irreducible(pp, k)
+    g = inputs.rng(inputs.SEED_GF + 99)
+    xa = torch.from_numpy(g.integers(0, pp, size=(cnt, ln, k), dtype="uint8")).to(dev)
+    xb = torch.from_numpy(g.integers(0, pp, size=(cnt, ln, k), dtype="uint8")).to(dev)
+    od = torch.empty((cnt, k), dtype=torch.uint8, device=dev)
+    s = timed_loop(lambda: D.gf_dot_u8(xa, xb, pp, P, out=od), max(4, reps_big), 2, torch)
+    byts = cnt * (2 * ln * k + k)
+    out["gf_3^5_dot_n128"] = {"dot_s": round(cnt / s, 1), "GB_s": round(byts / s / 1e9, 1),
+                              "hbm_frac": round(byts / s / PEAK_HBM, 4), "us_per_call": round(s * 1e6, 1)}
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baselines(A, B, p, row0, fp_ops, inputs):
+    """The CPU oracle (reduce after every operation) on bounded samples of each workload, with one
+    thread and with all cores.  Returns the headline entry (the 1024^3 product, all cores) and the table."""
+    import oracle as O
+    cores = O.max_threads()
+
+    def rate(fn, work, min_s):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s:
+                return reps * work / dt, reps, dt
+
+    table = {"cpu_model": cpu_model(), "cores": cores}
+    # the F_p product: the whole of it with all cores; 64 of its rows on one thread
+    v_all, reps, dt = rate(lambda: O.fgemm(A, B, p), fp_ops, 6.0)
+    assert (O.fgemm(A[:1], B, p) == row0).all()
+    v_one, _, _ = rate(lambda: O.fgemm(A[:64], B, p, threads=1), 2.0 * 64 * MNK * MNK, 2.0)
+    table["fgemm_1024_p3"] = {"unit": "Gop/s", "all_cores": round(v_all / 1e9, 3), "one_thread": round(v_one / 1e9, 3)}
+    headline = {"value": round(v_all / 1e9, 3), "unit": "Gop/s", "cores": cores, "kind": "oracle",
+                "sample": f"the whole 1024^3 mod-3 product, {reps} times ({dt:.1f} s), reduce after every op",
+                "cpu_model": table["cpu_model"], "one_thread_value": round(v_one / 1e9, 3)}
+    # 65,536 products of degree 3 over F_3
+    a, b = inputs.polymul_pairs(65536, 4, 3)
+    table["polymul_65536_deg3_f3"] = {
+        "unit": "polymul/s", "all_cores": round(rate(lambda: O.polymul(a, b, 3), 65536, 1.0)[0], 1),
+        "one_thread": round(rate(lambda: O.polymul(a, b, 3, threads=1), 65536, 1.0)[0], 1)}
+    # GF(3^5) and GF(7^3) products (a 2^20 sample of the 2^24)
+    for pp, k in ((3, 5), (7, 3)):
+        P = inputs.irreducible(pp, k)
+        x, y = inputs.gf_pairs(1 << 20, k, pp)
+        table[f"gf_{pp}^{k}_mul"] = {
+            "unit": "mul/s", "sample": "2^20 products",
+            "all_cores": round(rate(lambda: O.gf_mul(x, y, pp, P), 1 << 20, 1.0)[0], 1),
+            "one_thread": round(rate(lambda: O.gf_mul(x, y, pp, P, threads=1), 1 << 20, 1.0)[0], 1)}
+    # the first 300 products of the batched workload
+    items = inputs.batch_items(10000)[:300]
+    ops = [inputs.item_operands(it) + (it.p,) for it in items]
+    work = sum(2.0 * it.n ** 3 for it in items)
+
+    def batch(th):
+        for Ai, Bi, pi in ops:
+            O.fgemm(Ai, Bi, pi, threads=th)
+    table["batched_first300"] = {"unit": "Gop/s", "sample": "the first 300 of the 10,000 products",
+                                 "all_cores": round(rate(lambda: batch(0), work, 2.0)[0] / 1e9, 3),
+                                 "one_thread": round(rate(lambda: batch(1), work, 2.0)[0] / 1e9, 3)}
+    # the first 100 polynomial-product payloads of the serving pool (its products are like the above)
+    pool = [pl for pl in inputs.serve_pool() if pl.kind == "polymul"][:100]
+    pops = [inputs.payload_operands(pl) + (pl.p,) for pl in pool]
+    pwork = float(sum(pl.n for pl in pool))
+
+    def serve(th):
+        for ai, bi, pi in pops:
+            O.polymul(ai, bi, pi, threads=th)
+    table["serving_polymul_payloads_first100"] = {
+        "unit": "polymul/s", "all_cores": round(rate(lambda: serve(0), pwork, 1.0)[0], 1),
+        "one_thread": round(rate(lambda: serve(1), pwork, 1.0)[0], 1)}
+    return headline, table
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,14 +396,15 @@ def main():
     # warmup
     wcall = D.FgemmCall(dA, dB, dC, p, plan=plan, workspace=ws, stream=stream)
     for _ in range(args.warmup):
-        wcall.pack()
-        wcall.compute()
+        wcall.run()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps; the packed multiply kernel of every EVENT_EVERY-th step
+    # timed region: K whole steps; the packed multiply kernel of every event_every-th step
     # records its own start and end (a launch that records events costs the host more, so
-    # recording on every step would slow the steps it measures)
-    sampled = list(range(0, args.steps, EVENT_EVERY))
+    # recording on every step would slow the steps it measures); at least 8 such samples
+    # (every other step at the default 20 steps)
+    event_every = max(1, min(8, args.steps // (MIN_EVENT_SAMPLES + 2)))
+    sampled = list(range(0, args.steps, event_every))
     n_ev = len(sampled)
     ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
     ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
@@ -149,12 +417,12 @@ def main():
     torch.cuda.synchronize()
     t_start.record(stream)
     for i in range(args.steps):
-        call.pack()
-        if i % EVENT_EVERY == 0:
+        if i % event_every == 0:
             # the multiply kernel records its own start and end into the events
-            call.compute_timed(ev_a[i // EVENT_EVERY], ev_b[i // EVENT_EVERY])
+            call.pack()
+            call.compute_timed(ev_a[i // event_every], ev_b[i // event_every])
         else:
-            call.compute()
+            call.run()      # pack + multiply in one call
     t_end.record(stream)
     torch.cuda.synchronize()
     total_s = t_start.elapsed_time(t_end) / 1e3
@@ -193,78 +461,31 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    sections = set(args.sections.split(",")) if args.sections else set(SECTIONS)
+    if args.no_extra:
+        sections -= {"gemm", "polymul", "fqt", "gf"}
+    if args.no_workloads:
+        sections.discard("workloads")
+    if args.no_cpu:
+        sections.discard("cpu")
     extra = {}
-    reps_gemm = max(2, args.steps // 2)
+    reps_gemm = max(4, args.steps // 2)
     reps_big = max(2, args.steps // 20)
-    if not args.no_extra:
-        for name, algo in (("plain_mad", D.GEMM_PLAIN), ("plain_dot4", D.GEMM_DOT4), ("mfma_int8", D.GEMM_MFMA),
-                           ("cmm_redq_epilogue", None), ("right_compressed_f64mfma", D.GEMM_RIGHT),
-                           ("left_compressed_f64mfma", D.GEMM_LEFT), ("full_compressed_f64mfma", D.GEMM_FULL)):
-            pl = D.GemmPlan(algo=algo) if algo is not None else D.GemmPlan(algo=D.GEMM_CMM, epilogue=D.EPI_REDQ)
-            w2 = torch.empty(max(1, D.fgemm_workspace_size(p, MNK, MNK, MNK, pl)), dtype=torch.uint8, device=dev)
-            c2 = D.FgemmCall(dA, dB, dC, p, plan=pl, workspace=w2, stream=stream)
-            s = timed_loop(lambda: (c2.pack(), c2.compute()), reps_gemm, 3, torch)
-            extra["fgemm_" + name] = {"gop_s": round(fp_ops / s / 1e9, 1), "us_per_call": round(s * 1e6, 2)}
-            assert (dC[:1].cpu().numpy() == row0).all()
-        # one-word polynomial products: degree 3 over F_3, q = 2^6, 2^26 products (beyond the MALL)
-        n = 1 << 26
-        a, b = inputs.polymul_pairs(n, 4, 3)
-        da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
-        out = torch.empty((n, 7), dtype=torch.uint8, device=dev)
-        for name, fn in (("packed", lambda: D.polymul_u8(da, db, 3, out=out, log2q=6)),
-                         ("plain", lambda: D.polymul_plain_u8(da, db, 3, out=out))):
-            s = timed_loop(fn, reps_big, 2, torch)
-            extra["polymul_deg3_f3_" + name] = {"polymul_s": round(n / s, 1), "GB_s": round(15 * n / s / 1e9, 1),
-                                                "hbm_frac": round(15 * n / s / PEAK_HBM, 4)}
-        # the correction-table window (section 3.5): none, two or three residues per lookup
-        try:
-            for j in (1, 2, 3):
-                D.set_table_window(j)
-                s = timed_loop(lambda: D.polymul_u8(da, db, 3, out=out, log2q=6), reps_big, 2, torch)
-                extra[f"polymul_deg3_f3_table_window_{j}"] = {"GB_s": round(15 * n / s / 1e9, 1),
-                                                              "hbm_frac": round(15 * n / s / PEAK_HBM, 4)}
-        finally:
-            D.set_table_window(0)
-        a65, b65 = inputs.polymul_pairs(65536, 4, 3)
-        d65a, d65b = torch.from_numpy(a65).to(dev), torch.from_numpy(b65).to(dev)
-        o65 = torch.empty((65536, 7), dtype=torch.uint8, device=dev)
-        s = timed_loop(lambda: D.polymul_u8(d65a, d65b, 3, out=o65, log2q=6), reps_gemm, 3, torch)
-        extra["polymul_65536_packed"] = {"us_per_call": round(s * 1e6, 2), "polymul_s": round(65536 / s, 1)}
-        del da, db, out
-        # long products by blocks (FQT): degree 47 over F_3, 2^20 products, schoolbook and Karatsuba blocks
-        nl = 1 << 20
-        al, bl = inputs.polymul_pairs(nl, 48, 3)
-        dal, dbl = torch.from_numpy(al).to(dev), torch.from_numpy(bl).to(dev)
-        ol = torch.empty((nl, 95), dtype=torch.uint8, device=dev)
-        for name, fn in (("fqt", lambda: D.polymul_fqt_u8(dal, dbl, 3, out=ol)),
-                         ("fqt_karatsuba1", lambda: D.polymul_fqt_kara_u8(dal, dbl, 3, levels=1, out=ol)),
-                         ("fqt_karatsuba2", lambda: D.polymul_fqt_kara_u8(dal, dbl, 3, levels=2, out=ol)),
-                         ("plain", lambda: D.polymul_plain_u8(dal, dbl, 3, out=ol))):
-            try:
-                s = timed_loop(fn, reps_big, 2, torch)
-                extra["polymul_deg47_f3_" + name] = {"polymul_s": round(nl / s, 1), "us_per_call": round(s * 1e6, 1)}
-            except D.DQTError as e:
-                extra["polymul_deg47_f3_" + name] = {"error": str(e)}
-        del dal, dbl, ol
-        for (pp, k) in ((3, 5), (7, 3)):
-            P = inputs.irreducible(pp, k)
-            x, y = inputs.gf_pairs(n, k, pp)
-            dx, dy = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
-            oz = torch.empty((n, k), dtype=torch.uint8, device=dev)
-            for name, fn in (("packed", lambda: D.gf_mul_u8(dx, dy, pp, P, out=oz)),
-                             ("plain", lambda: D.gf_mul_plain_u8(dx, dy, pp, P, out=oz))):
-                s = timed_loop(fn, reps_big, 2, torch)
-                extra[f"gf_{pp}^{k}_{name}"] = {"mul_s": round(n / s, 1), "GB_s": round(3 * k * n / s / 1e9, 1),
-                                               "hbm_frac": round(3 * k * n / s / PEAK_HBM, 4)}
-            del dx, dy, oz
-
-    if not args.no_extra and not args.no_workloads:
+    if "gemm" in sections:
+        extra.update(bench_gemm_comparators(D, torch, dA, dB, dC, p, row0, stream, reps_gemm))
+    if "polymul" in sections:
+        extra.update(bench_polymul(D, inputs, torch, dev, reps_big, reps_gemm))
+    if "fqt" in sections:
+        extra.update(bench_fqt(D, inputs, torch, dev, reps_big))
+    if "gf" in sections:
+        extra.update(bench_gf(D, inputs, torch, dev, reps_big))
+    if "workloads" in sections:
         from paper_0809_0063_amd import workloads as W
         from paper_0809_0063_amd import tune as T
         for name, fn in (("batched_10000_tuned", lambda: W.batched(10000, replays=3, tuner=T.Tuner())),
                          ("batched_10000_packed_cmm", lambda: W.batched(10000, replays=3, tuner=T.Tuner(),
                                                                          algo=D.GEMM_CMM)),
-                         ("serving", lambda: W.serving(n_requests=2000, warmup=200))):
+                         ("serving", lambda: W.serving(n_requests=5000, warmup=500, loads=(0.5, 0.8, 1.2)))):
             try:
                 extra[name] = fn()
             except Exception as e:  # reported in the output line, not hidden
@@ -272,20 +493,9 @@ def main():
             torch.cuda.synchronize()
 
     cpu = None
-    if not args.no_cpu:
-        import oracle as O
-        # the whole 1024^3 product, repeated until about 8 s of wall time have passed
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            Cs = O.fgemm(A, B, p)
-            reps += 1
-            dt = time.perf_counter() - t0
-            if dt >= 8.0:
-                break
-        assert (Cs[:1] == row0).all()
-        cpu = {"value": round(reps * fp_ops / dt / 1e9, 3), "unit": "Gop/s",
-               "cores": O.max_threads(), "kind": "oracle",
-               "sample": f"the whole 1024^3 mod-3 product, {reps} times ({dt:.1f} s), reduce after every op"}
+    if "cpu" in sections:
+        cpu, table = cpu_baselines(A, B, p, row0, fp_ops, inputs)
+        extra["cpu_oracle"] = table
 
     rec = {
         "metric": METRIC,

@@ -289,8 +289,10 @@ typedef enum dqt_gemm_algo {
     DQT_GEMM_LEFT = 6,      /* left compressed (section 7.4, the transpose): e rows of A per word */
     DQT_GEMM_FULL = 7,      /* full compression (section 7.5): 2 rows of A in powers of Q times e_c
                                columns of B in powers of Theta = Q^2, 2 e_c digits per word */
-    DQT_GEMM_BY_SHAPE = 8   /* the rule of section 7.6.2: CMM (as AUTO) when kdim is the largest
+    DQT_GEMM_BY_SHAPE = 8,  /* the rule of section 7.6.2: CMM (as AUTO) when kdim is the largest
                                dimension, RIGHT when n is, LEFT when m is */
+    DQT_GEMM_DOT8 = 9       /* plain, p <= 16: eight 4-bit entries per word, one hardware dot
+                               instruction per eight multiply-adds (DQT_E_UNSUPPORTED for p > 16) */
 } dqt_gemm_algo;
 
 typedef enum dqt_gemm_epilogue {
@@ -371,7 +373,7 @@ dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, 
  * dqt_fgemm_compute, with the multiply kernel's own start and end recorded
  * into two caller-created hipEvent_t (either may be NULL): the elapsed time
  * between them is that kernel's execution, without the launch gaps around
- * it (measurement).  Not for DQT_GEMM_MFMA (DQT_E_UNSUPPORTED).
+ * it (measurement).
  */
 dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t *d_C, uint64_t ldc,
                                    const dqt_gemm_plan *plan, const void *d_work, size_t work_bytes,
@@ -403,8 +405,8 @@ dqt_status dqt_fgemm_packed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, c
  * Batched F_p matrix products in one persistent launch.
  *
  * Each descriptor names its own device operands (row-major uint8, as for
- * dqt_fgemm) and its packing choices: algo (DQT_GEMM_AUTO, _CMM, _PLAIN or
- * _DOT4), interval and log2Q (0 = smallest allowed), epilogue.  These are the
+ * dqt_fgemm) and its packing choices: algo (DQT_GEMM_AUTO, _CMM, _PLAIN,
+ * _DOT4 or _DOT8), interval and log2Q (0 = smallest allowed), epilogue.  These are the
  * knobs the tuner picks per (size, p) bucket.
  *
  * dqt_fgemm_batched_prepare builds the device-resident plan in d_work
@@ -425,7 +427,7 @@ typedef struct dqt_gemm_desc {
     uint32_t m, n, kdim;
     uint32_t lda, ldb, ldc;
     uint32_t p;
-    uint32_t algo;          /* DQT_GEMM_AUTO, DQT_GEMM_CMM, DQT_GEMM_PLAIN or DQT_GEMM_DOT4 */
+    uint32_t algo;          /* DQT_GEMM_AUTO, DQT_GEMM_CMM, DQT_GEMM_PLAIN, DQT_GEMM_DOT4 or DQT_GEMM_DOT8 */
     uint32_t interval;      /* delayed-reduction interval in k (0 = largest allowed) */
     uint32_t log2Q;         /* 0 = smallest allowed */
     uint32_t epilogue;      /* dqt_gemm_epilogue */

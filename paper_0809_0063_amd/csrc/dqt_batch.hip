@@ -109,6 +109,7 @@ __global__ __launch_bounds__(64 * S) void k_batch_compute(BatchHeader* hdr, cons
                 }
                 break;
             case OP_DOT4: gemm_tile<OP_DOT4, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
+            case OP_DOT8: gemm_tile<OP_DOT8, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
             default: gemm_tile<OP_MAD, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
         }
         __syncthreads();  // the LDS reduction buffer is reused by the next item
@@ -281,12 +282,13 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
     }
     prefix[count] = (uint32_t)blocks;
     if (blocks > 0xFFFFFFFFull) return DQT_E_INVALID;
-    // work items, most expensive products first (cost of a tile ~ its inner dimension)
+    // work items, most expensive products first (cost of a tile ~ the instructions of its
+    // k loop: the inner dimension over the entries per word)
     std::vector<uint32_t> order(count);
     for (uint32_t i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        return (uint64_t)descs[a].kdim * (plans[a].op == OP_MAD ? 4 : 1) >
-               (uint64_t)descs[b].kdim * (plans[b].op == OP_MAD ? 4 : 1);
+        return (uint64_t)descs[a].kdim * (8 / entries_per_word(plans[a].op)) >
+               (uint64_t)descs[b].kdim * (8 / entries_per_word(plans[b].op));
     });
     uint64_t it = 0;
     for (uint32_t oi = 0; oi < count; ++oi) {

@@ -679,13 +679,84 @@ __global__ __launch_bounds__(256) void k_polymul_plain_tiles(const uint8_t* __re
     });
 }
 
-// Plain GF(p^k) product: schoolbook with delayed sums, REDC per coefficient,
-// then long division by the monic modulus from the top down (each step
-// reduced), then REDC of the k remaining coefficients.
+// Plain GF(p^k) product of one pair: schoolbook with delayed sums, then long
+// division by the monic modulus from the top down in which only the leading
+// coefficient of each step is reduced (REDC) and the others take
+// lead (p - m_i) unreduced, then one REDC for each of the k remaining
+// coefficients: 2k - 1 reductions in all.  Every intermediate stays below
+// (2k - 1) (p-1)^2 < 2^24, the range of the REDC.
+template <int K>
+__device__ __forceinline__ void gf_plain_one(const uint8_t* x, const uint8_t* y, const uint32_t (&negm)[K], uint32_t p,
+                                             uint32_t pmagic, uint32_t (&r)[K]) {
+    uint32_t c[2 * K - 1];
+    plain_poly_product<K>(x, y, c);
+#pragma unroll
+    for (int j = 2 * K - 2; j >= K; --j) {
+        const uint32_t lead = mod_small(c[j], p, pmagic);
+#pragma unroll
+        for (int i = 0; i < K; ++i) c[j - K + i] += lead * negm[i];
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) r[i] = mod_small(c[i], p, pmagic);
+}
+
+// Four products per thread with whole-dword loads and stores (4k input bytes
+// per operand, 4k output bytes), the I/O of the packed GF kernel.
+template <int K>
+__global__ __launch_bounds__(256) void k_gf_mul_plain4(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+                                                       uint8_t* __restrict__ OUT, uint64_t count, uint32_t p,
+                                                       uint32_t pmagic, uint64_t modulus) {
+    uint32_t negm[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) negm[i] = (p - (uint32_t)((modulus >> (8 * i)) & 0xFF)) % p;
+    const uint64_t ngroups = count >> 2;
+    const uint32_t* A32 = reinterpret_cast<const uint32_t*>(A);
+    const uint32_t* B32 = reinterpret_cast<const uint32_t*>(B);
+    uint32_t* O32 = reinterpret_cast<uint32_t*>(OUT);
+    for (uint64_t g = blockIdx.x * 256ull + threadIdx.x; g < ngroups; g += (uint64_t)gridDim.x * 256) {
+        uint32_t a[K], b[K], o[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            a[i] = __builtin_nontemporal_load(A32 + g * K + i);
+            b[i] = __builtin_nontemporal_load(B32 + g * K + i);
+            o[i] = 0;
+        }
+        const uint8_t* ab = reinterpret_cast<const uint8_t*>(a);
+        const uint8_t* bb = reinterpret_cast<const uint8_t*>(b);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            uint32_t r[K];
+            gf_plain_one<K>(ab + t * K, bb + t * K, negm, p, pmagic, r);
+#pragma unroll
+            for (int i = 0; i < K; ++i) put_byte(o, t * K + i, r[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) __builtin_nontemporal_store(o[i], O32 + g * K + i);
+    }
+    const uint64_t rem = count & 3;
+    if (blockIdx.x == 0 && threadIdx.x < rem) {
+        const uint64_t t = ngroups * 4 + threadIdx.x;
+        uint8_t x[K], y[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            x[i] = A[t * K + i];
+            y[i] = B[t * K + i];
+        }
+        uint32_t r[K];
+        gf_plain_one<K>(x, y, negm, p, pmagic, r);
+#pragma unroll
+        for (int i = 0; i < K; ++i) OUT[t * K + i] = (uint8_t)r[i];
+    }
+}
+
+// One product per thread with byte loads and stores (operands not 4-byte aligned).
 template <int K>
 __global__ __launch_bounds__(256) void k_gf_mul_plain(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                       uint8_t* __restrict__ OUT, uint64_t count, uint32_t p,
                                                       uint32_t pmagic, uint64_t modulus) {
+    uint32_t negm[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) negm[i] = (p - (uint32_t)((modulus >> (8 * i)) & 0xFF)) % p;
     for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < count; t += (uint64_t)gridDim.x * 256) {
         uint8_t x[K], y[K];
 #pragma unroll
@@ -693,21 +764,10 @@ __global__ __launch_bounds__(256) void k_gf_mul_plain(const uint8_t* __restrict_
             x[i] = A[t * K + i];
             y[i] = B[t * K + i];
         }
-        uint32_t c[2 * K - 1];
-        plain_poly_product<K>(x, y, c);
+        uint32_t r[K];
+        gf_plain_one<K>(x, y, negm, p, pmagic, r);
 #pragma unroll
-        for (int j = 0; j < 2 * K - 1; ++j) c[j] = mod_small(c[j], p, pmagic);
-#pragma unroll
-        for (int j = 2 * K - 2; j >= K; --j) {
-            const uint32_t lead = c[j];
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const uint32_t mi = (uint32_t)((modulus >> (8 * i)) & 0xFF);
-                c[j - K + i] = mod_small(c[j - K + i] + p * p - lead * mi, p, pmagic);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < K; ++i) OUT[t * K + i] = (uint8_t)c[i];
+        for (int i = 0; i < K; ++i) OUT[t * K + i] = (uint8_t)r[i];
     }
 }
 
@@ -1041,14 +1101,26 @@ extern "C" dqt_status dqt_gf_mul_plain_u8(const uint8_t* d_a, const uint8_t* d_b
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
     hipStream_t s = S(stream);
     DQT_TRY(debug_gate(s, p, {{d_a, count, k, k}, {d_b, count, k, k}}));
+    const bool al = aligned4(d_a) && aligned4(d_b) && aligned4(d_out);
     const unsigned g = stream_grid(count, 256);
+    const unsigned g4 = stream_grid((count + 3) / 4, 256);
+#define DQT_GF_PLAIN_CASE(KK)                                                                                      \
+    case KK:                                                                                                       \
+        if (al)                                                                                                    \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain4<KK>), dim3(g4), dim3(256), 0, s, d_a, d_b, d_out, \
+                               count, p, pmagic, mod);                                                             \
+        else                                                                                                       \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain<KK>), dim3(g), dim3(256), 0, s, d_a, d_b, d_out,   \
+                               count, p, pmagic, mod);                                                             \
+        break;
     switch (k) {
-        case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain<2>), dim3(g), dim3(256), 0, s, d_a, d_b, d_out, count, p, pmagic, mod); break;
-        case 3: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain<3>), dim3(g), dim3(256), 0, s, d_a, d_b, d_out, count, p, pmagic, mod); break;
-        case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain<4>), dim3(g), dim3(256), 0, s, d_a, d_b, d_out, count, p, pmagic, mod); break;
-        case 5: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain<5>), dim3(g), dim3(256), 0, s, d_a, d_b, d_out, count, p, pmagic, mod); break;
-        case 6: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_mul_plain<6>), dim3(g), dim3(256), 0, s, d_a, d_b, d_out, count, p, pmagic, mod); break;
+        DQT_GF_PLAIN_CASE(2)
+        DQT_GF_PLAIN_CASE(3)
+        DQT_GF_PLAIN_CASE(4)
+        DQT_GF_PLAIN_CASE(5)
+        DQT_GF_PLAIN_CASE(6)
     }
+#undef DQT_GF_PLAIN_CASE
     DQT_LAUNCH_CHECK("dqt_gf_mul_plain_u8");
     return DQT_OK;
 }

@@ -15,9 +15,10 @@
 // into one word and reduced by one REDQ (section 3).
 //
 // Comparators in the same kernel structure: one entry per word and one
-// v_mad_u32_u24 per multiply-add ("plain", the paper's delayed baseline), and
-// four u8 entries per word with v_dot4_u32_u8.  A separate kernel uses the
-// INT8 matrix cores (exact int32 accumulation while k (p-1)^2 < 2^31).
+// v_mad_u32_u24 per multiply-add ("plain", the paper's delayed baseline),
+// four u8 entries per word with v_dot4_u32_u8, and eight 4-bit entries per
+// word with v_dot8_u32_u4 (p <= 16).  The INT8 matrix-core comparator is in
+// dqt_gemm_mfma.hip.
 //
 // Layout on the device (workspace, written by the pack kernel each call):
 //   CA: [m_pad/TM][KW][TM] uint32: the words of the TM rows of a row block at
@@ -148,90 +149,6 @@ __global__ __launch_bounds__(256) void k_gemm_pack4(Pack4Args pa) {
 }
 
 // ---------------------------------------------------------------------------
-// INT8 matrix-core comparator
-// ---------------------------------------------------------------------------
-// A8: [m_pad][k_pad] int8 (row-major, zero padded), BT8: [n_pad][k_pad] int8
-// (B transposed).  A wave computes a 32x32 block as 2x2 tiles of
-// v_mfma_i32_16x16x64_i8.  Lane l supplies row (or column) l%16 and the 16
-// consecutive k of slot l/16 for both operands, so the slots of A and B pair
-// up on the same k; lane l receives rows 4(l/16)..4(l/16)+3 of column l%16.
-
-struct MfmaArgs {
-    const uint8_t* A8;
-    const uint8_t* BT8;
-    uint8_t* C;
-    uint32_t m, n, ldc, k_pad, m_pad, n_pad;
-    uint32_t nrb;      // 64-row blocks
-    uint32_t p, pmagic;
-};
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(256) void k_gemm_mfma(MfmaArgs g) {
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    uint32_t rb, cb;
-    tile_of(blockIdx.x, gridDim.x, g.nrb, &rb, &cb);
-    const uint32_t row0 = rb * 64 + (wave & 1) * 32;
-    const uint32_t col0 = cb * 64 + (wave >> 1) * 32;
-    const uint32_t r = lane & 15u, slot = lane >> 4;
-    v4i acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = (v4i){0, 0, 0, 0};
-    const uint8_t* pa0 = g.A8 + (size_t)(row0 + r) * g.k_pad + slot * 16;
-    const uint8_t* pa1 = pa0 + (size_t)16 * g.k_pad;
-    const uint8_t* pb0 = g.BT8 + (size_t)(col0 + r) * g.k_pad + slot * 16;
-    const uint8_t* pb1 = pb0 + (size_t)16 * g.k_pad;
-    for (uint32_t k = 0; k < g.k_pad; k += 64) {
-        const v4i a0 = *reinterpret_cast<const v4i*>(pa0 + k);
-        const v4i a1 = *reinterpret_cast<const v4i*>(pa1 + k);
-        const v4i b0 = *reinterpret_cast<const v4i*>(pb0 + k);
-        const v4i b1 = *reinterpret_cast<const v4i*>(pb1 + k);
-        acc[0][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[1][1], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t row = row0 + 16 * i + 4 * slot + t;
-                const uint32_t col = col0 + 16 * j + r;
-                if (row < g.m && col < g.n)
-                    g.C[(size_t)row * g.ldc + col] = (uint8_t)mod_u32((uint32_t)acc[i][j][t], g.p, g.pmagic);
-            }
-}
-
-struct MfmaPackArgs {
-    const uint8_t* A;
-    const uint8_t* B;
-    uint8_t* A8;
-    uint8_t* BT8;
-    uint32_t m, n, kdim, lda, ldb, k_pad, m_pad, n_pad;
-    uint32_t nba;
-};
-
-// A8[row][k] = A[row][k] (zero padded); BT8[col][k] = B[k][col] (zero padded).
-__global__ __launch_bounds__(256) void k_mfma_pack(MfmaPackArgs a) {
-    if (blockIdx.x < a.nba) {
-        const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-        if (t >= (uint64_t)a.m_pad * a.k_pad) return;
-        const uint32_t row = (uint32_t)(t / a.k_pad), k = (uint32_t)(t % a.k_pad);
-        a.A8[t] = (row < a.m && k < a.kdim) ? a.A[(size_t)row * a.lda + k] : 0;
-    } else {
-        const uint64_t t = (uint64_t)(blockIdx.x - a.nba) * 256 + threadIdx.x;
-        if (t >= (uint64_t)a.n_pad * a.k_pad) return;
-        // consecutive threads walk columns (coalesced reads of B), writes are strided
-        const uint32_t k = (uint32_t)(t / a.n_pad), col = (uint32_t)(t % a.n_pad);
-        a.BT8[(size_t)col * a.k_pad + k] = (col < a.n && k < a.kdim) ? a.B[(size_t)k * a.ldb + col] : 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Host planning
 // ---------------------------------------------------------------------------
 
@@ -321,15 +238,15 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
             if (!sums_fit) return DQT_E_UNSUPPORTED;
             if (r->epi) return DQT_E_UNSUPPORTED;
             break;
-        case DQT_GEMM_MFMA:
-            if (p > 128) return DQT_E_UNSUPPORTED;  // entries must be valid int8
-            if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 31)) return DQT_E_UNSUPPORTED;
+        case DQT_GEMM_DOT8:
+            r->op = OP_DOT8;
+            if (p > 16) return DQT_E_UNSUPPORTED;   // entries must fit four bits
+            if (!sums_fit) return DQT_E_UNSUPPORTED;
             if (r->epi) return DQT_E_UNSUPPORTED;
-            r->k_pad = (uint32_t)round_up(kdim ? kdim : 64, 64);
-            r->m_pad = (uint32_t)round_up(m ? m : 64, 64);
-            r->n_pad = (uint32_t)round_up(n ? n : 64, 64);
-            r->ws_bytes = (size_t)r->k_pad * (r->m_pad + r->n_pad);
-            return DQT_OK;
+            break;
+        case DQT_GEMM_MFMA:
+            if (r->epi) return DQT_E_UNSUPPORTED;
+            return mfma_plan(p, m, n, kdim, r);
         default:
             return DQT_E_UNSUPPORTED;
     }
@@ -340,7 +257,7 @@ static dqt_status resolve_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim
     if (r->tm != 8 && r->tm != 16 && r->tm != 32) return DQT_E_INVALID;
     if (r->tn != 2 && r->tn != 4) return DQT_E_INVALID;
     if (r->tm == 32 && r->tn == 4) return DQT_E_INVALID;
-    const uint32_t epw = r->op == OP_MAD ? 1 : 4;
+    const uint32_t epw = entries_per_word(r->op);
     r->KW = (uint32_t)((kdim + epw - 1) / epw);
     if (pl.ksplit) {
         r->s = pl.ksplit;
@@ -454,7 +371,7 @@ dqt_status fgemm_epilogue_args(uint32_t p, uint64_t kdim, const GemmPlanResolved
 // Bytes of the packed copy of one side (0 = A, 1 = B).
 static size_t side_bytes(const GemmPlanResolved& r, int side) {
     if (is_f64_algo(r.algo)) return f64_side_bytes(r, side);
-    if (r.algo == DQT_GEMM_MFMA) return (size_t)r.k_pad * (side == 0 ? r.m_pad : r.n_pad);
+    if (r.algo == DQT_GEMM_MFMA) return mfma_side_bytes(r, side);
     return (size_t)r.KW * (side == 0 ? r.m_pad : r.n_pad) * sizeof(uint32_t);
 }
 
@@ -465,28 +382,7 @@ static dqt_status fgemm_pack_sides(uint64_t m, uint64_t n, uint64_t kdim, const 
                                    const uint8_t* B, uint64_t ldb, const GemmPlanResolved& r, void* pA, void* pB,
                                    hipStream_t s) {
     if (is_f64_algo(r.algo)) return f64_pack_enqueue(r, m, n, kdim, A, lda, B, ldb, pA, pB, s);
-    if (r.algo == DQT_GEMM_MFMA) {
-        MfmaPackArgs pa;
-        pa.A = A;
-        pa.B = B;
-        pa.A8 = reinterpret_cast<uint8_t*>(pA);
-        pa.BT8 = reinterpret_cast<uint8_t*>(pB);
-        pa.m = (uint32_t)m;
-        pa.n = (uint32_t)n;
-        pa.kdim = (uint32_t)kdim;
-        pa.lda = (uint32_t)lda;
-        pa.ldb = (uint32_t)ldb;
-        pa.k_pad = r.k_pad;
-        pa.m_pad = r.m_pad;
-        pa.n_pad = r.n_pad;
-        const uint32_t nba = A ? (uint32_t)(((uint64_t)r.m_pad * r.k_pad + 255) / 256) : 0;
-        const uint32_t nbb = B ? (uint32_t)(((uint64_t)r.n_pad * r.k_pad + 255) / 256) : 0;
-        pa.nba = nba;
-        if (nba + nbb == 0) return DQT_OK;
-        hipLaunchKernelGGL(k_mfma_pack, dim3(nba + nbb), dim3(256), 0, s, pa);
-        DQT_LAUNCH_CHECK("fgemm(mfma pack)");
-        return DQT_OK;
-    }
+    if (r.algo == DQT_GEMM_MFMA) return mfma_pack_enqueue(r, m, n, kdim, A, lda, B, ldb, pA, pB, s);
     uint32_t* CA = reinterpret_cast<uint32_t*>(pA);
     uint32_t* CB = reinterpret_cast<uint32_t*>(pB);
     PackArgs pa;
@@ -509,7 +405,7 @@ static dqt_status fgemm_pack_sides(uint64_t m, uint64_t n, uint64_t kdim, const 
     const bool a_al = !A || (((uintptr_t)A & 3) == 0 && (lda & 3) == 0);
     const bool b_al = !B || (((uintptr_t)B & 3) == 0 && (ldb & 3) == 0);
     const bool out_al = (!A || ((uintptr_t)pA & 15) == 0) && (!B || ((uintptr_t)pB & 15) == 0);
-    if (r.op != OP_MAD && a_al && b_al && (r.n_pad & 3) == 0 && out_al) {
+    if ((r.op == OP_DOT2 || r.op == OP_DOT4) && a_al && b_al && (r.n_pad & 3) == 0 && out_al) {
         Pack4Args p4;
         p4.a = pa;
         p4.tiles_m = (r.m_pad + 63) / 64;
@@ -549,25 +445,7 @@ dqt_status fgemm_compute_enqueue2(uint32_t p, uint64_t m, uint64_t n, uint64_t k
         }
         return f64_compute_enqueue(r, p, m, n, C, ldc, pA, pB, s, g_ev_start, g_ev_stop);
     }
-    if (r.algo == DQT_GEMM_MFMA) {
-        MfmaArgs g;
-        g.A8 = reinterpret_cast<const uint8_t*>(pA);
-        g.BT8 = reinterpret_cast<const uint8_t*>(pB);
-        g.C = C;
-        g.m = (uint32_t)m;
-        g.n = (uint32_t)n;
-        g.ldc = (uint32_t)ldc;
-        g.k_pad = r.k_pad;
-        g.m_pad = r.m_pad;
-        g.n_pad = r.n_pad;
-        g.nrb = r.m_pad / 64;
-        g.p = p;
-        g.pmagic = pmagic;
-        const unsigned grid = (r.m_pad / 64) * (r.n_pad / 64);
-        hipLaunchKernelGGL(k_gemm_mfma, dim3(grid), dim3(256), 0, s, g);
-        DQT_LAUNCH_CHECK("fgemm(mfma)");
-        return DQT_OK;
-    }
+    if (r.algo == DQT_GEMM_MFMA) return mfma_compute_enqueue(r, p, m, n, C, ldc, pA, pB, s, g_ev_start, g_ev_stop);
     // the k loop reads B with 8- or 16-byte vector loads
     if (((uintptr_t)pA & 15) || ((uintptr_t)pB & 15)) {
         set_error("fgemm: packed operands (workspace) must be 16-byte aligned");
@@ -600,6 +478,7 @@ dqt_status fgemm_compute_enqueue2(uint32_t p, uint64_t m, uint64_t n, uint64_t k
     switch (r.op) {
         case OP_DOT2: launch_words_tm<OP_DOT2>(g, grid, r.tm, r.tn, r.s, s); break;
         case OP_DOT4: launch_words_tm<OP_DOT4>(g, grid, r.tm, r.tn, r.s, s); break;
+        case OP_DOT8: launch_words_tm<OP_DOT8>(g, grid, r.tm, r.tn, r.s, s); break;
         default: launch_words_tm<OP_MAD>(g, grid, r.tm, r.tn, r.s, s); break;
     }
     DQT_LAUNCH_CHECK("fgemm");
@@ -610,7 +489,7 @@ dqt_status fgemm_compute_enqueue(uint32_t p, uint64_t m, uint64_t n, uint64_t kd
                                  const GemmPlanResolved& r, const void* work, hipStream_t s) {
     const uint8_t* w = reinterpret_cast<const uint8_t*>(work);
     const size_t a_bytes = is_f64_algo(r.algo)        ? f64_side_bytes(r, 0)
-                           : r.algo == DQT_GEMM_MFMA ? (size_t)r.m_pad * r.k_pad
+                           : r.algo == DQT_GEMM_MFMA ? mfma_side_bytes(r, 0)
                                                      : (size_t)r.KW * r.m_pad * 4;
     return fgemm_compute_enqueue2(p, m, n, kdim, C, ldc, r, w, w + a_bytes, s);
 }
@@ -679,7 +558,6 @@ extern "C" dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n
                                               void* stream) {
     GemmPlanResolved r;
     DQT_TRY(resolve_plan(p, m, n, kdim, plan, &r));
-    if (r.algo == DQT_GEMM_MFMA) return DQT_E_UNSUPPORTED;
     g_ev_start = reinterpret_cast<hipEvent_t>(start_event);
     g_ev_stop = reinterpret_cast<hipEvent_t>(stop_event);
     const dqt_status st = dqt_fgemm_compute(p, m, n, kdim, d_C, ldc, plan, d_work, work_bytes, stream);

@@ -1,0 +1,256 @@
+// Plain F_p matrix product on the INT8 matrix cores (comparator).
+//
+// C = A.B mod p with exact int32 accumulation: entries are residues below
+// p <= 128, so they are valid int8 values, and every dot product is at most
+// kdim (p-1)^2 < 2^31 (checked when the plan is resolved).  One reduction per
+// output.
+//
+// Layouts (workspace, written by the packing launch):
+//   A8:  [m_pad][k_pad] int8, the rows of A zero-padded to k_pad (a multiple of 64);
+//   BT8: [n_pad][k_pad] int8, B transposed (column j of B as row j), zero-padded.
+// m_pad is a multiple of 32, n_pad of 64.  B is transposed through LDS in tiles
+// of 64 k x 64 columns, so both the reads of B and the writes of BT8 are
+// whole 16-byte runs.
+//
+// Multiply: a workgroup of 4 waves owns a 32 x 32 tile of C; the waves split
+// k into S contiguous ranges (S = 4, 2 or 1 by the depth of k).  Each wave
+// computes its range as 2 x 2 tiles of v_mfma_i32_16x16x64_i8: lane l
+// supplies row (or column) l % 16 and the 16 consecutive k of slot l / 16,
+// for both operands, and receives rows 4 (l / 16) .. + 3 of column l % 16.
+// The loads of four k-steps (16 vector loads) are issued before their 16
+// matrix instructions.  The S partial tiles are added through LDS.
+
+#include <string.h>
+
+#include <hip/hip_ext.h>
+
+#include "dqt_gemm_tile.h"
+#include "dqt_internal.h"
+
+namespace dqt {
+
+namespace {
+
+struct MfmaPackArgs {
+    const uint8_t* A;
+    const uint8_t* B;
+    uint8_t* A8;
+    uint8_t* BT8;
+    uint32_t m, n, kdim, lda, ldb, k_pad, m_pad, n_pad;
+    uint32_t nba;          // workgroups copying A (16 bytes per thread)
+    uint32_t tiles_n;      // 64-column tiles of B
+    uint32_t al;           // bit 0: A and lda 16-byte aligned; bit 1: B and ldb 16-byte aligned
+};
+
+// 16 bytes of a row from x[0 .. len) (zero beyond len), as one vector load
+// when aligned and whole.
+__device__ __forceinline__ uint4 load16(const uint8_t* x, uint32_t len, bool aligned) {
+    if (aligned && len >= 16) return *reinterpret_cast<const uint4*>(x);
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (uint32_t i = 0; i < 16 && i < len; ++i) w[i >> 2] |= (uint32_t)x[i] << (8 * (i & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ __launch_bounds__(256) void k_mfma_pack(MfmaPackArgs a) {
+    if (blockIdx.x < a.nba) {
+        // A8[row][16 c .. 16 c + 15]
+        const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+        const uint32_t cpr = a.k_pad / 16;
+        if (t >= (uint64_t)a.m_pad * cpr) return;
+        const uint32_t row = (uint32_t)(t / cpr), c = (uint32_t)(t % cpr);
+        const uint32_t k0 = 16 * c;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (row < a.m && k0 < a.kdim) v = load16(a.A + (size_t)row * a.lda + k0, a.kdim - k0, a.al & 1u);
+        *reinterpret_cast<uint4*>(a.A8 + (size_t)row * a.k_pad + k0) = v;
+        return;
+    }
+    // BT8 tile: k0 .. k0+63 x columns n0 .. n0+63
+    __shared__ uint8_t tile[64][64 + 4];
+    const uint32_t b = blockIdx.x - a.nba;
+    const uint32_t n0 = (b % a.tiles_n) * 64, k0 = (b / a.tiles_n) * 64;
+    {
+        const uint32_t kk = threadIdx.x >> 2, cc = (threadIdx.x & 3) * 16;
+        const uint32_t k = k0 + kk, col = n0 + cc;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (k < a.kdim && col < a.n) v = load16(a.B + (size_t)k * a.ldb + col, a.n - col, a.al & 2u);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&tile[kk][cc]);
+        dst[0] = v.x;
+        dst[1] = v.y;
+        dst[2] = v.z;
+        dst[3] = v.w;
+    }
+    __syncthreads();
+    const uint32_t nn = threadIdx.x >> 2, kc = (threadIdx.x & 3) * 16;
+    uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i) w[i >> 2] |= (uint32_t)tile[kc + i][nn] << (8 * (i & 3));
+    *reinterpret_cast<uint4*>(a.BT8 + (size_t)(n0 + nn) * a.k_pad + k0 + kc) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+struct MfmaArgs {
+    const uint8_t* A8;
+    const uint8_t* BT8;
+    uint8_t* C;
+    uint32_t m, n, ldc, k_pad;
+    uint32_t nrb;          // 32-row blocks
+    uint32_t ks;           // 64-k steps per wave
+    uint32_t p, pmagic;
+};
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void mfma_tile_of(uint32_t bid, uint32_t nblk, uint32_t nrb, uint32_t* rb, uint32_t* cb) {
+    uint32_t logical = bid;
+    if ((nblk & 7u) == 0) logical = (bid & 7u) * (nblk >> 3) + (bid >> 3);
+    *rb = logical % nrb;
+    *cb = logical / nrb;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_gemm_mfma(MfmaArgs g) {
+    __shared__ v4i red[S * 4 * 64];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    uint32_t rb, cb;
+    mfma_tile_of(blockIdx.x, gridDim.x, g.nrb, &rb, &cb);
+    const uint32_t row0 = rb * 32, col0 = cb * 32;
+    const uint32_t r = lane & 15u, slot = lane >> 4;
+    v4i acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (v4i){0, 0, 0, 0};
+    const uint32_t nsteps = g.k_pad / 64;
+    const uint32_t s0 = min(nsteps, (wave % S) * g.ks), s1 = min(nsteps, s0 + g.ks);
+    if (wave < (uint32_t)S) {
+        const uint8_t* pa0 = g.A8 + (size_t)(row0 + r) * g.k_pad + slot * 16;
+        const uint8_t* pa1 = pa0 + (size_t)16 * g.k_pad;
+        const uint8_t* pb0 = g.BT8 + (size_t)(col0 + r) * g.k_pad + slot * 16;
+        const uint8_t* pb1 = pb0 + (size_t)16 * g.k_pad;
+        uint32_t st = s0;
+        for (; st + 4 <= s1; st += 4) {
+            v4i a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t o = (size_t)(st + u) * 64;
+                a0[u] = *reinterpret_cast<const v4i*>(pa0 + o);
+                a1[u] = *reinterpret_cast<const v4i*>(pa1 + o);
+                b0[u] = *reinterpret_cast<const v4i*>(pb0 + o);
+                b1[u] = *reinterpret_cast<const v4i*>(pb1 + o);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc[0][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0[u], b0[u], acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0[u], b1[u], acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1[u], b0[u], acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1[u], b1[u], acc[1][1], 0, 0, 0);
+            }
+        }
+        for (; st < s1; ++st) {
+            const size_t o = (size_t)st * 64;
+            const v4i a0 = *reinterpret_cast<const v4i*>(pa0 + o);
+            const v4i a1 = *reinterpret_cast<const v4i*>(pa1 + o);
+            const v4i b0 = *reinterpret_cast<const v4i*>(pb0 + o);
+            const v4i b1 = *reinterpret_cast<const v4i*>(pb1 + o);
+            acc[0][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+    // the S partial tiles meet in LDS; wave w (of 4) finishes the 16 x 16 tile (w >> 1, w & 1)
+    const uint32_t ti = wave >> 1, tj = wave & 1;
+    if (wave < (uint32_t)S) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) red[((wave * 2 + i) * 2 + j) * 64 + lane] = acc[i][j];
+    }
+    __syncthreads();
+    v4i sum = (v4i){0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < S; ++w) sum += red[((w * 2 + ti) * 2 + tj) * 64 + lane];
+    const uint32_t col = col0 + 16 * tj + r;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const uint32_t row = row0 + 16 * ti + 4 * slot + t;
+        if (row < g.m && col < g.n) g.C[(size_t)row * g.ldc + col] = (uint8_t)mod_u32((uint32_t)sum[t], g.p, g.pmagic);
+    }
+}
+
+}  // namespace
+
+static uint64_t ru(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+dqt_status mfma_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, GemmPlanResolved* r) {
+    if (p > 128) return DQT_E_UNSUPPORTED;   // entries must be valid int8
+    if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 31)) return DQT_E_UNSUPPORTED;
+    r->k_pad = (uint32_t)ru(kdim ? kdim : 64, 64);
+    r->m_pad = (uint32_t)ru(m ? m : 32, 32);
+    r->n_pad = (uint32_t)ru(n ? n : 64, 64);   // whole 64-column transpose tiles
+    const uint32_t steps = r->k_pad / 64;
+    r->s = steps >= 4 ? 4 : (steps >= 2 ? 2 : 1);
+    r->ws_bytes = (size_t)r->k_pad * (r->m_pad + r->n_pad);
+    return DQT_OK;
+}
+
+size_t mfma_side_bytes(const GemmPlanResolved& r, int side) { return (size_t)r.k_pad * (side == 0 ? r.m_pad : r.n_pad); }
+
+dqt_status mfma_pack_enqueue(const GemmPlanResolved& r, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A,
+                             uint64_t lda, const uint8_t* B, uint64_t ldb, void* pA, void* pB, hipStream_t s) {
+    if ((A && ((uintptr_t)pA & 15)) || (B && ((uintptr_t)pB & 15))) {
+        set_error("fgemm(mfma): packed operands must be 16-byte aligned");
+        return DQT_E_INVALID;
+    }
+    MfmaPackArgs a;
+    a.A = A;
+    a.B = B;
+    a.A8 = reinterpret_cast<uint8_t*>(pA);
+    a.BT8 = reinterpret_cast<uint8_t*>(pB);
+    a.m = (uint32_t)m;
+    a.n = (uint32_t)n;
+    a.kdim = (uint32_t)kdim;
+    a.lda = (uint32_t)lda;
+    a.ldb = (uint32_t)ldb;
+    a.k_pad = r.k_pad;
+    a.m_pad = r.m_pad;
+    a.n_pad = r.n_pad;
+    a.al = ((A && ((uintptr_t)A & 15) == 0 && (lda & 15) == 0) ? 1u : 0u) |
+           ((B && ((uintptr_t)B & 15) == 0 && (ldb & 15) == 0) ? 2u : 0u);
+    a.nba = A ? (uint32_t)(((uint64_t)r.m_pad * (r.k_pad / 16) + 255) / 256) : 0;
+    a.tiles_n = r.n_pad / 64;
+    const uint64_t nbb = B ? (uint64_t)a.tiles_n * (r.k_pad / 64) : 0;
+    if (a.nba + nbb == 0) return DQT_OK;
+    hipLaunchKernelGGL(k_mfma_pack, dim3((uint32_t)(a.nba + nbb)), dim3(256), 0, s, a);
+    DQT_LAUNCH_CHECK("fgemm(mfma pack)");
+    return DQT_OK;
+}
+
+dqt_status mfma_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t m, uint64_t n, uint8_t* C,
+                                uint64_t ldc, const void* pA, const void* pB, hipStream_t s, hipEvent_t e0,
+                                hipEvent_t e1) {
+    MfmaArgs g;
+    g.A8 = reinterpret_cast<const uint8_t*>(pA);
+    g.BT8 = reinterpret_cast<const uint8_t*>(pB);
+    g.C = C;
+    g.m = (uint32_t)m;
+    g.n = (uint32_t)n;
+    g.ldc = (uint32_t)ldc;
+    g.k_pad = r.k_pad;
+    g.nrb = r.m_pad / 32;
+    const uint32_t steps = r.k_pad / 64;
+    g.ks = (steps + r.s - 1) / r.s;
+    g.p = p;
+    g.pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
+    const unsigned grid = (r.m_pad / 32) * (r.n_pad / 32);
+    auto go = [&](auto kern) {
+        if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, e0, e1, 0, g);
+        else hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, g);
+    };
+    if (r.s == 4) go(k_gemm_mfma<4>);
+    else if (r.s == 2) go(k_gemm_mfma<2>);
+    else go(k_gemm_mfma<1>);
+    DQT_LAUNCH_CHECK("fgemm(mfma)");
+    return DQT_OK;
+}
+
+}  // namespace dqt

@@ -17,7 +17,8 @@
 //
 // Comparators in the same structure: one entry per word and one
 // v_mad_u32_u24 per multiply-add (the paper's delayed baseline, section 5.1),
-// or four u8 entries per word and v_dot4_u32_u8.
+// four u8 entries per word and v_dot4_u32_u8, or, for p <= 16, eight 4-bit
+// entries per word and v_dot8_u32_u4 (eight multiply-adds per instruction).
 //
 // A wave owns TM rows (uniform: their words are scalar loads, operands in
 // SGPRs) and 64*TN columns (TN adjacent columns per lane, one vector load per
@@ -30,7 +31,12 @@
 
 namespace dqt {
 
-enum GemmOp { OP_DOT2 = 0, OP_DOT4 = 1, OP_MAD = 2 };
+enum GemmOp { OP_DOT2 = 0, OP_DOT4 = 1, OP_MAD = 2, OP_DOT8 = 3 };
+
+// Entries of a matrix per packed word along k.
+__host__ __device__ inline uint32_t entries_per_word(uint32_t op) {
+    return op == OP_MAD ? 1u : (op == OP_DOT8 ? 8u : 4u);
+}
 
 struct GemmArgs {
     const uint32_t* CA;   // [m_pad/TM][KW][TM] packed words of A (tile-major, see gemm_tile)
@@ -64,6 +70,8 @@ __device__ __forceinline__ uint32_t mac(uint32_t a, uint32_t b, uint32_t acc) {
         return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b), acc, false);
     } else if (OP == OP_DOT4) {
         return __builtin_amdgcn_udot4(a, b, acc, false);
+    } else if (OP == OP_DOT8) {
+        return __builtin_amdgcn_udot8(a, b, acc, false);
     } else {
         return __umul24(a, b) + acc;
     }
@@ -353,8 +361,8 @@ struct PackArgs {
     uint32_t al;      // bit 0: A and lda 4-byte aligned; bit 1: B and ldb 4-byte aligned
 };
 
-// Words packed per thread: four (one 16-byte store) for the four-entry
-// layouts, one for the one-entry layout.
+// Words packed per thread: four (one 16-byte store) for the four- and
+// eight-entry layouts, one for the one-entry layout.
 __host__ __device__ inline uint32_t pack_words_per_thread(uint32_t op) { return op == OP_MAD ? 1u : 4u; }
 __host__ __device__ inline uint32_t pack_blocks_for(uint64_t words, uint32_t op) {
     const uint64_t per_block = 256ull * pack_words_per_thread(op);
@@ -426,8 +434,68 @@ __device__ __forceinline__ void gemm_pack_block4(const PackArgs& a, uint32_t blk
     }
 }
 
+// Four bytes (each below 16) as four nibbles.
+__device__ __forceinline__ uint32_t nibbles4(uint32_t d) {
+    return (d & 0xFu) | ((d >> 4) & 0xF0u) | ((d >> 8) & 0xF00u) | ((d >> 12) & 0xF000u);
+}
+
+// Eight-entry layout (v_dot8_u32_u4, p <= 16): a word holds the entries of
+// eight consecutive k as nibbles, entry 8 kw + x at bits 4x.  Four words per
+// thread, as gemm_pack_block4.
+__device__ __forceinline__ void gemm_pack_block8(const PackArgs& a, uint32_t blk, uint32_t tid) {
+    if (blk < a.nba) {
+        // words w0 .. w0+3 of CA: rows i0 .. i0+3 of row block rb at k-group kw
+        const uint64_t w0 = ((uint64_t)blk * 256 + tid) * 4;
+        if (w0 >= (uint64_t)a.KW * a.m_pad) return;
+        const uint32_t i0 = (uint32_t)(w0 % a.tm);
+        const uint64_t q = w0 / a.tm;
+        const uint32_t kw = (uint32_t)(q % a.KW), row0 = (uint32_t)(q / a.KW) * a.tm + i0;
+        uint4 out;
+        uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+        for (uint32_t x = 0; x < 4; ++x) {
+            const uint32_t row = row0 + x;
+            uint32_t lo = 0, hi = 0;
+            if (row < a.m) {
+                const uint8_t* r = a.A + (size_t)row * a.lda;
+                lo = row_group(r, 8 * kw, a.kdim, a.al & 1u);
+                hi = row_group(r, 8 * kw + 4, a.kdim, a.al & 1u);
+            }
+            o[x] = nibbles4(lo) | (nibbles4(hi) << 16);
+        }
+        *reinterpret_cast<uint4*>(a.CA + w0) = out;
+    } else {
+        // words w0 .. w0+3 of CB: columns c0 .. c0+3 of column block cb at k-group kw
+        const uint64_t w0 = ((uint64_t)(blk - a.nba) * 256 + tid) * 4;
+        if (w0 >= (uint64_t)a.KW * a.n_pad) return;
+        const uint32_t c0 = (uint32_t)(w0 % a.cbw);
+        const uint64_t q = w0 / a.cbw;
+        const uint32_t kw = (uint32_t)(q % a.KW), col0 = (uint32_t)(q / a.KW) * a.cbw + c0;
+        uint32_t d[8];
+#pragma unroll
+        for (uint32_t x = 0; x < 8; ++x) {
+            const uint32_t k = 8 * kw + x;
+            d[x] = k < a.kdim ? row_group(a.B + (size_t)k * a.ldb, col0, a.n, a.al & 2u) : 0u;
+        }
+        uint4 out;
+        uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            uint32_t w = 0;
+#pragma unroll
+            for (uint32_t x = 0; x < 8; ++x) w |= ((d[x] >> (8 * j)) & 0xFu) << (4 * x);
+            o[j] = w;
+        }
+        *reinterpret_cast<uint4*>(a.CB + w0) = out;
+    }
+}
+
 __device__ __forceinline__ void gemm_pack_block(const PackArgs& a, uint32_t blk, uint32_t tid) {
-    const uint32_t epw = a.op == OP_MAD ? 1u : 4u;  // entries per word
+    const uint32_t epw = entries_per_word(a.op);
+    if (epw == 8) {
+        gemm_pack_block8(a, blk, tid);
+        return;
+    }
     if (epw == 4) {
         gemm_pack_block4(a, blk, tid);
         return;
@@ -483,6 +551,14 @@ dqt_status f64_pack_enqueue(const GemmPlanResolved& r, uint64_t m, uint64_t n, u
                             uint64_t lda, const uint8_t* B, uint64_t ldb, void* pA, void* pB, hipStream_t s);
 dqt_status f64_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t m, uint64_t n, uint8_t* C, uint64_t ldc,
                                const void* pA, const void* pB, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// Plain product on the INT8 matrix cores (dqt_gemm_mfma.hip).
+dqt_status mfma_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, GemmPlanResolved* r);
+size_t mfma_side_bytes(const GemmPlanResolved& r, int side);
+dqt_status mfma_pack_enqueue(const GemmPlanResolved& r, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* A,
+                             uint64_t lda, const uint8_t* B, uint64_t ldb, void* pA, void* pB, hipStream_t s);
+dqt_status mfma_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t m, uint64_t n, uint8_t* C,
+                                uint64_t ldc, const void* pA, const void* pB, hipStream_t s, hipEvent_t e0,
+                                hipEvent_t e1);
 inline bool is_f64_algo(uint32_t algo) {
     return algo == DQT_GEMM_RIGHT || algo == DQT_GEMM_LEFT || algo == DQT_GEMM_FULL;
 }

@@ -8,7 +8,7 @@
 // word is then compressed once (REDQ compression), its residues u_0..u_{k-1}
 // and u_{k-1}..u_{2k-2} index the two tables T_L and T_H (theorem thm:fgdp,
 // built per workgroup in LDS), and H + L is added to the running result in
-// the field, coefficient-wise mod p.  One thread computes one dot product.
+// the field, coefficient-wise mod p.
 
 #include <string.h>
 
@@ -55,7 +55,13 @@ __device__ __forceinline__ uint64_t add_mod_bytes(uint64_t a, uint64_t b, uint32
     return s - (uint64_t)p * ge;
 }
 
-template <int K>
+// G lanes share one dot product: lane g of a group takes the pairs l = g,
+// g + G, g + 2G, ..., so the G lanes of a group read G consecutive records of
+// k bytes (whole runs of the operands, G k bytes per step), each lane keeps
+// its own packed sums of n_q products and its own field result, and the G
+// results are added in the field across the group by shuffles.  G = 1 is one
+// thread per dot product (short dot products).
+template <int K, int G>
 __global__ __launch_bounds__(256) void k_gf_dot(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                 uint8_t* __restrict__ OUT, uint64_t count, uint32_t n, uint32_t nq,
                                                 RedqArgs ra, GfArgs ga) {
@@ -67,19 +73,28 @@ __global__ __launch_bounds__(256) void k_gf_dot(const uint8_t* __restrict__ A, c
     __syncthreads();
     const uint64_t ones = 0x0101010101010101ull >> (8 * (8 - K));
     const uint32_t wm = (1u << ra.w) - 1u;
-    for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < count; t += (uint64_t)gridDim.x * 256) {
-        const uint8_t* x = A + t * (uint64_t)n * K;
-        const uint8_t* y = B + t * (uint64_t)n * K;
+    const uint32_t g = threadIdx.x % G;
+    const uint64_t groups = (uint64_t)gridDim.x * (256 / G);
+    // every lane of a group runs the same number of outer iterations (the
+    // shuffles below need the whole wave), so the loop runs to the padded count
+    const uint64_t padded = (count + groups - 1) / groups * groups;
+    for (uint64_t t = (uint64_t)blockIdx.x * (256 / G) + threadIdx.x / G; t < padded; t += groups) {
+        const bool live = t < count;
+        const uint8_t* x = A + (live ? t : 0) * (uint64_t)n * K;
+        const uint8_t* y = B + (live ? t : 0) * (uint64_t)n * K;
         uint64_t R = 0;
-        for (uint32_t l0 = 0; l0 < n; l0 += nq) {
-            const uint32_t l1 = min(n, l0 + nq);
+        // this lane's pairs: l = g + G j; n_q of them per packed word
+        const uint32_t mine = live && g < n ? (n - g + G - 1) / G : 0;
+        for (uint32_t j0 = 0; j0 < mine; j0 += nq) {
+            const uint32_t j1 = min(mine, j0 + nq);
             uint64_t acc = 0;
-            for (uint32_t l = l0; l < l1; ++l) {
+            for (uint32_t j = j0; j < j1; ++j) {
+                const uint64_t l = (uint64_t)g + (uint64_t)G * j;
                 uint64_t xa = 0, yb = 0;
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
-                    xa |= (uint64_t)x[(uint64_t)l * K + i] << (ra.b * i);
-                    yb |= (uint64_t)y[(uint64_t)l * K + i] << (ra.b * i);
+                    xa |= (uint64_t)x[l * K + i] << (ra.b * i);
+                    yb |= (uint64_t)y[l * K + i] << (ra.b * i);
                 }
                 acc += xa * yb;
             }
@@ -88,23 +103,42 @@ __global__ __launch_bounds__(256) void k_gf_dot(const uint8_t* __restrict__ A, c
             const uint64_t xh64 = U >> (ra.b * (K - 1));
             uint32_t il = 0, ih = 0;
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                il |= ((xl >> (ra.b * j)) & wm) << (ra.w * j);
-                ih |= ((uint32_t)(xh64 >> (ra.b * j)) & wm) << (ra.w * j);
+            for (int jj = 0; jj < K; ++jj) {
+                il |= ((xl >> (ra.b * jj)) & wm) << (ra.w * jj);
+                ih |= ((uint32_t)(xh64 >> (ra.b * jj)) & wm) << (ra.w * jj);
             }
             R = add_mod_bytes(R, add_mod_bytes(th[ih], tl[il], ra.p, ones), ra.p, ones);
         }
 #pragma unroll
-        for (int i = 0; i < K; ++i) OUT[t * K + i] = (uint8_t)(R >> (8 * i));
+        for (int off = G / 2; off >= 1; off /= 2) {
+            const uint32_t lo = __shfl_xor((uint32_t)R, off, G);
+            const uint32_t hi = __shfl_xor((uint32_t)(R >> 32), off, G);
+            R = add_mod_bytes(R, ((uint64_t)hi << 32) | lo, ra.p, ones);
+        }
+        if (live && g == 0) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) OUT[t * K + i] = (uint8_t)(R >> (8 * i));
+        }
     }
 }
 
+template <int K, int G>
+static void launch_gf_dot_g(const uint8_t* A, const uint8_t* B, uint8_t* out, uint64_t count, uint32_t n,
+                            uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
+    const size_t smem = 2ull * (1ull << (K * ra.w)) * sizeof(uint64_t);
+    const uint64_t threads = count * G;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_dot<K, G>), dim3(stream_grid(threads, 256, 4)), dim3(256), smem, s, A, B,
+                       out, count, n, nq, ra, ga);
+}
+
+// Lanes per dot product: one wave for long ones, fewer for short ones.
 template <int K>
 static dqt_status launch_gf_dot(const uint8_t* A, const uint8_t* B, uint8_t* out, uint64_t count, uint32_t n,
                                 uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
-    const size_t smem = 2ull * (1ull << (K * ra.w)) * sizeof(uint64_t);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_dot<K>), dim3(stream_grid(count, 256, 4)), dim3(256), smem, s, A, B, out,
-                       count, n, nq, ra, ga);
+    if (n >= 256) launch_gf_dot_g<K, 64>(A, B, out, count, n, nq, ra, ga, s);
+    else if (n >= 32) launch_gf_dot_g<K, 16>(A, B, out, count, n, nq, ra, ga, s);
+    else if (n >= 8) launch_gf_dot_g<K, 4>(A, B, out, count, n, nq, ra, ga, s);
+    else launch_gf_dot_g<K, 1>(A, B, out, count, n, nq, ra, ga, s);
     DQT_LAUNCH_CHECK("dqt_gf_dot_u8");
     return DQT_OK;
 }

@@ -24,6 +24,7 @@ DEBUG = os.environ.get("DQT_DEBUG", "") not in ("", "0")
 
 GEMM_AUTO, GEMM_CMM, GEMM_PLAIN, GEMM_DOT4, GEMM_MFMA, GEMM_RIGHT, GEMM_LEFT, GEMM_FULL = 0, 1, 2, 3, 4, 5, 6, 7
 GEMM_BY_SHAPE = 8
+GEMM_DOT8 = 9
 EPI_REDC, EPI_REDQ = 0, 1
 
 
@@ -557,7 +558,13 @@ class FgemmCall:
         self._pack_args = (p, m, n, kdim, _dev(A, "A", torch.uint8), kdim, _dev(B, "B", torch.uint8), n, pcp,
                            wptr, wbytes, st)
         self._comp_args = (p, m, n, kdim, _dev(C, "C", torch.uint8), n, pcp, wptr, wbytes)
+        self._full_args = (p, m, n, kdim, _dev(A, "A", torch.uint8), kdim, _dev(B, "B", torch.uint8), n,
+                           _dev(C, "C", torch.uint8), n, pcp, wptr, wbytes, st)
         self._st = st
+
+    def run(self):
+        """Both phases in one call (dqt_fgemm)."""
+        _check(self._lib.dqt_fgemm(*self._full_args), "dqt_fgemm")
 
     def pack(self):
         _check(self._lib.dqt_fgemm_pack(*self._pack_args), "dqt_fgemm_pack")

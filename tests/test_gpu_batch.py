@@ -32,8 +32,8 @@ def _make(D, items, algo_of=lambda i, it: 0):
                                                         (8, 2, 4), (16, 2, 4), (16, 4, 4)])
 def test_batch_small_mixed(dqt, tile_rows, ksplit, tile_cols):
     items = inputs.batch_items(60, nmin=1, nmax=300, seed=99)
-    algos = [dqt.GEMM_AUTO, dqt.GEMM_CMM, dqt.GEMM_PLAIN, dqt.GEMM_DOT4]
-    ops, host = _make(dqt, items, lambda i, it: algos[i % 4])
+    algos = [dqt.GEMM_AUTO, dqt.GEMM_CMM, dqt.GEMM_PLAIN, dqt.GEMM_DOT4, dqt.GEMM_DOT8]
+    ops, host = _make(dqt, items, lambda i, it: algos[i % 5])
     descs = dqt.make_descs(ops)
     ws = torch.empty(dqt.fgemm_batched_workspace_size(descs, tile_rows, ksplit, tile_cols), dtype=torch.uint8,
                      device=device())

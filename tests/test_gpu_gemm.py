@@ -1,4 +1,4 @@
-"""GPU parity: F_p matrix products (packed CMM, plain, dot4, INT8 matrix cores) vs the oracle, bit-exact."""
+"""GPU parity: F_p matrix products (packed CMM, plain, dot4, dot8, INT8 matrix cores) vs the oracle, bit-exact."""
 import numpy as np
 import pytest
 
@@ -18,7 +18,8 @@ def dqt():
 
 def _all_algos(D):
     return [D.GemmPlan(algo=D.GEMM_CMM), D.GemmPlan(algo=D.GEMM_CMM, epilogue=D.EPI_REDQ),
-            D.GemmPlan(algo=D.GEMM_PLAIN), D.GemmPlan(algo=D.GEMM_DOT4), D.GemmPlan(algo=D.GEMM_MFMA)]
+            D.GemmPlan(algo=D.GEMM_PLAIN), D.GemmPlan(algo=D.GEMM_DOT4), D.GemmPlan(algo=D.GEMM_DOT8),
+            D.GemmPlan(algo=D.GEMM_MFMA)]
 
 
 def test_fgemm_1024_p3(dqt):
@@ -42,7 +43,8 @@ def test_fgemm_bound_edges_worst_case(dqt, p):
         A = to_dev(inputs.worst_case((33, k), p))
         B = to_dev(inputs.worst_case((k, 65), p))
         want = (k * (p - 1) ** 2) % p
-        for plan in [None, dqt.GemmPlan(algo=dqt.GEMM_PLAIN), dqt.GemmPlan(algo=dqt.GEMM_CMM, epilogue=dqt.EPI_REDQ)]:
+        for plan in [None, dqt.GemmPlan(algo=dqt.GEMM_PLAIN), dqt.GemmPlan(algo=dqt.GEMM_CMM, epilogue=dqt.EPI_REDQ),
+                     dqt.GemmPlan(algo=dqt.GEMM_DOT8)]:
             got = to_host(dqt.fgemm(A, B, p, plan=plan))
             assert (got == want).all(), (p, k, plan)
 
@@ -78,7 +80,7 @@ def test_fgemm_plans(dqt):
                                         epilogue=epi)
                     got = to_host(dqt.fgemm(dA, dB, p, plan=plan))
                     assert (got == ref).all(), plan
-            for algo in (dqt.GEMM_PLAIN, dqt.GEMM_DOT4):
+            for algo in (dqt.GEMM_PLAIN, dqt.GEMM_DOT4, dqt.GEMM_DOT8):
                 got = to_host(dqt.fgemm(dA, dB, p, plan=dqt.GemmPlan(algo=algo, tile_rows=tm, tile_cols=tn, ksplit=ks)))
                 assert (got == ref).all(), (algo, tm, tn, ks)
 
@@ -92,6 +94,31 @@ def test_fgemm_large_prime_routes_plain(dqt):
     with pytest.raises(dqt.DQTError) as e:
         dqt.fgemm(to_dev(A), to_dev(B), 251, plan=dqt.GemmPlan(algo=dqt.GEMM_CMM))
     assert e.value.status in (dqt.DQT_E_UNSUPPORTED, dqt.DQT_E_BOUND)
+    # four-bit entries stop at p = 16
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.fgemm(to_dev(A), to_dev(B), 251, plan=dqt.GemmPlan(algo=dqt.GEMM_DOT8))
+    assert e.value.status == dqt.DQT_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("p", [2, 13, 16])
+def test_fgemm_dot8_edges(dqt, p):
+    """The eight-entry words at every k mod 8 (partial last word), unaligned leading dimensions and
+    the all-(p-1) case; p = 16 (entries 15, a full nibble) included."""
+    g = np.random.default_rng(900 + p)
+    plan = dqt.GemmPlan(algo=dqt.GEMM_DOT8)
+    for k in (1, 7, 8, 9, 15, 16, 17, 1023, 1024, 1025, 4097):
+        m, n = int(g.integers(1, 70)), int(g.integers(1, 300))
+        A = inputs.uniform_residues((m, k), p, int(g.integers(1 << 30)))
+        B = inputs.uniform_residues((k, n), p, int(g.integers(1 << 30)))
+        assert (to_host(dqt.fgemm(to_dev(A), to_dev(B), p, plan=plan)) == O.fgemm(A, B, p)).all(), (k, m, n)
+        W = to_dev(inputs.worst_case((m, k), p))
+        V = to_dev(inputs.worst_case((k, n), p))
+        assert (to_host(dqt.fgemm(W, V, p, plan=plan)) == (k * (p - 1) ** 2) % p).all(), k
+    # rows that start off 4-byte boundaries take the byte-wise packing
+    A = inputs.uniform_residues((45, 203), p, 1)
+    B = inputs.uniform_residues((203, 77), p, 2)
+    got = to_host(dqt.fgemm(to_dev(A), to_dev(B), p, plan=plan))
+    assert (got == O.fgemm(A, B, p)).all()
 
 
 def test_fgemm_identity_permutation(dqt):

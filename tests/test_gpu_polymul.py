@@ -187,6 +187,21 @@ def test_gf_ragged_and_unaligned(dqt):
             out = unaligned_empty((count, k), 1)
             dqt.gf_mul_u8(unaligned_like(a, 3), unaligned_like(b, 2), p, P, out=out)
             assert (to_host(out) == ref).all(), (p, k, count)
+            out = unaligned_empty((count, k), 3)
+            dqt.gf_mul_plain_u8(unaligned_like(a, 1), unaligned_like(b, 2), p, P, out=out)
+            assert (to_host(out) == ref).all(), (p, k, count)
+
+
+@pytest.mark.parametrize("p,k", [(251, 2), (251, 3), (127, 3)])
+def test_gf_plain_large_prime(dqt, p, k):
+    """The plain GF comparator's unreduced division steps at the largest primes (sums near their bound)."""
+    P = inputs.irreducible(p, k)
+    for count in (4096 + 3, 5):
+        a, b = inputs.gf_pairs(count, k, p, seed=p + count)
+        a[:64] = p - 1
+        b[:64] = p - 1
+        ref = O.gf_mul(a, b, p, P)
+        assert (to_host(dqt.gf_mul_plain_u8(to_dev(a), to_dev(b), p, P)) == ref).all(), (p, k, count)
 
 
 @pytest.mark.parametrize("p", [2, 3, 5, 7, 11])
@@ -310,6 +325,18 @@ def test_gf_dot_products(dqt, p, k, n):
     assert (got == ref).all()
     w = inputs.worst_case((5, n, k), p)
     assert (to_host(dqt.gf_dot_u8(to_dev(w), to_dev(w), p, P)) == O.gf_dot(w, w, p, P)).all()
+
+
+def test_gf_dot_many_long(dqt):
+    """More long dot products than one pass of the grid holds (a wave per dot product, grid-stride),
+    and a count that leaves the last pass partly empty."""
+    p, k, n = 3, 5, 300
+    P = inputs.irreducible(p, k)
+    g = np.random.default_rng(4242)
+    for count in (5003, 70):
+        a = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
+        b = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
+        assert (to_host(dqt.gf_dot_u8(to_dev(a), to_dev(b), p, P)) == O.gf_dot(a, b, p, P)).all(), count
 
 
 def test_check_input_and_debug_mode(dqt):

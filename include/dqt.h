@@ -378,6 +378,10 @@ dqt_status dqt_fgemm_compute(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, 
 dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, uint8_t *d_C, uint64_t ldc,
                                    const dqt_gemm_plan *plan, const void *d_work, size_t work_bytes,
                                    void *start_event, void *stop_event, void *stream);
+/* dqt_fgemm (both phases in one call) with the multiply kernel's start and end recorded the same way. */
+dqt_status dqt_fgemm_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t *d_A, uint64_t lda,
+                           const uint8_t *d_B, uint64_t ldb, uint8_t *d_C, uint64_t ldc, const dqt_gemm_plan *plan,
+                           void *d_work, size_t work_bytes, void *start_event, void *stop_event, void *stream);
 
 /*
  * One packed operand in a buffer of its own, so that it can stay resident

@@ -31,9 +31,14 @@ struct RedqArgs {
     uint32_t pad;
 };
 
+// High 32 bits of a 32 x 32-bit product (v_mul_hi_u32 on the device).
+__host__ __device__ __forceinline__ uint32_t mulhi_u32(uint32_t x, uint32_t y) {
+    return (uint32_t)(((uint64_t)x * y) >> 32);
+}
+
 // x mod p for x < 2^24 and p < 2^8, by the precomputed reciprocal (a REDC).
-__device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t p, uint32_t pmagic) {
-    uint32_t qt = __umulhi(x, pmagic);
+__host__ __device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t p, uint32_t pmagic) {
+    uint32_t qt = mulhi_u32(x, pmagic);
     uint32_t r = x - qt * p;
     return r >= p ? r - p : r;
 }
@@ -48,7 +53,7 @@ __device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t p, uint32_t p
 // fma(2^52 + r, invp, -2^52 invp) is r * invp rounded once (the same x), and
 // floor(x) + 2^52 carries floor(x) in its mantissa bits.
 template <bool SMALL>
-__device__ __forceinline__ uint64_t fdiv_floor(uint64_t r, const struct RedqArgs& a) {
+__host__ __device__ __forceinline__ uint64_t fdiv_floor(uint64_t r, const struct RedqArgs& a) {
 #pragma clang fp contract(off)
     if (SMALL) {
         const double z = __builtin_bit_cast(double, r | 0x4330000000000000ull);
@@ -90,7 +95,7 @@ struct SwarMasks {
 // are computed by one masked multiply-subtract (each field value stays in
 // [1, 2^(2w+1)), so no borrow or carry crosses a field).
 template <int NR, int B, int W, bool SMALL>
-__device__ __forceinline__ uint64_t redq_compress_t(uint64_t r, const RedqArgs& a) {
+__host__ __device__ __forceinline__ uint64_t redq_compress_t(uint64_t r, const RedqArgs& a) {
     const uint64_t s = fdiv_floor<SMALL>(r, a);
     if (B && W && B >= 2 * W + 1 && NR > 0) {
         constexpr uint64_t M = SwarMasks<(NR > 0 ? NR : 1), (B ? B : 1), (W ? W : 1)>::mask();
@@ -114,19 +119,19 @@ __device__ __forceinline__ uint64_t redq_compress_t(uint64_t r, const RedqArgs& 
 }
 
 // Run-time form (words up to 2^53).
-__device__ __forceinline__ uint64_t redq_compress(uint64_t r, const RedqArgs& a) {
+__host__ __device__ __forceinline__ uint64_t redq_compress(uint64_t r, const RedqArgs& a) {
     return redq_compress_t<0, 0, 0, false>(r, a);
 }
 
 // Residue i of U (w bits at b*i).
 template <int B = 0, int W = 0>
-__device__ __forceinline__ uint32_t field(uint64_t U, uint32_t i, const RedqArgs& a) {
+__host__ __device__ __forceinline__ uint32_t field(uint64_t U, uint32_t i, const RedqArgs& a) {
     const uint32_t b = B ? B : a.b, w = W ? W : a.w;
     return (uint32_t)(U >> (b * i)) & ((1u << w) - 1u);
 }
 
 // Correction of one residue without a table: (u_i - c*u_{i+1}) mod p.
-__device__ __forceinline__ uint32_t correct_arith(uint32_t ui, uint32_t ui1, const RedqArgs& a) {
+__host__ __device__ __forceinline__ uint32_t correct_arith(uint32_t ui, uint32_t ui1, const RedqArgs& a) {
     return mod_small(ui + a.p * a.p - a.c * ui1, a.p, a.pmagic);
 }
 
@@ -170,7 +175,7 @@ __host__ __device__ constexpr bool gather3_by_multiply() {
 
 // Table index of the window of `j` residues starting at residue s.
 template <int B = 0, int W = 0>
-__device__ __forceinline__ uint32_t window_index(uint64_t U, uint32_t s, uint32_t j, const RedqArgs& a) {
+__host__ __device__ __forceinline__ uint32_t window_index(uint64_t U, uint32_t s, uint32_t j, const RedqArgs& a) {
     const uint32_t b = B ? B : a.b, w = W ? W : a.w;
     const uint32_t x = (uint32_t)(U >> (b * s));
     if (B && W && gather3_by_multiply<(B ? B : 1), (W ? W : 1)>()) {
@@ -192,7 +197,7 @@ __device__ __forceinline__ uint32_t window_index(uint64_t U, uint32_t s, uint32_
 // Full REDQ correction: writes mu_0 .. mu_{nres-1} (section 3.2, second part)
 // through `put(i, mu_i)`.  With p | q the compressed residues are final.
 template <int NR, int B = 0, int W = 0, class Put>
-__device__ __forceinline__ void redq_correct(uint64_t U, const RedqArgs& a, const uint16_t* tab, Put put) {
+__host__ __device__ __forceinline__ void redq_correct(uint64_t U, const RedqArgs& a, const uint16_t* tab, Put put) {
     // Every branch fills all of r[] (compile-time indices), and the values are
     // handed to `put` after the branches: the array stays in registers.
     uint32_t r[NR];
@@ -227,12 +232,12 @@ __device__ __forceinline__ void redq_correct(uint64_t U, const RedqArgs& a, cons
 
 // Byte `pos` (compile-time) of a little-endian array of 32-bit words.
 template <int POS>
-__device__ __forceinline__ uint32_t byte_at(const uint32_t* w) {
+__host__ __device__ __forceinline__ uint32_t byte_at(const uint32_t* w) {
     return (w[POS >> 2] >> (8 * (POS & 3))) & 0xFFu;
 }
 
 // Deposit byte value v (< 256) at byte position pos (compile-time after unrolling).
-__device__ __forceinline__ void put_byte(uint32_t* w, int pos, uint32_t v) {
+__host__ __device__ __forceinline__ void put_byte(uint32_t* w, int pos, uint32_t v) {
     w[pos >> 2] |= v << (8 * (pos & 3));
 }
 
@@ -257,7 +262,7 @@ __host__ __device__ constexpr bool pack4_by_multiply() {
 }
 
 template <int B, int W>
-__device__ __forceinline__ uint32_t pack4_multiply(uint32_t x) {
+__host__ __device__ __forceinline__ uint32_t pack4_multiply(uint32_t x) {
     constexpr uint32_t mul = 1u | (1u << (8 - B)) | (1u << (2 * (8 - B))) | (1u << (3 * (8 - B)));
     constexpr uint32_t sh = 3 * (8 - B);
     constexpr uint32_t wm = (1u << W) - 1u;

@@ -565,6 +565,17 @@ extern "C" dqt_status dqt_fgemm_compute_timed(uint32_t p, uint64_t m, uint64_t n
     return st;
 }
 
+extern "C" dqt_status dqt_fgemm_timed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, const uint8_t* d_A,
+                                      uint64_t lda, const uint8_t* d_B, uint64_t ldb, uint8_t* d_C, uint64_t ldc,
+                                      const dqt_gemm_plan* plan, void* d_work, size_t work_bytes, void* start_event,
+                                      void* stop_event, void* stream) {
+    g_ev_start = reinterpret_cast<hipEvent_t>(start_event);
+    g_ev_stop = reinterpret_cast<hipEvent_t>(stop_event);
+    const dqt_status st = dqt_fgemm(p, m, n, kdim, d_A, lda, d_B, ldb, d_C, ldc, plan, d_work, work_bytes, stream);
+    g_ev_start = g_ev_stop = nullptr;
+    return st;
+}
+
 // Packed operands in caller-chosen buffers (one side at a time), so that a
 // packed B can stay resident and be multiplied by many row blocks of A.
 static dqt_status side_plan(uint32_t p, uint64_t rows_or_cols, uint64_t kdim, int side, const dqt_gemm_plan* plan,

@@ -8,17 +8,19 @@
 // Layouts (workspace, written by the packing launch):
 //   A8:  [m_pad][k_pad] int8, the rows of A zero-padded to k_pad (a multiple of 64);
 //   BT8: [n_pad][k_pad] int8, B transposed (column j of B as row j), zero-padded.
-// m_pad is a multiple of 32, n_pad of 64.  B is transposed through LDS in tiles
+// m_pad and n_pad are multiples of 64.  B is transposed through LDS in tiles
 // of 64 k x 64 columns, so both the reads of B and the writes of BT8 are
 // whole 16-byte runs.
 //
-// Multiply: a workgroup of 4 waves owns a 32 x 32 tile of C; the waves split
+// Multiply: a workgroup of 4 waves owns a 64 x 64 square of C; the waves split
 // k into S contiguous ranges (S = 4, 2 or 1 by the depth of k).  Each wave
-// computes its range as 2 x 2 tiles of v_mfma_i32_16x16x64_i8: lane l
-// supplies row (or column) l % 16 and the 16 consecutive k of slot l / 16,
-// for both operands, and receives rows 4 (l / 16) .. + 3 of column l % 16.
-// The loads of four k-steps (16 vector loads) are issued before their 16
-// matrix instructions.  The S partial tiles are added through LDS.
+// computes the whole square over its range as 4 x 4 tiles of
+// v_mfma_i32_16x16x64_i8 (each loaded fragment feeds four matrix
+// instructions): lane l supplies row (or column) l % 16 and the 16
+// consecutive k of slot l / 16, for both operands, and receives rows
+// 4 (l / 16) .. + 3 of column l % 16.  The loads of four k-steps (32 vector
+// loads) are issued before their 64 matrix instructions.  The S partial
+// squares are added through LDS.
 
 #include <string.h>
 
@@ -106,74 +108,89 @@ __device__ __forceinline__ void mfma_tile_of(uint32_t bid, uint32_t nblk, uint32
     *cb = logical / nrb;
 }
 
-template <int S>
+// T x T tiles of 16 x 16 per wave (a 16 T square of C); the S waves of a
+// workgroup take contiguous k ranges of the same square and meet in LDS.
+template <int S, int T>
 __global__ __launch_bounds__(256) void k_gemm_mfma(MfmaArgs g) {
-    __shared__ v4i red[S * 4 * 64];
+    constexpr int CH = 4;                        // k-steps whose loads are issued together
+    __shared__ v4i red[S > 1 ? S * T * T * 64 : 1];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
     uint32_t rb, cb;
     mfma_tile_of(blockIdx.x, gridDim.x, g.nrb, &rb, &cb);
-    const uint32_t row0 = rb * 32, col0 = cb * 32;
+    const uint32_t row0 = rb * 16 * T, col0 = cb * 16 * T;
     const uint32_t r = lane & 15u, slot = lane >> 4;
-    v4i acc[2][2];
+    v4i acc[T][T];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < T; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = (v4i){0, 0, 0, 0};
+        for (int j = 0; j < T; ++j) acc[i][j] = (v4i){0, 0, 0, 0};
     const uint32_t nsteps = g.k_pad / 64;
     const uint32_t s0 = min(nsteps, (wave % S) * g.ks), s1 = min(nsteps, s0 + g.ks);
     if (wave < (uint32_t)S) {
-        const uint8_t* pa0 = g.A8 + (size_t)(row0 + r) * g.k_pad + slot * 16;
-        const uint8_t* pa1 = pa0 + (size_t)16 * g.k_pad;
-        const uint8_t* pb0 = g.BT8 + (size_t)(col0 + r) * g.k_pad + slot * 16;
-        const uint8_t* pb1 = pb0 + (size_t)16 * g.k_pad;
+        const uint8_t* pa = g.A8 + (size_t)(row0 + r) * g.k_pad + slot * 16;
+        const uint8_t* pb = g.BT8 + (size_t)(col0 + r) * g.k_pad + slot * 16;
+        const size_t rs = (size_t)16 * g.k_pad;      // 16 rows (or columns) further
         uint32_t st = s0;
-        for (; st + 4 <= s1; st += 4) {
-            v4i a0[4], a1[4], b0[4], b1[4];
+        for (; st + CH <= s1; st += CH) {
+            v4i fa[CH][T], fb[CH][T];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const size_t o = (size_t)(st + u) * 64;
-                a0[u] = *reinterpret_cast<const v4i*>(pa0 + o);
-                a1[u] = *reinterpret_cast<const v4i*>(pa1 + o);
-                b0[u] = *reinterpret_cast<const v4i*>(pb0 + o);
-                b1[u] = *reinterpret_cast<const v4i*>(pb1 + o);
-            }
+            for (int u = 0; u < CH; ++u)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                acc[0][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0[u], b0[u], acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0[u], b1[u], acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1[u], b0[u], acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1[u], b1[u], acc[1][1], 0, 0, 0);
-            }
+                for (int i = 0; i < T; ++i) {
+                    const size_t o = (size_t)(st + u) * 64 + i * rs;
+                    fa[u][i] = *reinterpret_cast<const v4i*>(pa + o);
+                    fb[u][i] = *reinterpret_cast<const v4i*>(pb + o);
+                }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+#pragma unroll
+                for (int i = 0; i < T; ++i)
+#pragma unroll
+                    for (int j = 0; j < T; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[u][i], fb[u][j], acc[i][j], 0, 0, 0);
         }
         for (; st < s1; ++st) {
-            const size_t o = (size_t)st * 64;
-            const v4i a0 = *reinterpret_cast<const v4i*>(pa0 + o);
-            const v4i a1 = *reinterpret_cast<const v4i*>(pa1 + o);
-            const v4i b0 = *reinterpret_cast<const v4i*>(pb0 + o);
-            const v4i b1 = *reinterpret_cast<const v4i*>(pb1 + o);
-            acc[0][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[1][1], 0, 0, 0);
+            v4i fa[T], fb[T];
+#pragma unroll
+            for (int i = 0; i < T; ++i) {
+                const size_t o = (size_t)st * 64 + i * rs;
+                fa[i] = *reinterpret_cast<const v4i*>(pa + o);
+                fb[i] = *reinterpret_cast<const v4i*>(pb + o);
+            }
+#pragma unroll
+            for (int i = 0; i < T; ++i)
+#pragma unroll
+                for (int j = 0; j < T; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
         }
     }
-    // the S partial tiles meet in LDS; wave w (of 4) finishes the 16 x 16 tile (w >> 1, w & 1)
-    const uint32_t ti = wave >> 1, tj = wave & 1;
-    if (wave < (uint32_t)S) {
+    // the S partial squares meet in LDS; wave w finishes the 16 x 16 tiles t = w, w + 4, ...
+    if (S > 1) {
+        if (wave < (uint32_t)S) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < T; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) red[((wave * 2 + i) * 2 + j) * 64 + lane] = acc[i][j];
+                for (int j = 0; j < T; ++j) red[((wave * T + i) * T + j) * 64 + lane] = acc[i][j];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    v4i sum = (v4i){0, 0, 0, 0};
 #pragma unroll
-    for (int w = 0; w < S; ++w) sum += red[((w * 2 + ti) * 2 + tj) * 64 + lane];
-    const uint32_t col = col0 + 16 * tj + r;
+    for (int t = 0; t < T * T; ++t) {
+        if (S > 1 && (uint32_t)t % 4 != wave) continue;
+        const int ti = t / T, tj = t % T;
+        v4i sum = acc[ti][tj];
+        if (S > 1) {
+            sum = (v4i){0, 0, 0, 0};
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const uint32_t row = row0 + 16 * ti + 4 * slot + t;
-        if (row < g.m && col < g.n) g.C[(size_t)row * g.ldc + col] = (uint8_t)mod_u32((uint32_t)sum[t], g.p, g.pmagic);
+            for (int w = 0; w < S; ++w) sum += red[((w * T + ti) * T + tj) * 64 + lane];
+        }
+        const uint32_t col = col0 + 16 * tj + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t row = row0 + 16 * ti + 4 * slot + e;
+            if (row < g.m && col < g.n)
+                g.C[(size_t)row * g.ldc + col] = (uint8_t)mod_u32((uint32_t)sum[e], g.p, g.pmagic);
+        }
     }
 }
 
@@ -185,7 +202,7 @@ dqt_status mfma_plan(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, GemmPlan
     if (p > 128) return DQT_E_UNSUPPORTED;   // entries must be valid int8
     if (kdim * (uint64_t)(p - 1) * (p - 1) >= (1ull << 31)) return DQT_E_UNSUPPORTED;
     r->k_pad = (uint32_t)ru(kdim ? kdim : 64, 64);
-    r->m_pad = (uint32_t)ru(m ? m : 32, 32);
+    r->m_pad = (uint32_t)ru(m ? m : 64, 64);
     r->n_pad = (uint32_t)ru(n ? n : 64, 64);   // whole 64-column transpose tiles
     const uint32_t steps = r->k_pad / 64;
     r->s = steps >= 4 ? 4 : (steps >= 2 ? 2 : 1);
@@ -236,19 +253,19 @@ dqt_status mfma_compute_enqueue(const GemmPlanResolved& r, uint32_t p, uint64_t 
     g.n = (uint32_t)n;
     g.ldc = (uint32_t)ldc;
     g.k_pad = r.k_pad;
-    g.nrb = r.m_pad / 32;
+    g.nrb = r.m_pad / 64;
     const uint32_t steps = r.k_pad / 64;
     g.ks = (steps + r.s - 1) / r.s;
     g.p = p;
     g.pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
-    const unsigned grid = (r.m_pad / 32) * (r.n_pad / 32);
+    const unsigned grid = (r.m_pad / 64) * (r.n_pad / 64);
     auto go = [&](auto kern) {
         if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, e0, e1, 0, g);
         else hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, g);
     };
-    if (r.s == 4) go(k_gemm_mfma<4>);
-    else if (r.s == 2) go(k_gemm_mfma<2>);
-    else go(k_gemm_mfma<1>);
+    if (r.s == 4) go(k_gemm_mfma<4, 4>);
+    else if (r.s == 2) go(k_gemm_mfma<2, 4>);
+    else go(k_gemm_mfma<1, 4>);
     DQT_LAUNCH_CHECK("fgemm(mfma)");
     return DQT_OK;
 }

@@ -58,7 +58,7 @@ struct GemmArgs {
 
 // x mod p for any 32-bit x: quotient from the rounded-up reciprocal, one fix.
 __device__ __forceinline__ uint32_t mod_u32(uint32_t x, uint32_t p, uint32_t pmagic) {
-    const uint32_t qt = __umulhi(x, pmagic);
+    const uint32_t qt = mulhi_u32(x, pmagic);
     const int32_t r = (int32_t)(x - qt * p);
     return (uint32_t)(r < 0 ? r + (int32_t)p : r);
 }

@@ -127,6 +127,7 @@ def _load():
         "dqt_fgemm_pack": [U32, U64, U64, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_compute": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_compute_timed": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V, V, V],
+        "dqt_fgemm_timed": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V, V, V],
         "dqt_fgemm_pack_side": [U32, U64, U64, V, U64, I, ctypes.POINTER(_GemmPlan), V, V],
         "dqt_fgemm_packed": [U32, U64, U64, U64, V, V, V, U64, ctypes.POINTER(_GemmPlan), V],
         "dqt_fgemm_noalloc": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V],
@@ -565,6 +566,11 @@ class FgemmCall:
     def run(self):
         """Both phases in one call (dqt_fgemm)."""
         _check(self._lib.dqt_fgemm(*self._full_args), "dqt_fgemm")
+
+    def run_timed(self, start, stop):
+        """Both phases in one call, the multiply kernel recording its own start and end (dqt_fgemm_timed)."""
+        _check(self._lib.dqt_fgemm_timed(*self._full_args[:-1], ctypes.c_void_p(start.cuda_event),
+                                         ctypes.c_void_p(stop.cuda_event), self._st), "dqt_fgemm_timed")
 
     def pack(self):
         _check(self._lib.dqt_fgemm_pack(*self._pack_args), "dqt_fgemm_pack")

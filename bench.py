@@ -268,6 +268,49 @@ def bench_fqt(D, inputs, torch, dev, reps_big):
             out["polymul_deg47_f3_" + name] = {"polymul_s": round(nl / s, 1), "us_per_call": round(s * 1e6, 1)}
         except D.DQTError as e:
             out["polymul_deg47_f3_" + name] = {"error": str(e)}
+    del dal, dbl, ol
+    out.update(bench_fqt_long(D, inputs, torch, dev))
+    return out
+
+
+def fqt_long_model(p, n, bs):
+    """Operation counts of section 5.3's model for a product of two n-coefficient polynomials: block products
+    and REDQ_{2bs-1} of a bs-block FQT (sums of at most n_q block products, q = 2^b, (2bs-1) b <= 51), against
+    the n^2 coefficient products and 2n-1 reductions of the plain delayed product."""
+    b = 51 // (2 * bs - 1)
+    nq = ((1 << b) - 1) // (bs * (p - 1) ** 2)
+    nb = -(-n // bs)
+    nw = 2 * nb - 1
+    reds = sum(-(-(min(u, nb - 1) - max(0, u - nb + 1) + 1) // nq) for u in range(nw))
+    return {"block": bs, "q": 1 << b, "n_q": nq, "block_products": nb * nb, "redq": reds,
+            "plain_products": n * n, "plain_reductions": 2 * n - 1,
+            "model_op_ratio": round((n * n + 2 * n - 1) / (nb * nb + reds), 2)}
+
+
+def bench_fqt_long(D, inputs, torch, dev):
+    """Long products over F_3 (n = 128 .. 4096 coefficients, n = 500 the example of section 5.3): FQT by
+    blocks against the plain per-coefficient product, same batch, same launch shape."""
+    out = {}
+    p = 3
+    for n in (128, 256, 500, 1024, 2048, 4096):
+        count = max(2048, (1 << 34) // (n * n))
+        a, b = inputs.polymul_pairs(count, n, p, seed=inputs.SEED_POLYMUL + n)
+        da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+        o = torch.empty((count, 2 * n - 1), dtype=torch.uint8, device=dev)
+        row = {"count": count}
+        blocks = (0, 2, 3, 4) if n == 500 else (0,)
+        for blk in blocks:
+            s = timed_loop(lambda: D.polymul_fqt_u8(da, db, p, block=blk, out=o), 5, 2, torch)
+            key = "fqt" if blk == 0 else f"fqt_block{blk}"
+            row[key] = {"products_s": round(count / s, 1), "us_per_call": round(s * 1e6, 1),
+                        "coeff_products_s": round(count * n * n / s, 1)}
+        s = timed_loop(lambda: D.polymul_plain_u8(da, db, p, out=o), 5, 2, torch)
+        row["plain"] = {"products_s": round(count / s, 1), "us_per_call": round(s * 1e6, 1),
+                        "lane_op_frac": round(count * n * n / s / PEAK_LANE_OPS, 4)}
+        row["fqt_over_plain"] = round(row["fqt"]["products_s"] / row["plain"]["products_s"], 2)
+        row["model"] = [fqt_long_model(p, n, bs) for bs in (2, 3, 4)]
+        out[f"polymul_n{n}_f3_long"] = row
+        del da, db, o
     return out
 
 
@@ -393,10 +436,17 @@ def main():
     ws = torch.empty(D.fgemm_workspace_size(p, MNK, MNK, MNK, plan), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
-    # warmup
+    # warmup: both launch forms of the timed loop (the plain one and the one recording events), so
+    # that no first-call cost of either falls into the timed region
     wcall = D.FgemmCall(dA, dB, dC, p, plan=plan, workspace=ws, stream=stream)
-    for _ in range(args.warmup):
-        wcall.run()
+    w_a, w_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w_a.record(stream)           # torch creates the HIP event at its first record
+    w_b.record(stream)
+    for i in range(max(2, args.warmup)):
+        if i % 2:
+            wcall.run_timed(w_a, w_b)
+        else:
+            wcall.run()
     torch.cuda.synchronize()
 
     # timed region: K whole steps; the packed multiply kernel of every event_every-th step
@@ -487,6 +537,7 @@ def main():
         for name, fn in (("batched_10000_tuned", lambda: W.batched(10000, replays=3, tuner=T.Tuner())),
                          ("batched_10000_packed_cmm", lambda: W.batched(10000, replays=3, tuner=T.Tuner(),
                                                                          algo=D.GEMM_CMM)),
+                         ("batched_10000_by_bucket", lambda: W.batched_buckets(10000, tuner=T.Tuner())),
                          ("serving", lambda: W.serving(n_requests=5000, warmup=500, loads=(0.5, 0.8, 1.2)))):
             try:
                 extra[name] = fn()

@@ -239,7 +239,9 @@ dqt_status dqt_gf_dot_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count,
  * Plain per-entry comparators (the paper's "delayed" baseline, section 5.1):
  * one coefficient per machine multiply-add, integer accumulation, one
  * reduction (REDC) per output coefficient.  Same layouts and results as the
- * packed entry points.  dqt_polymul_plain_u8 accepts any k <= 64.
+ * packed entry points.  dqt_polymul_plain_u8 accepts any k <= 4096 (above 64
+ * coefficients one wave computes a product, eight output coefficients per
+ * lane, operands in LDS).
  */
 dqt_status dqt_polymul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t k, uint32_t p,
                                 uint8_t *d_out, void *stream);
@@ -253,7 +255,15 @@ dqt_status dqt_gf_mul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t 
  * per word) and each output block is recovered by one REDQ_{2d+1}; the d
  * overlapping coefficients of consecutive blocks are added mod p.
  * d_a: uint8 [count][na], d_b: uint8 [count][nb], d_out: uint8 [count][na+nb-1].
- * block = d+1 coefficients per word (0 = choose).  na, nb <= 64.
+ * block = d+1 coefficients per word (0 = choose).  na, nb <= 4096.  Up to 64
+ * coefficients each, a thread computes a product and every output block holds
+ * all its block products in one word.  Above that (p <= 127, block 2..4), one
+ * wave computes a product: the block words of both operands sit in LDS, each
+ * output block is summed n_q block products at a time (q > n_q (d+1)(p-1)^2,
+ * eq:bounds, the largest q with (2d+1) log2 q <= 53 and 32-bit operand
+ * words), with one REDQ_{2d+1} per such sum and the sums' residues added mod
+ * p; the block size minimizes block products plus reductions (section 5.3).
+ * DQT_E_UNSUPPORTED for p > 127 there.
  */
 dqt_status dqt_polymul_fqt_u8(const uint8_t *d_a, uint32_t na, const uint8_t *d_b, uint32_t nb, uint64_t count,
                               uint32_t p, uint32_t block, uint8_t *d_out, void *stream);
@@ -423,6 +433,16 @@ dqt_status dqt_fgemm_packed(uint32_t p, uint64_t m, uint64_t n, uint64_t kdim, c
  * graph and replayed) as long as the operands and d_work stay valid; calls
  * that share a d_work must not overlap.  dqt_fgemm_batched = prepare + run +
  * free.
+ *
+ * Resident packed operands (section 7.1: compressed matrices are often
+ * reused): run = pack + compute.  dqt_fgemm_batched_pack enqueues only the
+ * packing launch, which writes every product's packed copies of A and B into
+ * d_work; dqt_fgemm_batched_compute enqueues only the persistent launch (after
+ * a one-thread kernel that clears the item counter), which reads the packed
+ * copies left in d_work by the last run or pack of this batch.  The caller
+ * calls pack (or run) again after changing any operand; compute alone on
+ * operands changed since then gives the products of the old operands.  Both
+ * may be captured in a graph; DQT_E_INVALID for a null handle.
  */
 typedef struct dqt_gemm_desc {
     const uint8_t *A;
@@ -439,7 +459,7 @@ typedef struct dqt_gemm_desc {
 
 typedef struct dqt_batch_opts {
     uint32_t tile_rows;     /* 8 or 16 (0 = 16) */
-    uint32_t ksplit;        /* 2 or 4 waves per workgroup (0 = 4) */
+    uint32_t ksplit;        /* 2, 4 or 8 waves per workgroup (0 = 4); 8 not with 16 rows and 4 columns */
     uint32_t tile_cols;     /* columns per lane, 2 or 4 (0 = 2) */
 } dqt_batch_opts;
 
@@ -449,6 +469,8 @@ size_t dqt_fgemm_batched_workspace_size(const dqt_gemm_desc *descs, uint32_t cou
 dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc *descs, uint32_t count, const dqt_batch_opts *opts,
                                      void *d_work, size_t work_bytes, void *stream, dqt_batch **out);
 dqt_status dqt_fgemm_batched_run(const dqt_batch *batch, void *stream);
+dqt_status dqt_fgemm_batched_pack(const dqt_batch *batch, void *stream);
+dqt_status dqt_fgemm_batched_compute(const dqt_batch *batch, void *stream);
 void dqt_batch_free(dqt_batch *batch);
 dqt_status dqt_fgemm_batched(const dqt_gemm_desc *descs, uint32_t count, const dqt_batch_opts *opts,
                              void *d_work, size_t work_bytes, void *stream);

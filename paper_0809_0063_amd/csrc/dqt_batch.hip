@@ -178,7 +178,8 @@ static dqt_status batch_opts(const dqt_batch_opts* o, uint32_t* tm, uint32_t* tn
     *s = (o && o->ksplit) ? o->ksplit : 4;
     if (*tm != 8 && *tm != 16) return DQT_E_INVALID;
     if (*tn != 2 && *tn != 4) return DQT_E_INVALID;
-    if (*s != 2 && *s != 4) return DQT_E_INVALID;
+    if (*s != 2 && *s != 4 && *s != 8) return DQT_E_INVALID;
+    if (*s == 8 && *tm == 16 && *tn == 4) return DQT_E_INVALID;   // 128 KiB of LDS partial sums
     return DQT_OK;
 }
 
@@ -323,20 +324,30 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
 
 
 
+// Clears the work-item counter before a compute launch that follows no packing
+// launch (a kernel rather than a memset, so that the launch can be captured).
+__global__ void k_batch_reset(BatchHeader* hdr) { hdr->counter = 0; }
+
 template <int TM, int TN, int S>
-static dqt_status batch_launch(const dqt_batch* b, hipStream_t st) {
+static dqt_status batch_launch(const dqt_batch* b, hipStream_t st, bool pack, bool compute) {
     BatchHeader* hdr = reinterpret_cast<BatchHeader*>(b->work);
     const BatchDesc* descs = reinterpret_cast<const BatchDesc*>(b->work + b->descs_off);
     const uint32_t* prefix = reinterpret_cast<const uint32_t*>(b->work + b->prefix_off);
     const uint2* items = reinterpret_cast<const uint2*>(b->work + b->items_off);
     const uint64_t cus = (uint64_t)device_cus();
-    uint64_t gp = b->pack_blocks < cus * 16 ? b->pack_blocks : cus * 16;
-    if (gp < 1) gp = 1;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_batch_pack<TM, S>), dim3((unsigned)gp), dim3(256), 0, st, hdr, hdr, descs,
-                       prefix);
-    DQT_LAUNCH_CHECK("batched pack");
+    if (pack) {
+        uint64_t gp = b->pack_blocks < cus * 16 ? b->pack_blocks : cus * 16;
+        if (gp < 1) gp = 1;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_batch_pack<TM, S>), dim3((unsigned)gp), dim3(256), 0, st, hdr, hdr,
+                           descs, prefix);
+        DQT_LAUNCH_CHECK("batched pack");
+    } else {
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, hdr);
+        DQT_LAUNCH_CHECK("batched counter reset");
+    }
+    if (!compute) return DQT_OK;
     // persistent workgroups: a few per CU, never more than there are items
-    const uint64_t per_cu = (S == 2) ? 8 : 4;
+    const uint64_t per_cu = (S == 2) ? 8 : (S == 4 ? 4 : 2);
     uint64_t gc = b->n_items < cus * per_cu ? b->n_items : cus * per_cu;
     if (gc < 1) gc = 1;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_batch_compute<TM, TN, S>), dim3((unsigned)gc), dim3(64 * S), 0, st, hdr, descs,
@@ -345,19 +356,36 @@ static dqt_status batch_launch(const dqt_batch* b, hipStream_t st) {
     return DQT_OK;
 }
 
-extern "C" dqt_status dqt_fgemm_batched_run(const dqt_batch* b, void* stream) {
+static dqt_status batch_dispatch(const dqt_batch* b, void* stream, bool pack, bool compute) {
     if (!b) return DQT_E_INVALID;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (b->tn == 4) {
-        if (b->tm == 8 && b->s == 2) return batch_launch<8, 4, 2>(b, st);
-        if (b->tm == 8 && b->s == 4) return batch_launch<8, 4, 4>(b, st);
-        if (b->tm == 16 && b->s == 2) return batch_launch<16, 4, 2>(b, st);
-        return batch_launch<16, 4, 4>(b, st);
+    if (b->s == 8) {
+        if (b->tm == 8 && b->tn == 4) return batch_launch<8, 4, 8>(b, st, pack, compute);
+        if (b->tm == 8) return batch_launch<8, 2, 8>(b, st, pack, compute);
+        return batch_launch<16, 2, 8>(b, st, pack, compute);
     }
-    if (b->tm == 8 && b->s == 2) return batch_launch<8, 2, 2>(b, st);
-    if (b->tm == 8 && b->s == 4) return batch_launch<8, 2, 4>(b, st);
-    if (b->tm == 16 && b->s == 2) return batch_launch<16, 2, 2>(b, st);
-    return batch_launch<16, 2, 4>(b, st);
+    if (b->tn == 4) {
+        if (b->tm == 8 && b->s == 2) return batch_launch<8, 4, 2>(b, st, pack, compute);
+        if (b->tm == 8 && b->s == 4) return batch_launch<8, 4, 4>(b, st, pack, compute);
+        if (b->tm == 16 && b->s == 2) return batch_launch<16, 4, 2>(b, st, pack, compute);
+        return batch_launch<16, 4, 4>(b, st, pack, compute);
+    }
+    if (b->tm == 8 && b->s == 2) return batch_launch<8, 2, 2>(b, st, pack, compute);
+    if (b->tm == 8 && b->s == 4) return batch_launch<8, 2, 4>(b, st, pack, compute);
+    if (b->tm == 16 && b->s == 2) return batch_launch<16, 2, 2>(b, st, pack, compute);
+    return batch_launch<16, 2, 4>(b, st, pack, compute);
+}
+
+extern "C" dqt_status dqt_fgemm_batched_run(const dqt_batch* b, void* stream) {
+    return batch_dispatch(b, stream, true, true);
+}
+
+extern "C" dqt_status dqt_fgemm_batched_pack(const dqt_batch* b, void* stream) {
+    return batch_dispatch(b, stream, true, false);
+}
+
+extern "C" dqt_status dqt_fgemm_batched_compute(const dqt_batch* b, void* stream) {
+    return batch_dispatch(b, stream, false, true);
 }
 
 extern "C" void dqt_batch_free(dqt_batch* b) { delete b; }

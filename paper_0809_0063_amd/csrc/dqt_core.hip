@@ -224,7 +224,7 @@ extern "C" dqt_status dqt_check_input_u8(const uint8_t* d_x, uint64_t count, uin
     return h ? DQT_E_INPUT : DQT_OK;
 }
 
-extern "C" const char* dqt_version(void) { return "libdqt 0.1 gfx950"; }
+extern "C" const char* dqt_version(void) { return "libdqt 0.2 gfx950"; }
 
 extern "C" dqt_status dqt_set_table_window(uint32_t j) {
     if (j > 3) return DQT_E_INVALID;
@@ -1040,15 +1040,21 @@ extern "C" dqt_status dqt_gf_mul_u8(const uint8_t* d_a, const uint8_t* d_b, uint
     return DQT_E_UNSUPPORTED;
 }
 
+namespace dqt {
+dqt_status plain_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint64_t count, uint32_t p,
+                              uint8_t* out, hipStream_t s);
+}
+
 extern "C" dqt_status dqt_polymul_plain_u8(const uint8_t* d_a, const uint8_t* d_b, uint64_t count, uint32_t k,
                                            uint32_t p, uint8_t* d_out, void* stream) {
-    if (p < 2 || p > 255 || k < 1 || k > 64) return DQT_E_INVALID;
+    if (p < 2 || p > 255 || k < 1 || k > 4096) return DQT_E_INVALID;
     if (count == 0) return DQT_OK;
     if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
     hipStream_t s = S(stream);
     DQT_TRY(debug_gate(s, p, {{d_a, count, k, k}, {d_b, count, k, k}}));
+    if (k > 64) return plain_long_enqueue(d_a, k, d_b, k, count, p, d_out, s);
     const unsigned g4 = stream_grid((count + 3) / 4, 256);
 #define DQT_PLAIN_CASE(KK)                                                                                           \
     case KK:                                                                                                         \

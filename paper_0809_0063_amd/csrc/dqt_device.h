@@ -139,18 +139,20 @@ __host__ __device__ __forceinline__ uint32_t correct_arith(uint32_t ui, uint32_t
 // idx = u_0 | u_1 << w | ... | u_{j-1} << (j-1)w holds the j-1 corrected
 // residues mu_t = (u_t - c*u_{t+1}) mod p as bytes (section 3.5: the first
 // j-1 rows of Q_{j-1} times a window of j residues, binary indexing).
+__host__ __device__ __forceinline__ uint16_t correction_entry(uint32_t idx, const RedqArgs& a) {
+    const uint32_t wm = (1u << a.w) - 1u;
+    const uint32_t u0 = idx & wm, u1 = (idx >> a.w) & wm;
+    uint32_t e = mod_small(u0 + a.p * a.p - a.c * u1, a.p, a.pmagic);
+    if (a.tabj == 3) {
+        const uint32_t u2 = (idx >> (2 * a.w)) & wm;
+        e |= mod_small(u1 + a.p * a.p - a.c * u2, a.p, a.pmagic) << 8;
+    }
+    return (uint16_t)e;
+}
+
 __device__ __forceinline__ void build_correction_table(uint16_t* tab, const RedqArgs& a) {
     if (a.tabj == 0) return;
-    const uint32_t wm = (1u << a.w) - 1u;
-    for (uint32_t idx = threadIdx.x; idx < a.tab_entries; idx += blockDim.x) {
-        const uint32_t u0 = idx & wm, u1 = (idx >> a.w) & wm;
-        uint32_t e = mod_small(u0 + a.p * a.p - a.c * u1, a.p, a.pmagic);
-        if (a.tabj == 3) {
-            const uint32_t u2 = (idx >> (2 * a.w)) & wm;
-            e |= mod_small(u1 + a.p * a.p - a.c * u2, a.p, a.pmagic) << 8;
-        }
-        tab[idx] = (uint16_t)e;
-    }
+    for (uint32_t idx = threadIdx.x; idx < a.tab_entries; idx += blockDim.x) tab[idx] = correction_entry(idx, a);
 }
 
 // Gathering three w-bit fields spaced b apart into one 3w-bit index with one
@@ -188,6 +190,14 @@ __host__ __device__ __forceinline__ uint32_t window_index(uint64_t U, uint32_t s
         }
     }
     const uint32_t wm = (1u << w) - 1u;
+    if ((j - 1) * b + w > 32) {
+        // the window spans more than 32 bits of U: gather its fields from 64 bits
+        const uint64_t y = U >> (b * s);
+        uint32_t idx = (uint32_t)(y & wm);
+        idx |= (uint32_t)((y >> b) & wm) << w;
+        if (j == 3) idx |= (uint32_t)((y >> (2 * b)) & wm) << (2 * w);
+        return idx;
+    }
     uint32_t idx = x & wm;
     idx |= ((x >> b) & wm) << w;
     if (j == 3) idx |= ((x >> (2 * b)) & wm) << (2 * w);

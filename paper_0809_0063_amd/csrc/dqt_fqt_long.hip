@@ -1,0 +1,376 @@
+// Long polynomial products (more than 64 coefficients) by the FQT (section
+// 5.2 of the paper), and their plain per-coefficient comparator.
+//
+// FQT: each operand is cut into blocks of BS = d+1 coefficients, block i
+// holding coefficients i BS .. i BS + BS - 1 as the q-adic word
+// sum_s a_{i BS + s} q^s with q = 2^b, kept as a binary64 in LDS.  Output
+// block u, W_u = sum_i A_i B_{u-i}, is accumulated by binary64 FMAs (exact:
+// every partial sum stays below 2^51), L block products at a time: with
+// q > L BS (p-1)^2 no digit of the sum reaches q (eq:bounds), so one
+// REDQ_{2BS-1} of the sum gives the 2BS-1 residues of its coefficients
+// (section 5.3 counts these reductions).  The residues of the sums of one
+// block are added mod p in byte lanes; the top BS-1 residues of block u fall on
+// the first BS-1 coefficients of block u+1 and are added mod p when the
+// coefficients are written.
+//
+// Work split (both kernels): one workgroup per product, a thread owns R
+// consecutive outputs (output blocks for the FQT, coefficients for the plain
+// one), a "chunk".  The number of terms of a chunk rises and falls along the
+// product, so chunk c is paired with chunk C-1-c on the same thread: every
+// thread then has about the same number of terms, and one pair per thread
+// covers products of up to 4096 coefficients with at most 512 threads.  The
+// terms are taken G at a time: G values of a and the G+R-1 values of b that
+// meet them are read from LDS once and used G R times.  The operands sit in LDS
+// between zeros, so groups that overlap the ends of the operands need no test.
+//
+// The plain comparator keeps the coefficients as 32-bit values and does one
+// v_mad_u32_u24 per coefficient product (the sums stay below
+// 4096 (p-1)^2 < 2^32) and one reduction per output.
+
+#include <string.h>
+
+#include "dqt_internal.h"
+
+namespace dqt {
+
+namespace {
+
+constexpr int kLongR = 4;          // output blocks per FQT chunk
+constexpr int kPlainR = 8;         // coefficients per plain chunk
+constexpr int kPlainG = 8;         // terms per plain group
+constexpr uint32_t kPad = 16;      // zeros in LDS before b (>= R + G - 2 for both kernels)
+
+struct LongArgs {
+    uint32_t na, nb, nout;
+    uint32_t b;                     // log2 q
+    uint32_t Na, Nb, NW;            // blocks of A, of B, output blocks
+    uint32_t L;                     // block products per REDQ (a multiple of G)
+    uint32_t C;                     // chunks of R output blocks (block NW, all zero, included)
+    uint32_t na_pad, nb_tot;        // doubles of A (a multiple of G) and of B with its zeros
+    uint32_t lds_a, lds_b, lds_bnd; // byte offsets in LDS: A words, B words, last residues of each chunk
+    RedqArgs ra;
+};
+
+// coefficient-wise a + b mod p on byte lanes (each lane < p <= 127)
+__device__ __forceinline__ uint64_t add_mod_lanes(uint64_t a, uint64_t b, uint32_t p) {
+    const uint64_t ones = 0x0101010101010101ull;
+    const uint64_t s = a + b;
+    const uint64_t t = s + (uint64_t)(128 - p) * ones;
+    return s - (uint64_t)p * ((t >> 7) & ones);
+}
+
+// the integer x < 2^52 held by a binary64
+__device__ __forceinline__ uint64_t exact_u52(double x) {
+    return __builtin_bit_cast(uint64_t, x + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+
+// Smallest / largest value over the 64 lanes of the wave (the same result in every lane).
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// QB, QW: log2 q and the residue width as compile-time constants (0 = from the
+// run-time arguments).
+template <int BS, int G, int QB, int QW>
+__global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+                                                          uint8_t* __restrict__ OUT, uint64_t count, LongArgs g) {
+    constexpr int NR = 2 * BS - 1;
+    constexpr int R = kLongR;
+    extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
+    uint16_t* tab = reinterpret_cast<uint16_t*>(lsm);
+    double* ad = reinterpret_cast<double*>(lsm + g.lds_a);
+    double* bd = reinterpret_cast<double*>(lsm + g.lds_b);   // bd[kPad + i] = B_i
+    uint64_t* bnd = reinterpret_cast<uint64_t*>(lsm + g.lds_bnd);
+    const RedqArgs& ra = g.ra;
+    build_correction_table(tab, ra);
+    const uint32_t pair = threadIdx.x;
+    const uint32_t cs[2] = {pair, g.C - 1 - pair};
+    const int nc = pair < (g.C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
+    // one REDQ_{2BS-1} of each of the R sums; their residues added to res
+    auto reduce = [&](double (&W)[R], uint64_t (&res)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t U = redq_compress_t<NR, QB, QW, true>(exact_u52(W[r]), ra);
+            uint64_t v = 0;
+            redq_correct<NR, QB, QW>(U, ra, tab, [&](int s, uint32_t m) { v |= (uint64_t)m << (8 * s); });
+            res[r] = add_mod_lanes(res[r], v, ra.p);
+            W[r] = 0.0;
+        }
+    };
+    for (uint64_t t = blockIdx.x; t < count; t += gridDim.x) {
+        __syncthreads();   // the table is built / the previous product has left LDS
+        const uint8_t* a = A + t * g.na;
+        const uint8_t* b = B + t * g.nb;
+        for (uint32_t i = threadIdx.x; i < g.na_pad; i += blockDim.x) {
+            uint64_t w = 0;
+#pragma unroll
+            for (int s = 0; s < BS; ++s) {
+                const uint32_t c = i * BS + s;
+                if (c < g.na) w |= (uint64_t)a[c] << (g.b * s);
+            }
+            ad[i] = (double)w;
+        }
+        for (uint32_t k = threadIdx.x; k < g.nb_tot; k += blockDim.x) {
+            uint64_t w = 0;
+            const uint32_t i = k - kPad;
+            if (k >= kPad && i < g.Nb) {
+#pragma unroll
+                for (int s = 0; s < BS; ++s) {
+                    const uint32_t c = i * BS + s;
+                    if (c < g.nb) w |= (uint64_t)b[c] << (g.b * s);
+                }
+            }
+            bd[k] = (double)w;
+        }
+        __syncthreads();
+        uint64_t res[2][R];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // The wave walks one common sequence of term groups (from the smallest first group
+            // of its lanes to the largest last one); a lane multiplies only in its own groups.
+            // The sums are reduced at multiples of L in the common sequence, so every lane of
+            // the wave reduces at the same time and each sum holds at most L block products.
+            const bool mine = h < nc;
+            const uint32_t u0 = mine ? cs[h] * R : 0;
+            const uint32_t ilo = u0 + 1 > g.Nb ? u0 + 1 - g.Nb : 0;
+            const uint32_t ihi = min(g.Na - 1, u0 + R - 1);
+            const uint32_t lo = mine ? (ilo & ~(uint32_t)(G - 1)) : 0xFFFFFFFFu;
+            const uint32_t hi = mine ? ihi : 0u;
+            const uint32_t wlo = wave_min(lo), whi = wave_max(hi);
+            double W[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                W[r] = 0.0;
+                res[h][r] = 0;
+            }
+            if (wlo <= whi) {
+                uint32_t next_red = (wlo / g.L + 1) * g.L;
+                for (uint32_t ig = wlo; ig <= whi; ig += G) {
+                    if (ig >= lo && ig <= hi) {
+                        double av[G], wv[G + R - 1];
+#pragma unroll
+                        for (int s = 0; s < G; ++s) av[s] = ad[ig + s];
+                        const double* wb = bd + (kPad + u0 - ig - (G - 1));   // wv[x] = B_{u0 - ig - (G-1) + x}
+#pragma unroll
+                        for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[x];
+#pragma unroll
+                        for (int s = 0; s < G; ++s)
+#pragma unroll
+                            for (int r = 0; r < R; ++r) W[r] = __builtin_fma(av[s], wv[r - s + G - 1], W[r]);
+                    }
+                    if (ig + G == next_red) {
+                        next_red += g.L;
+                        reduce(W, res[h]);
+                    }
+                }
+                reduce(W, res[h]);
+            }
+            if (mine) bnd[cs[h]] = res[h][R - 1];
+        }
+        __syncthreads();
+        // coefficient j = u BS + s: residue s of block u plus residue s + BS of block u - 1
+        uint8_t* o = OUT + t * g.nout;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nc) break;
+            const uint32_t c = cs[h];
+            uint64_t prev = c ? bnd[c - 1] : 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t u = c * R + r;
+                const uint64_t cur = res[h][r];
+#pragma unroll
+                for (int s = 0; s < BS; ++s) {
+                    const uint32_t j = u * BS + s;
+                    uint32_t v = (uint32_t)(cur >> (8 * s)) & 0xFFu;
+                    if (s + BS < NR) v += (uint32_t)(prev >> (8 * (s + BS))) & 0xFFu;
+                    if (j < g.nout) o[j] = (uint8_t)(v >= ra.p ? v - ra.p : v);
+                }
+                prev = cur;
+            }
+        }
+    }
+}
+
+// Plain per-coefficient products c_j = sum_i a_i b_{j-i}; chunk c owns j = 8c .. 8c + 7.
+__global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+                                                            uint8_t* __restrict__ OUT, uint64_t count, uint32_t na,
+                                                            uint32_t nb, uint32_t p, uint32_t pmagic, uint32_t na_pad,
+                                                            uint32_t nb_tot) {
+    constexpr int R = kPlainR, G = kPlainG;
+    extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
+    uint32_t* a32 = reinterpret_cast<uint32_t*>(lsm);     // a32[i] = a_i, zeros up to na_pad
+    uint32_t* b32 = a32 + na_pad;                         // b32[kPad + k] = b_k, zeros around
+    const uint32_t nout = na + nb - 1;
+    const uint32_t C = (nout + R - 1) / R;
+    const uint32_t pair = threadIdx.x;
+    const uint32_t cs[2] = {pair, C - 1 - pair};
+    const int nc = pair < (C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
+    for (uint64_t t = blockIdx.x; t < count; t += gridDim.x) {
+        __syncthreads();
+        const uint8_t* a = A + t * na;
+        const uint8_t* b = B + t * nb;
+        for (uint32_t i = threadIdx.x; i < na_pad; i += blockDim.x) a32[i] = i < na ? a[i] : 0u;
+        for (uint32_t k = threadIdx.x; k < nb_tot; k += blockDim.x)
+            b32[k] = (k >= kPad && k - kPad < nb) ? b[k - kPad] : 0u;
+        __syncthreads();
+        uint8_t* o = OUT + t * nout;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nc) break;
+            const uint32_t j0 = cs[h] * R;
+            // i with 0 <= j - i < nb for some j in [j0, j0 + R): j0 - nb < i <= j0 + R - 1
+            const uint32_t ilo = j0 + 1 > nb ? j0 + 1 - nb : 0;
+            const uint32_t ihi = min(na - 1, j0 + R - 1);
+            uint32_t c[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) c[r] = 0;
+            for (uint32_t ig = ilo & ~(uint32_t)(G - 1); ig <= ihi; ig += G) {
+                uint32_t av[G], wv[G + R - 1];
+#pragma unroll
+                for (int s = 0; s < G; ++s) av[s] = a32[ig + s];
+                const uint32_t* wb = b32 + (kPad + j0 - ig - (G - 1));   // wv[x] = b_{j0 - ig - (G-1) + x}
+#pragma unroll
+                for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[x];
+#pragma unroll
+                for (int s = 0; s < G; ++s)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) c[r] = __umul24(av[s], wv[r - s + G - 1]) + c[r];
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (j0 + r < nout) o[j0 + r] = (uint8_t)mod_small(c[r] > 0xFFFFFFu ? c[r] % p : c[r], p, pmagic);
+        }
+    }
+}
+
+}  // namespace
+
+// Block size, q, L and the group width G of a long product: the smallest cost
+// (block products plus reductions, the two counts of section 5.3's model) over
+// block sizes 2..4 (the 2 BS - 1 residues of a block stay within the eight
+// byte lanes of one word) with q = 2^b, (2 BS - 1) b <= 51 and at least four
+// block products per reduction.  p <= 127 (two residues add within a byte lane).
+dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out,
+                         uint32_t* L_out, uint32_t* G_out) {
+    if (p > 127) return DQT_E_UNSUPPORTED;
+    const uint64_t e2 = (uint64_t)(p - 1) * (p - 1);
+    double best = 1e300;
+    uint32_t best_bs = 0;
+    for (uint32_t bs = 2; bs <= 4; ++bs) {
+        if (block && bs != block) continue;
+        const uint32_t b = 51 / (2 * bs - 1);
+        const uint64_t nq = ((1ull << b) - 1) / ((uint64_t)bs * e2);
+        if (nq < 4) continue;
+        const uint32_t G = nq >= 8 ? 8 : 4;
+        const uint32_t L = (uint32_t)(nq / G) * G;
+        const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs, NW = Na + Nb - 1;
+        double reds = 0;
+        for (uint32_t u = 0; u < NW; ++u) {
+            const uint32_t i0 = u >= Nb ? u - (Nb - 1) : 0, i1 = u < Na ? u : Na - 1;
+            reds += (double)(i1 / L - i0 / L + 1);
+        }
+        const double cost = (double)Na * Nb + reds * (16.0 + 3.0 * (2 * bs - 1));
+        if (cost < best) {
+            best = cost;
+            best_bs = bs;
+            *b_out = b;
+            *L_out = L;
+            *G_out = G;
+        }
+    }
+    if (!best_bs) return block ? DQT_E_BOUND : DQT_E_UNSUPPORTED;
+    *bs_out = best_bs;
+    return DQT_OK;
+}
+
+static constexpr uint32_t kLongMaxCoeffs = 4096;
+
+// Workgroups per CU that the LDS (160 KiB) and the wave slots allow.
+static unsigned groups_per_cu(size_t smem, unsigned threads) {
+    const unsigned by_lds = (unsigned)((160u * 1024u) / (smem ? smem : 1));
+    const unsigned by_waves = 32u / ((threads + 63) / 64);
+    const unsigned n = by_lds < by_waves ? by_lds : by_waves;
+    return n ? n : 1;
+}
+
+dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint64_t count, uint32_t p,
+                            uint32_t block, uint8_t* out, hipStream_t s, bool check_only) {
+    if (na > kLongMaxCoeffs || nb > kLongMaxCoeffs) return DQT_E_UNSUPPORTED;
+    uint32_t bs = 0, b = 0, L = 0, G = 0;
+    DQT_TRY(fqt_long_plan(p, na, nb, block, &bs, &b, &L, &G));
+    LongArgs g;
+    memset(&g, 0, sizeof(g));
+    DQT_TRY(make_redq_args(p, b, 2 * bs - 1, (2 * bs - 1) * b, &g.ra));
+    if (check_only) return DQT_OK;
+    g.na = na;
+    g.nb = nb;
+    g.nout = na + nb - 1;
+    g.b = b;
+    g.Na = (na + bs - 1) / bs;
+    g.Nb = (nb + bs - 1) / bs;
+    g.NW = g.Na + g.Nb - 1;
+    g.L = L;
+    g.C = (g.NW + 1 + kLongR - 1) / kLongR;   // blocks 0 .. NW (block NW only carries the top residues of NW-1)
+    g.na_pad = (g.Na + G - 1) / G * G;
+    g.nb_tot = kPad + g.Nb + kPad;
+    g.lds_a = 4096 * 2;                        // the correction table
+    g.lds_b = g.lds_a + g.na_pad * 8;
+    g.lds_bnd = g.lds_b + ((g.nb_tot * 8 + 15) & ~15u);
+    const size_t smem = g.lds_bnd + (size_t)g.C * 8;
+    const unsigned threads = ((g.C + 1) / 2 + 63) / 64 * 64;   // one chunk pair per thread
+    if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
+    const unsigned grid = stream_grid(count, 1, groups_per_cu(smem, threads));
+    // F_3 in blocks of three at q = 2^10 (the case of section 5.3's example) has a
+    // compile-time q and residue width; every other case the run-time form
+    if (bs == 3 && G == 8 && b == 10 && g.ra.w == 2) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<3, 8, 10, 2>), dim3(grid), dim3(threads), smem, s, A, B,
+                           out, count, g);
+        DQT_LAUNCH_CHECK("dqt_polymul_fqt_u8 (long)");
+        return DQT_OK;
+    }
+    const unsigned key = bs * 16 + G;
+    switch (key) {
+#define DQT_LONG_CASE(BSV, GV)                                                                                   \
+    case BSV * 16 + GV:                                                                                          \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, GV, 0, 0>), dim3(grid), dim3(threads), smem, s, \
+                           A, B, out, count, g);                                                                 \
+        break;
+        DQT_LONG_CASE(2, 4)
+        DQT_LONG_CASE(2, 8)
+        DQT_LONG_CASE(3, 4)
+        DQT_LONG_CASE(3, 8)
+        DQT_LONG_CASE(4, 4)
+        DQT_LONG_CASE(4, 8)
+#undef DQT_LONG_CASE
+        default: return DQT_E_UNSUPPORTED;
+    }
+    DQT_LAUNCH_CHECK("dqt_polymul_fqt_u8 (long)");
+    return DQT_OK;
+}
+
+dqt_status plain_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint64_t count, uint32_t p,
+                              uint8_t* out, hipStream_t s) {
+    if (na > kLongMaxCoeffs || nb > kLongMaxCoeffs) return DQT_E_UNSUPPORTED;
+    const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
+    const uint32_t na_pad = (na + kPlainG - 1) / kPlainG * kPlainG;
+    const uint32_t nb_tot = kPad + nb + kPad;
+    const size_t smem = ((size_t)na_pad + nb_tot) * 4;
+    const uint32_t C = (na + nb - 1 + kPlainR - 1) / kPlainR;
+    const unsigned threads = ((C + 1) / 2 + 63) / 64 * 64;
+    if (threads > 512) return DQT_E_UNSUPPORTED;
+    const unsigned grid = stream_grid(count, 1, groups_per_cu(smem, threads));
+    hipLaunchKernelGGL(k_polymul_plain_long, dim3(grid), dim3(threads), smem, s, A, B, out, count, na, nb, p, pmagic,
+                       na_pad, nb_tot);
+    DQT_LAUNCH_CHECK("dqt_polymul_plain_u8 (long)");
+    return DQT_OK;
+}
+
+}  // namespace dqt

@@ -124,6 +124,8 @@ def _load():
         "dqt_fgemm_batched_prepare": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V,
                                       ctypes.POINTER(ctypes.c_void_p)],
         "dqt_fgemm_batched_run": [V, V],
+        "dqt_fgemm_batched_pack": [V, V],
+        "dqt_fgemm_batched_compute": [V, V],
         "dqt_fgemm_pack": [U32, U64, U64, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_compute": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_compute_timed": [U32, U64, U64, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V, V, V],
@@ -635,6 +637,14 @@ class Batch:
 
     def run(self, stream=None):
         _check(_load().dqt_fgemm_batched_run(self._handle, _stream(stream)), "dqt_fgemm_batched_run")
+
+    def pack(self, stream=None):
+        """Only the packing launch: the packed copies of every operand in the workspace."""
+        _check(_load().dqt_fgemm_batched_pack(self._handle, _stream(stream)), "dqt_fgemm_batched_pack")
+
+    def compute(self, stream=None):
+        """Only the persistent launch, on the packed copies left by the last run() or pack()."""
+        _check(_load().dqt_fgemm_batched_compute(self._handle, _stream(stream)), "dqt_fgemm_batched_compute")
 
     def close(self):
         if self._handle:

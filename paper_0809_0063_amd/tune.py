@@ -4,7 +4,8 @@ For each bucket (a range of orders n and a prime p) the tuner times the
 candidate plans on one representative square product and keeps the fastest:
 
 * algo: packed CMM (four entries per word, middle product on 16-bit Kronecker
-  pairs), plain (one entry per word), dot4 (four u8 entries per word);
+  pairs), plain (one entry per word), dot4 (four u8 entries per word), dot8
+  (eight 4-bit entries per word, p <= 16);
 * the delayed-reduction interval of the packed path (the largest allowed by
   eq:lower, or a fraction of it) and the matching Q;
 * the epilogue (one REDC per output, or REDQ over gathered dot products).
@@ -27,7 +28,7 @@ import math
 import os
 import time
 from dataclasses import asdict, dataclass
-from typing import Dict, List, Optional, Sequence, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import torch
 
@@ -35,7 +36,8 @@ from . import dqt as D
 
 BUCKET_EDGES = (16, 32, 64, 128, 256, 512, 1025)
 # persistent-launch shapes (rows per wave, waves splitting k, columns per lane)
-LAUNCH_SHAPES = ((16, 4, 2), (8, 2, 2), (16, 2, 2), (8, 4, 2), (8, 4, 4), (8, 2, 4), (16, 2, 4), (16, 4, 4))
+LAUNCH_SHAPES = ((16, 4, 2), (8, 2, 2), (16, 2, 2), (8, 4, 2), (8, 4, 4), (8, 2, 4), (16, 2, 4), (16, 4, 4),
+                 (8, 8, 4), (8, 8, 2), (16, 8, 2))
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
@@ -78,6 +80,8 @@ def model_cost(p: int, n: int, plan: BucketPlan) -> float:
         return macs / 4 + n * n * (3 if plan.epilogue == 0 else 5)
     if plan.algo == D.GEMM_DOT4:
         return macs / 4 + 3 * n * n
+    if plan.algo == D.GEMM_DOT8:
+        return macs / 8 + 3 * n * n
     return macs + 3 * n * n
 
 
@@ -102,6 +106,8 @@ def fqt_model(N: int, p: int, d: int, beta: int) -> Tuple[float, float, float, f
 
 def candidates(p: int, n: int) -> List[BucketPlan]:
     out = [BucketPlan(D.GEMM_PLAIN), BucketPlan(D.GEMM_DOT4)]
+    if p <= 16:
+        out.append(BucketPlan(D.GEMM_DOT8))
     lmax = cmm_interval_max(p, n)
     if lmax >= 4:
         ivals = sorted({min(lmax, ((n + 3) // 4) * 4), max(4, (lmax // 2) // 4 * 4)})
@@ -237,10 +243,13 @@ class Tuner:
         self.table[f"{p}:{bucket}"] = best
         return best
 
-    def tune(self, primes: Sequence[int], buckets: Optional[Sequence[int]] = None, reps: int = 5):
+    def tune(self, primes: Sequence[int], buckets: Optional[Sequence[int]] = None, reps: int = 5,
+             progress: Optional[Callable[[str], None]] = None):
         for p in primes:
             for b in (buckets if buckets is not None else range(len(BUCKET_EDGES) - 1)):
-                self.tune_bucket(p, b, reps)
+                best = self.tune_bucket(p, b, reps)
+                if progress is not None:
+                    progress(f"{p}:{b} {best}")
         return self.table
 
     def tune_launch(self, descs, ws: torch.Tensor, shapes=LAUNCH_SHAPES, reps: int = 3):
@@ -284,9 +293,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     t = Tuner(args.out)
     t0 = time.time()
-    t.tune(args.primes, reps=args.reps)
-    for k in sorted(t.table):
-        print(k, t.table[k], flush=True)
+    t.tune(args.primes, reps=args.reps, progress=lambda m: print(m, flush=True))
     # launch shape on a prefix of the batched workload with the tuned plans
     dev = torch.device("cuda:0")
     items = inputs.batch_items(10000)[: args.launch_items]

@@ -234,3 +234,18 @@ def test_shape_rule_refused_for_one_packed_side(D):
     cp = pl._c()
     assert lib.dqt_fgemm_pack_side(3, 8, 8, None, 8, 0, ctypes.byref(cp), None, None) == D.DQT_E_INVALID
     assert lib.dqt_fgemm_packed(3, 8, 8, 8, None, None, None, 8, ctypes.byref(cp), None) == D.DQT_E_INVALID
+
+
+def test_batched_launch_shapes(D):
+    """Workspace sizes of a batch for every accepted launch shape (rows, k-split, columns); the shape
+    whose LDS partial sums would exceed the workgroup's share (16 rows, 4 columns, 8 waves) and
+    unknown shapes get 0."""
+    descs = (D._GemmDesc * 2)()
+    for i, (m, n, k, p) in enumerate([(100, 70, 300, 3), (1024, 1024, 1024, 7)]):
+        descs[i] = D._GemmDesc(0x1000, 0x2000, 0x3000, m, n, k, k, n, n, p, D.GEMM_CMM, 0, 0, 0)
+    ok = [(8, 2, 2), (8, 4, 2), (8, 8, 2), (16, 2, 2), (16, 4, 2), (16, 8, 2), (8, 2, 4), (8, 4, 4), (8, 8, 4),
+          (16, 2, 4), (16, 4, 4)]
+    for shape in ok:
+        assert D.fgemm_batched_workspace_size(descs, *shape) > 0, shape
+    for shape in [(16, 8, 4), (4, 2, 2), (8, 3, 2), (8, 2, 3)]:
+        assert D.fgemm_batched_workspace_size(descs, *shape) == 0, shape

@@ -29,7 +29,8 @@ def _make(D, items, algo_of=lambda i, it: 0):
 
 
 @pytest.mark.parametrize("tile_rows,ksplit,tile_cols", [(16, 4, 2), (8, 2, 2), (16, 2, 2), (8, 4, 2), (8, 4, 4),
-                                                        (8, 2, 4), (16, 2, 4), (16, 4, 4)])
+                                                        (8, 2, 4), (16, 2, 4), (16, 4, 4), (8, 8, 4),
+                                                        (8, 8, 2), (16, 8, 2)])
 def test_batch_small_mixed(dqt, tile_rows, ksplit, tile_cols):
     items = inputs.batch_items(60, nmin=1, nmax=300, seed=99)
     algos = [dqt.GEMM_AUTO, dqt.GEMM_CMM, dqt.GEMM_PLAIN, dqt.GEMM_DOT4, dqt.GEMM_DOT8]

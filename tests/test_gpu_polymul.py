@@ -112,9 +112,11 @@ def test_unfused_composition_matches(dqt):
 
 @pytest.mark.parametrize("p,b,nres", [(3, 6, 7), (3, 13, 4), (2, 11, 4), (5, 7, 7), (7, 7, 7), (11, 9, 5),
                                       (13, 10, 5), (31, 11, 4), (251, 17, 3), (3, 4, 13), (3, 13, 1),
-                                      (7, 3, 17), (5, 26, 2), (3, 5, 10), (3, 8, 6)])
+                                      (7, 3, 17), (5, 26, 2), (3, 5, 10), (3, 8, 6), (5, 17, 3), (3, 16, 3),
+                                      (13, 17, 3), (7, 17, 3)])
 def test_redq_unpack_words(dqt, p, b, nres):
-    """REDQ of arbitrary words with digits < q (top digit free) vs radix conversion + mod p."""
+    """REDQ of arbitrary words with digits < q (top digit free) vs radix conversion + mod p; the last
+    four have correction windows of three residues spanning more than 32 bits of the word."""
     g = np.random.default_rng(p * 1000 + b * 10 + nres)
     n = 20000
     top_bits = 53 - b * (nres - 1)
@@ -337,6 +339,41 @@ def test_gf_dot_many_long(dqt):
         a = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
         b = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
         assert (to_host(dqt.gf_dot_u8(to_dev(a), to_dev(b), p, P)) == O.gf_dot(a, b, p, P)).all(), count
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 13, 31, 127])
+def test_fqt_long_products(dqt, p):
+    """Products of more than 64 coefficients (one wave per product, chunked packed sums) and the plain
+    comparator at the same lengths, up to 4096 coefficients, the all-(p-1) case included."""
+    g = np.random.default_rng(7000 + p)
+    for na, nb, count in [(65, 65, 300), (100, 200, 100), (256, 255, 64), (500, 500, 40), (1000, 1024, 9),
+                          (4096, 4096, 3), (65, 4096, 5), (3000, 70, 5)]:
+        a = g.integers(0, p, size=(count, na), dtype=np.uint8)
+        b = g.integers(0, p, size=(count, nb), dtype=np.uint8)
+        a[0] = p - 1
+        b[0] = p - 1
+        ref = O.polymul(a, b, p)
+        got = to_host(dqt.polymul_fqt_u8(to_dev(a), to_dev(b), p))
+        assert (got == ref).all(), (p, na, nb)
+        if na == nb:
+            assert (to_host(dqt.polymul_plain_u8(to_dev(a), to_dev(b), p)) == ref).all(), (p, na)
+
+
+def test_fqt_long_block_sizes_and_limits(dqt):
+    """Every block size of the long path gives the oracle's bytes; the limits are refused."""
+    p, na, nb, count = 3, 777, 500, 20
+    a, b = inputs.polymul_pairs(count, na, p, seed=77, kb=nb)
+    ref = O.polymul(a, b, p)
+    for block in (2, 3, 4):
+        got = to_host(dqt.polymul_fqt_u8(to_dev(a), to_dev(b), p, block=block))
+        assert (got == ref).all(), block
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.polymul_fqt_u8(to_dev(a), to_dev(b), 131)
+    assert e.value.status == dqt.DQT_E_UNSUPPORTED
+    big = np.zeros((1, 4097), dtype=np.uint8)
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.polymul_fqt_u8(to_dev(big), to_dev(big), 3)
+    assert e.value.status == dqt.DQT_E_INVALID
 
 
 def test_check_input_and_debug_mode(dqt):

@@ -37,13 +37,18 @@ def test_cmm_interval_bounds():
         assert L * (p - 1) ** 2 < 2 ** bmax and (L + 4) * (p - 1) ** 2 >= 2 ** bmax - 4 * (p - 1) ** 2
 
 
-def test_model_prefers_four_macs_per_instruction():
+def test_model_prefers_most_macs_per_instruction():
+    """The seed model orders the candidates by multiply-adds per instruction: eight (dot8, p <= 16),
+    then four (packed CMM or dot4); no CMM where (p-1)^2 leaves no delayed interval, no dot8 above 16."""
     from paper_0809_0063_amd import dqt as D
     from paper_0809_0063_amd import tune as T
     cands = T.candidates(3, 512)
     best = min(cands, key=lambda c: T.model_cost(3, 512, c))
-    assert best.algo in (D.GEMM_CMM, D.GEMM_DOT4)
-    assert all(c.algo != D.GEMM_CMM for c in T.candidates(251, 512))
+    assert best.algo == D.GEMM_DOT8
+    c17 = T.candidates(17, 512)
+    assert all(c.algo != D.GEMM_DOT8 for c in c17)
+    assert min(c17, key=lambda c: T.model_cost(17, 512, c)).algo in (D.GEMM_CMM, D.GEMM_DOT4)
+    assert all(c.algo not in (D.GEMM_CMM, D.GEMM_DOT8) for c in T.candidates(251, 512))
 
 
 def test_buckets():

@@ -163,6 +163,37 @@ def bench_gemm_comparators(D, torch, dA, dB, dC, p, row0, stream, reps):
                                 "kernel_us": round(kus, 3), "kernel_fp_top_s": round(2 * macs / kus / 1e6, 1),
                                 "bound": bound, "work_per_launch": work, "work_unit": unit[bound],
                                 "kernel_frac": round(work / (kus * 1e-6) / peak[bound], 4)}
+    out.update(bench_gemm_4096(D, torch, p, stream, peak, unit))
+    return out
+
+
+def bench_gemm_4096(D, torch, p, stream, peak, unit):
+    """The multiply kernels at 4096^3 over F_3 (64 times the work of the headline product), where launch
+    and start-up latency no longer dominate: kernel time and fraction of each kernel's own roofline."""
+    import numpy as np
+    from paper_0809_0063_amd import inputs
+    n = 4096
+    macs = float(n) ** 3
+    A, B = inputs.gemm_pair(n, n, n, p, seed=inputs.SEED_FGEMM + 4096)
+    dA, dB = torch.from_numpy(A).to("cuda"), torch.from_numpy(B).to("cuda")
+    dC = torch.empty((n, n), dtype=torch.uint8, device="cuda")
+    row0 = (A[:1].astype(np.int64) @ B.astype(np.int64)) % p
+    out = {}
+    for name, pl, bound, work in (("packed_cmm", D.GemmPlan(algo=D.GEMM_CMM), "alu", macs / 4),
+                                  ("plain_dot4", D.GemmPlan(algo=D.GEMM_DOT4), "alu", macs / 4),
+                                  ("plain_dot8", D.GemmPlan(algo=D.GEMM_DOT8), "alu", macs / 8),
+                                  ("mfma_int8", D.GemmPlan(algo=D.GEMM_MFMA), "mfma_int8", 2 * macs),
+                                  ("right_compressed_f64mfma", D.GemmPlan(algo=D.GEMM_RIGHT), "mfma_f64",
+                                   macs / f64_digits(p, n))):
+        c2 = D.FgemmCall(dA, dB, dC, p, plan=pl, stream=stream)
+        c2.run()
+        torch.cuda.synchronize()
+        assert (dC[:1].cpu().numpy() == row0).all(), name
+        kus = kernel_us(c2, torch, 6)
+        out["fgemm4096_" + name] = {"kernel_us": round(kus, 1), "kernel_fp_top_s": round(2 * macs / kus / 1e6, 1),
+                                    "bound": bound, "work_per_launch": work, "work_unit": unit[bound],
+                                    "kernel_frac": round(work / (kus * 1e-6) / peak[bound], 4)}
+        del c2
     return out
 
 

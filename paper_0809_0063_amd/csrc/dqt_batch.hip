@@ -1,20 +1,26 @@
-// Batched F_p matrix products: one persistent launch over all (product,
-// tile) work items, preceded by one packing launch for all products.
+// Batched F_p matrix products: one packing launch for all products, then
+// persistent launches over all (product, tile) work items.
 //
 // The host builds, once per batch, a device-resident plan in the caller's
 // workspace: a header, one descriptor per product (its resolved packing and
 // delayed-reduction parameters and its packed-operand slices of the
-// workspace), the prefix sums of packing blocks, and the work-item list
-// sorted by decreasing cost (largest inner dimension first, so that the big
-// tiles start early and the small ones fill the tail).  Running the batch is
-// two kernel launches that read only the workspace, so they can be captured
-// in a graph and replayed:
+// workspace), the prefix sums of packing blocks, and the work-item list,
+// grouped by kernel variant (packed middle product with or without
+// intermediate extraction and with either epilogue, dot4, dot8, plain) and,
+// within a variant, sorted by decreasing cost (largest inner dimension first,
+// so that the big tiles start early and the small ones fill the tail).
+// Running the batch reads only the workspace, so it can be captured in a
+// graph and replayed:
 //   k_batch_pack:    grid-stride over every packing block of every product
 //                    (binary search of the block prefix); resets the item
-//                    counter;
-//   k_batch_compute: persistent workgroups take the next item from an atomic
-//                    counter until the list is exhausted (every workgroup
-//                    exits when its fetched index passes the end).
+//                    counters;
+//   k_batch_compute: one launch per variant present; its persistent
+//                    workgroups take the next item of the variant's range
+//                    from an atomic counter until the range is exhausted
+//                    (every workgroup exits when its fetched index passes the
+//                    end).  A launch per variant gives each its own register
+//                    allocation (one kernel holding every variant would need
+//                    the largest of them, and more, for all).
 
 #include <string.h>
 
@@ -33,14 +39,34 @@ struct BatchDesc {
     uint32_t pad[3];
 };
 
+// Kernel variants of the multiply: the packed middle product (with or without
+// intermediate extraction, REDC or REDQ epilogue), dot4, dot8 and the plain
+// per-entry product.  Each variant has its own persistent launch (its own
+// register allocation) over its own contiguous range of the item list.
+enum BatchVariant : uint32_t {
+    BV_DOT2 = 0,        // packed, whole k in one interval, REDC
+    BV_DOT2_EPIQ,       // packed, whole k in one interval, REDQ epilogue
+    BV_DOT2_FLUSH,      // packed, intermediate extraction, REDC
+    BV_DOT2_FLUSH_EPIQ, // packed, intermediate extraction, REDQ epilogue
+    BV_DOT4,
+    BV_DOT8,
+    BV_MAD,
+    BV_COUNT
+};
+
 struct BatchHeader {
     uint32_t n_desc;
     uint32_t n_items;
-    uint32_t counter;      // next work item (reset by the packing launch)
     uint32_t total_pack_blocks;
-    uint32_t tm, s;        // tile rows and k-split the plan was built for
-    uint32_t pad[58];
+    uint32_t tm, s;                   // tile rows and k-split the plan was built for
+    uint32_t pad0[3];
+    uint32_t counter[BV_COUNT];       // next work item of each variant (reset before each compute launch)
+    uint32_t pad1;
+    uint32_t begin[BV_COUNT], end[BV_COUNT];   // item range of each variant
+    uint32_t pad2[34];
 };
+
+static_assert(sizeof(BatchHeader) == 256, "batch header layout");
 
 struct BatchLayout {
     size_t header, descs, prefix, items, packed, total;
@@ -52,7 +78,7 @@ template <int TM, int S>
 __global__ __launch_bounds__(256) void k_batch_pack(const BatchHeader* __restrict__ hdr, BatchHeader* hdr_w,
                                                     const BatchDesc* __restrict__ descs,
                                                     const uint32_t* __restrict__ prefix) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) hdr_w->counter = 0;
+    if (blockIdx.x == 0 && threadIdx.x < BV_COUNT) hdr_w->counter[threadIdx.x] = 0;
     const uint32_t nd = hdr->n_desc;
     const uint32_t total = hdr->total_pack_blocks;
     // each workgroup packs one contiguous range of blocks: one binary search
@@ -79,40 +105,38 @@ __global__ __launch_bounds__(256) void k_batch_pack(const BatchHeader* __restric
     }
 }
 
-template <int TM, int TN, int S>
+template <int OP, int TM, int TN, int S, bool FLUSH, int EPI>
 __global__ __launch_bounds__(64 * S) void k_batch_compute(BatchHeader* hdr, const BatchDesc* __restrict__ descs,
-                                                          const uint2* __restrict__ items) {
+                                                          const uint2* __restrict__ items, uint32_t variant) {
     __shared__ __attribute__((aligned(16))) uint32_t red[TileSmem<TM, TN, S>::words];
     __shared__ uint32_t next;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t n_items = hdr->n_items;
+    const uint32_t begin = hdr->begin[variant], end = hdr->end[variant];
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(&hdr->counter, 1u);
+        if (threadIdx.x == 0) next = atomicAdd(&hdr->counter[variant], 1u);
         __syncthreads();
-        const uint32_t it = __builtin_amdgcn_readfirstlane(next);
+        const uint32_t it = __builtin_amdgcn_readfirstlane(next) + begin;
         __syncthreads();
-        if (it >= n_items) break;
+        if (it >= end) break;
         const uint2 item = items[it];
         const uint32_t d = __builtin_amdgcn_readfirstlane(item.x);
         const uint32_t tile = __builtin_amdgcn_readfirstlane(item.y);
         const GemmArgs g = descs[d].g;
         const uint32_t rb = tile % g.nrb, cb = tile / g.nrb;
-        switch (g.op) {
-            case OP_DOT2:
-                if (g.lw) {
-                    if (g.epi) gemm_tile<OP_DOT2, TM, TN, S, true, 1>(g, rb, cb, wave, lane, red);
-                    else gemm_tile<OP_DOT2, TM, TN, S, true, 0>(g, rb, cb, wave, lane, red);
-                } else {
-                    if (g.epi) gemm_tile<OP_DOT2, TM, TN, S, false, 1>(g, rb, cb, wave, lane, red);
-                    else gemm_tile<OP_DOT2, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red);
-                }
-                break;
-            case OP_DOT4: gemm_tile<OP_DOT4, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
-            case OP_DOT8: gemm_tile<OP_DOT8, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
-            default: gemm_tile<OP_MAD, TM, TN, S, false, 0>(g, rb, cb, wave, lane, red); break;
-        }
+        gemm_tile<OP, TM, TN, S, FLUSH, EPI>(g, rb, cb, wave, lane, red);
         __syncthreads();  // the LDS reduction buffer is reused by the next item
+    }
+}
+
+static uint32_t batch_variant(const GemmPlanResolved& r) {
+    switch (r.op) {
+        case OP_DOT2:
+            if (r.lw) return r.epi ? BV_DOT2_FLUSH_EPIQ : BV_DOT2_FLUSH;
+            return r.epi ? BV_DOT2_EPIQ : BV_DOT2;
+        case OP_DOT4: return BV_DOT4;
+        case OP_DOT8: return BV_DOT8;
+        default: return BV_MAD;
     }
 }
 
@@ -170,6 +194,7 @@ struct dqt_batch {
     size_t descs_off, prefix_off, items_off;
     uint32_t tm, tn, s, count;
     uint64_t n_items, pack_blocks;
+    uint32_t variant_items[BV_COUNT];
 };
 
 static dqt_status batch_opts(const dqt_batch_opts* o, uint32_t* tm, uint32_t* tn, uint32_t* s) {
@@ -283,23 +308,32 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
     }
     prefix[count] = (uint32_t)blocks;
     if (blocks > 0xFFFFFFFFull) return DQT_E_INVALID;
-    // work items, most expensive products first (cost of a tile ~ the instructions of its
-    // k loop: the inner dimension over the entries per word)
+    // work items grouped by kernel variant; within a variant, most expensive products
+    // first (cost of a tile ~ the instructions of its k loop: the inner dimension over
+    // the entries per word)
     std::vector<uint32_t> order(count);
     for (uint32_t i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        const uint32_t va = batch_variant(plans[a]), vb = batch_variant(plans[b]);
+        if (va != vb) return va < vb;
         return (uint64_t)descs[a].kdim * (8 / entries_per_word(plans[a].op)) >
                (uint64_t)descs[b].kdim * (8 / entries_per_word(plans[b].op));
     });
     uint64_t it = 0;
+    uint32_t vcount[BV_COUNT] = {0};
+    for (uint32_t v = 0; v < BV_COUNT; ++v) H->begin[v] = H->end[v] = 0;
     for (uint32_t oi = 0; oi < count; ++oi) {
         const uint32_t i = order[oi];
+        const uint32_t v = batch_variant(plans[i]);
+        if (vcount[v] == 0) H->begin[v] = (uint32_t)it;
         const uint32_t tiles = D[i].g.nrb * D[i].g.ncb;
         for (uint32_t t = 0; t < tiles; ++t) items[it++] = make_uint2(i, t);
+        vcount[v] += tiles;
+        H->end[v] = (uint32_t)it;
     }
     H->n_desc = count;
     H->n_items = (uint32_t)n_items;
-    H->counter = 0;
+    for (uint32_t v = 0; v < BV_COUNT; ++v) H->counter[v] = 0;
     H->total_pack_blocks = (uint32_t)blocks;
     H->tm = tm;
     H->s = s;
@@ -318,6 +352,7 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
     b->count = count;
     b->n_items = n_items;
     b->pack_blocks = blocks;
+    for (uint32_t v = 0; v < BV_COUNT; ++v) b->variant_items[v] = vcount[v];
     *out = b;
     return DQT_OK;
 }
@@ -326,7 +361,9 @@ extern "C" dqt_status dqt_fgemm_batched_prepare(const dqt_gemm_desc* descs, uint
 
 // Clears the work-item counter before a compute launch that follows no packing
 // launch (a kernel rather than a memset, so that the launch can be captured).
-__global__ void k_batch_reset(BatchHeader* hdr) { hdr->counter = 0; }
+__global__ void k_batch_reset(BatchHeader* hdr) {
+    if (threadIdx.x < BV_COUNT) hdr->counter[threadIdx.x] = 0;
+}
 
 template <int TM, int TN, int S>
 static dqt_status batch_launch(const dqt_batch* b, hipStream_t st, bool pack, bool compute) {
@@ -342,17 +379,32 @@ static dqt_status batch_launch(const dqt_batch* b, hipStream_t st, bool pack, bo
                            descs, prefix);
         DQT_LAUNCH_CHECK("batched pack");
     } else {
-        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, hdr);
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, hdr);
         DQT_LAUNCH_CHECK("batched counter reset");
     }
     if (!compute) return DQT_OK;
-    // persistent workgroups: a few per CU, never more than there are items
+    // one persistent launch per variant present: a few workgroups per CU, never more
+    // than the variant has items
     const uint64_t per_cu = (S == 2) ? 8 : (S == 4 ? 4 : 2);
-    uint64_t gc = b->n_items < cus * per_cu ? b->n_items : cus * per_cu;
-    if (gc < 1) gc = 1;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_batch_compute<TM, TN, S>), dim3((unsigned)gc), dim3(64 * S), 0, st, hdr, descs,
-                       items);
-    DQT_LAUNCH_CHECK("batched compute");
+    for (uint32_t v = 0; v < BV_COUNT; ++v) {
+        const uint64_t nv = b->variant_items[v];
+        if (!nv) continue;
+        const unsigned gc = (unsigned)(nv < cus * per_cu ? nv : cus * per_cu);
+#define DQT_BV(OPV, FL, EP)                                                                                         \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_batch_compute<OPV, TM, TN, S, FL, EP>), dim3(gc), dim3(64 * S), 0, st, hdr, \
+                       descs, items, v)
+        switch (v) {
+            case BV_DOT2: DQT_BV(OP_DOT2, false, 0); break;
+            case BV_DOT2_EPIQ: DQT_BV(OP_DOT2, false, 1); break;
+            case BV_DOT2_FLUSH: DQT_BV(OP_DOT2, true, 0); break;
+            case BV_DOT2_FLUSH_EPIQ: DQT_BV(OP_DOT2, true, 1); break;
+            case BV_DOT4: DQT_BV(OP_DOT4, false, 0); break;
+            case BV_DOT8: DQT_BV(OP_DOT8, false, 0); break;
+            default: DQT_BV(OP_MAD, false, 0); break;
+        }
+#undef DQT_BV
+        DQT_LAUNCH_CHECK("batched compute");
+    }
     return DQT_OK;
 }
 

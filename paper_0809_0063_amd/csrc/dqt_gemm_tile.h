@@ -83,27 +83,36 @@ struct TileSmem {
     static constexpr int words = (S > 1) ? S * TM * TN * 64 : 1;
 };
 
-// Words of TN consecutive columns held by one lane (one vector load).
+// Words of TN consecutive columns held by one lane (one vector load; clang
+// vector types, which load through any address space).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <int TN>
 struct LaneWords;
 template <>
 struct LaneWords<2> {
-    typedef uint2 T;
-    static __device__ __forceinline__ void get(const uint2& v, uint32_t (&o)[2]) {
+    typedef u32x2 T;
+    static __device__ __forceinline__ void get(const u32x2& v, uint32_t (&o)[2]) {
         o[0] = v.x;
         o[1] = v.y;
     }
 };
 template <>
 struct LaneWords<4> {
-    typedef uint4 T;
-    static __device__ __forceinline__ void get(const uint4& v, uint32_t (&o)[4]) {
+    typedef u32x4 T;
+    static __device__ __forceinline__ void get(const u32x4& v, uint32_t (&o)[4]) {
         o[0] = v.x;
         o[1] = v.y;
         o[2] = v.z;
         o[3] = v.w;
     }
 };
+
+// Address-space views of read-only device memory: constant (scalar loads for
+// wave-uniform addresses) and global.
+typedef __attribute__((address_space(4))) uint32_t ConstU32;
+template <class T>
+using GlobalT = __attribute__((address_space(1))) T;
 
 // k-groups per pipeline step: the A words of two steps (the one being
 // multiplied and the one being loaded) stay within 64 SGPRs.
@@ -151,8 +160,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
 
     const uint32_t kw0 = min(g.KW, wave * g.kw_split);
     const uint32_t kw1 = min(g.KW, kw0 + g.kw_split);
-    const uint32_t* __restrict__ pa = g.CA + ((size_t)rb * g.KW + kw0) * TM;
-    const V* __restrict__ pb = reinterpret_cast<const V*>(g.CB + ((size_t)cb * g.KW + kw0) * (64u * TN)) + lane;
+    // The packed operands are read-only while this kernel runs (they are written by
+    // the packing kernel before it): A through the constant address space, so
+    // that its wave-uniform words come in by scalar loads, and B through the
+    // global one, also when the pointers come from a descriptor in memory (the
+    // batched kernel) rather than from the kernel arguments.
+    const ConstU32* __restrict__ pa =
+        reinterpret_cast<const ConstU32*>(reinterpret_cast<uintptr_t>(g.CA + ((size_t)rb * g.KW + kw0) * TM));
+    const GlobalT<V>* __restrict__ pb = reinterpret_cast<const GlobalT<V>*>(
+        reinterpret_cast<uintptr_t>(reinterpret_cast<const V*>(g.CB + ((size_t)cb * g.KW + kw0) * (64u * TN)) + lane));
     const uint32_t mask = (1u << g.b) - 1u;
 
     uint32_t a0[U][TM], a1[U][TM];
@@ -212,7 +228,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
             uint32_t a[TM];
 #pragma unroll
             for (int i = 0; i < TM; ++i) a[i] = pa[i];
-            kgroup(a, pb[0], false);
+            const V bv = pb[0];
+            kgroup(a, bv, false);
             pa += TM;
             pb += 64;
         }

@@ -49,13 +49,14 @@ def _replay_seconds(g, replays: int) -> float:
 
 
 def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inputs.SEED_BATCH,
-            algo: Optional[int] = None, verify: Optional[Callable] = None) -> Dict[str, float]:
+            algo: Optional[int] = None, verify: Optional[Callable] = None, launch=None) -> Dict[str, float]:
     """The whole batch as one graph, replayed: once with packing (one packing launch + one persistent
     launch) and once on the resident packed operands (the persistent launch only, the packed copies
     left by the previous replay; section 7.1's reuse of compressed matrices).  `algo` forces one
     algorithm for every product (otherwise the tuner's per-bucket plan, or the library default).
     `verify(items, outputs)`, if given, receives the items and their output tensors after the
-    resident replays, whose outputs were cleared beforehand."""
+    resident replays, whose outputs were cleared beforehand.  `launch` (rows, k-split, columns)
+    overrides the tuner's launch shape."""
     dev = torch.device("cuda:0")
     items = inputs.batch_items(n_items, seed=seed)
     t0 = time.perf_counter()
@@ -77,7 +78,8 @@ def batched(n_items: int = 10000, replays: int = 3, tuner=None, seed: int = inpu
         a = d.get("algo", 0)
         algo_count[a] = algo_count.get(a, 0) + 1
     descs = D.make_descs(ops)
-    launch = tuner.launch if (tuner is not None and tuner.launch) else (16, 2, 4)
+    if launch is None:
+        launch = tuner.launch if (tuner is not None and tuner.launch) else (16, 2, 4)
     ws = torch.empty(D.fgemm_batched_workspace_size(descs, *launch), dtype=torch.uint8, device=dev)
     batch = D.Batch(descs, ws, *launch)
     batch.run()
@@ -209,9 +211,18 @@ def main(argv=None):
     ap.add_argument("--serving", action="store_true")
     ap.add_argument("--replays", type=int, default=3)
     ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--packed", action="store_true", help="batched: the packed middle product on every product")
+    ap.add_argument("--buckets", action="store_true", help="batched: every algorithm on each order bucket")
     args = ap.parse_args(argv)
     if args.batched:
-        print(json.dumps({"batched_10000_tuned": batched(10000, replays=args.replays, tuner=T.Tuner())}), flush=True)
+        if args.packed:
+            print(json.dumps({"batched_10000_packed_cmm": batched(10000, replays=args.replays, tuner=T.Tuner(),
+                                                                 algo=D.GEMM_CMM)}), flush=True)
+        else:
+            print(json.dumps({"batched_10000_tuned": batched(10000, replays=args.replays, tuner=T.Tuner())}),
+                  flush=True)
+    if args.buckets:
+        print(json.dumps({"batched_10000_by_bucket": batched_buckets(10000, tuner=T.Tuner())}), flush=True)
     if args.serving:
         print(json.dumps({"serving": serving(n_requests=args.requests, warmup=args.requests // 10)}), flush=True)
 

@@ -22,7 +22,7 @@ def test_tuner_buckets_and_tuned_batch(tmp_path):
     assert set(table) == {"3:0", "3:3", "3:5", "7:0", "7:3", "7:5"}
     for key, plan in table.items():
         assert plan.us > 0
-        assert plan.algo in (D.GEMM_CMM, D.GEMM_PLAIN, D.GEMM_DOT4)
+        assert plan.algo in (D.GEMM_CMM, D.GEMM_PLAIN, D.GEMM_DOT4, D.GEMM_DOT8)
     tu.save()
     again = T.Tuner(cache)
     assert again.table == tu.table

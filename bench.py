@@ -98,6 +98,14 @@ def hip_elapsed_ms(start, stop) -> float:
 _HIP = None
 
 
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    """Progress on stderr (the result line alone goes to stdout)."""
+    print(f"bench [{time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def timed_loop(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -404,6 +412,7 @@ def cpu_baselines(A, B, p, row0, fp_ops, inputs):
     v_all, reps, dt = rate(lambda: O.fgemm(A, B, p), fp_ops, 6.0)
     assert (O.fgemm(A[:1], B, p) == row0).all()
     v_one, _, _ = rate(lambda: O.fgemm(A[:64], B, p, threads=1), 2.0 * 64 * MNK * MNK, 2.0)
+    log("cpu: F_p product done")
     table["fgemm_1024_p3"] = {"unit": "Gop/s", "all_cores": round(v_all / 1e9, 3), "one_thread": round(v_one / 1e9, 3)}
     headline = {"value": round(v_all / 1e9, 3), "unit": "Gop/s", "cores": cores, "kind": "oracle",
                 "sample": f"the whole 1024^3 mod-3 product, {reps} times ({dt:.1f} s), reduce after every op",
@@ -422,16 +431,19 @@ def cpu_baselines(A, B, p, row0, fp_ops, inputs):
             "all_cores": round(rate(lambda: O.gf_mul(x, y, pp, P), 1 << 20, 1.0)[0], 1),
             "one_thread": round(rate(lambda: O.gf_mul(x, y, pp, P, threads=1), 1 << 20, 1.0)[0], 1)}
     # the first 300 products of the batched workload
-    items = inputs.batch_items(10000)[:300]
+    items = inputs.batch_items(10000)[:100]
     ops = [inputs.item_operands(it) + (it.p,) for it in items]
     work = sum(2.0 * it.n ** 3 for it in items)
+    work20 = sum(2.0 * it.n ** 3 for it in items[:20])
 
-    def batch(th):
-        for Ai, Bi, pi in ops:
+    def batch(th, count):
+        for Ai, Bi, pi in ops[:count]:
             O.fgemm(Ai, Bi, pi, threads=th)
-    table["batched_first300"] = {"unit": "Gop/s", "sample": "the first 300 of the 10,000 products",
-                                 "all_cores": round(rate(lambda: batch(0), work, 2.0)[0] / 1e9, 3),
-                                 "one_thread": round(rate(lambda: batch(1), work, 2.0)[0] / 1e9, 3)}
+    table["batched_sample"] = {"unit": "Gop/s",
+                               "sample": "all cores: the first 100 of the 10,000 products; one thread: the first 20",
+                               "all_cores": round(rate(lambda: batch(0, 100), work, 1.0)[0] / 1e9, 3),
+                               "one_thread": round(rate(lambda: batch(1, 20), work20, 1.0)[0] / 1e9, 3)}
+    log("cpu: batched sample done")
     # the first 100 polynomial-product payloads of the serving pool (its products are like the above)
     pool = [pl for pl in inputs.serve_pool() if pl.kind == "polymul"][:100]
     pops = [inputs.payload_operands(pl) + (pl.p,) for pl in pool]
@@ -480,13 +492,13 @@ def main():
             wcall.run()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps; the packed multiply kernel of every event_every-th step
-    # records its own start and end (a launch that records events costs the host more, so
-    # recording on every step would slow the steps it measures); at least 8 such samples
-    # (every other step at the default 20 steps)
-    event_every = max(1, min(8, args.steps // (MIN_EVENT_SAMPLES + 2)))
-    sampled = list(range(0, args.steps, event_every))
-    n_ev = len(sampled)
+    # timed region: K whole steps; the packed multiply kernel of the last n_ev steps records its
+    # own start and end (a launch that records events costs the host about twice as much as a
+    # plain one; the plain steps before them let the host run ahead of the device, so that the
+    # sampled steps do not leave the device idle): at least 8 samples, every eighth step's worth
+    # beyond 64 steps
+    n_ev = min(args.steps, max(MIN_EVENT_SAMPLES, args.steps // 8))
+    first_sampled = args.steps - n_ev
     ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
     ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
     t_start = torch.cuda.Event(enable_timing=True)
@@ -499,9 +511,9 @@ def main():
     t_start.record(stream)
     host_t0 = time.perf_counter()
     for i in range(args.steps):
-        if i % event_every == 0:
+        if i >= first_sampled:
             # pack + multiply in one call; the multiply kernel records its own start and end
-            call.run_timed(ev_a[i // event_every], ev_b[i // event_every])
+            call.run_timed(ev_a[i - first_sampled], ev_b[i - first_sampled])
         else:
             call.run()      # pack + multiply in one call
     t_end.record(stream)
@@ -551,17 +563,22 @@ def main():
         sections.discard("workloads")
     if args.no_cpu:
         sections.discard("cpu")
+    log(f"headline done: {step_s * 1e6:.2f} us per step")
     extra = {}
     reps_gemm = max(4, args.steps // 2)
     reps_big = max(2, args.steps // 20)
     if "gemm" in sections:
         extra.update(bench_gemm_comparators(D, torch, dA, dB, dC, p, row0, stream, reps_gemm))
+        log("gemm comparators done")
     if "polymul" in sections:
         extra.update(bench_polymul(D, inputs, torch, dev, reps_big, reps_gemm))
+        log("polymul done")
     if "fqt" in sections:
         extra.update(bench_fqt(D, inputs, torch, dev, reps_big))
+        log("fqt done")
     if "gf" in sections:
         extra.update(bench_gf(D, inputs, torch, dev, reps_big))
+        log("gf done")
     if "workloads" in sections:
         from paper_0809_0063_amd import workloads as W
         from paper_0809_0063_amd import tune as T
@@ -575,10 +592,12 @@ def main():
             except Exception as e:  # reported in the output line, not hidden
                 extra[name] = {"error": f"{type(e).__name__}: {e}"}
             torch.cuda.synchronize()
+            log(f"{name} done")
 
     cpu = None
     if "cpu" in sections:
         cpu, table = cpu_baselines(A, B, p, row0, fp_ops, inputs)
+        log("cpu baselines done")
         extra["cpu_oracle"] = table
 
     rec = {

@@ -94,7 +94,7 @@ struct MfmaArgs {
     const uint8_t* BT8;
     uint8_t* C;
     uint32_t m, n, ldc, k_pad;
-    uint32_t nrb;          // 32-row blocks
+    uint32_t nrb;          // 64-row blocks
     uint32_t ks;           // 64-k steps per wave
     uint32_t p, pmagic;
 };
@@ -164,6 +164,8 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(MfmaArgs g) {
                     acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
         }
     }
+    // with one wave on the k range, that wave holds the whole square and writes it alone
+    if (S == 1 && wave != 0) return;
     // the S partial squares meet in LDS; wave w finishes the 16 x 16 tiles t = w, w + 4, ...
     if (S > 1) {
         if (wave < (uint32_t)S) {

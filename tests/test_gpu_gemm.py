@@ -36,6 +36,21 @@ def test_fgemm_1024_p3(dqt):
         assert (got == (1024 * 4) % 3).all(), plan
 
 
+@pytest.mark.parametrize("p,m,n,k", [(3, 3000, 3000, 200), (7, 2900, 3100, 333), (127, 2945, 2817, 64),
+                                     (2, 2944, 2944, 1)])
+def test_fgemm_mfma_large_ragged(dqt, p, m, n, k):
+    """The INT8 matrix-core comparator on products of about 3000^2 outputs: uniform entries vs the
+    oracle with ragged m, n, k (k = 1 gives each workgroup one wave on k); and all entries p - 1."""
+    A, B = inputs.gemm_pair(m, n, k, p, seed=m + n + k)
+    plan = dqt.GemmPlan(algo=dqt.GEMM_MFMA)
+    got = to_host(dqt.fgemm(to_dev(A), to_dev(B), p, plan=plan))
+    assert (got == O.fgemm(A, B, p)).all()
+    W = inputs.worst_case((m, k), p)
+    V = inputs.worst_case((k, n), p)
+    got = to_host(dqt.fgemm(to_dev(W), to_dev(V), p, plan=plan))
+    assert (got == (k * (p - 1) ** 2) % p).all()
+
+
 @pytest.mark.parametrize("p", [2, 3, 5, 7, 11, 13])
 def test_fgemm_bound_edges_worst_case(dqt, p):
     """All entries p-1 at inner dimensions around the interval limits (digits at their maximum)."""

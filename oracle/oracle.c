@@ -25,10 +25,15 @@ static inline uint32_t add_mod(uint32_t x, uint32_t y, uint32_t p) { return (x +
 static inline uint32_t mul_mod(uint32_t x, uint32_t y, uint32_t p) { return (x * y) % p; }
 static inline uint32_t sub_mod(uint32_t x, uint32_t y, uint32_t p) { return (x + p - (y % p)) % p; }
 
+/* nthreads > 0: that many threads for this call; 0: the process default (the
+   OpenMP maximum seen at the first call), also after a call that asked for
+   fewer. */
 static void set_threads(int32_t nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    static int32_t default_threads = 0;
+    if (default_threads == 0) default_threads = omp_get_max_threads();
+    omp_set_num_threads(nthreads > 0 ? nthreads : default_threads);
 #else
     (void)nthreads;
 #endif

@@ -46,7 +46,7 @@ SECTIONS = ("gemm", "polymul", "fqt", "gf", "workloads", "cpu")
 TRAFFIC_SOURCES = ("paper_0809_0063_amd/csrc/dqt_gemm_tile.h", "paper_0809_0063_amd/csrc/dqt_device.h")
 TRAFFIC_KERNEL = ("paper_0809_0063_amd/csrc/dqt_gemm.hip", "__device__ __forceinline__ void tile_of(",
                   "// Pack A (rows")
-TRAFFIC = {"sha256": "d58efc1c7d24491d141d46e5f98f526f9cd62e5fba67af7238c9c7112fe98218", "bytes": 11725824}
+TRAFFIC = {"sha256": "01b41c8ea1fd684ea0767aec0e407df6c393fcb33d298144b477c7c635efdf83", "bytes": 11725824}
 
 
 def kernel_sources_sha256() -> str:
@@ -337,7 +337,7 @@ def bench_fqt_long(D, inputs, torch, dev):
         da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
         o = torch.empty((count, 2 * n - 1), dtype=torch.uint8, device=dev)
         row = {"count": count}
-        blocks = (0, 2, 3, 4) if n == 500 else (0,)
+        blocks = (0, 2, 3, 4) if n in (500, 1024, 2048) else (0,)
         for blk in blocks:
             s = timed_loop(lambda: D.polymul_fqt_u8(da, db, p, block=blk, out=o), 5, 2, torch)
             key = "fqt" if blk == 0 else f"fqt_block{blk}"

@@ -180,7 +180,7 @@ template <int B = 0, int W = 0>
 __host__ __device__ __forceinline__ uint32_t window_index(uint64_t U, uint32_t s, uint32_t j, const RedqArgs& a) {
     const uint32_t b = B ? B : a.b, w = W ? W : a.w;
     const uint32_t x = (uint32_t)(U >> (b * s));
-    if (B && W && gather3_by_multiply<(B ? B : 1), (W ? W : 1)>()) {
+    if constexpr (B && W && gather3_by_multiply<(B ? B : 1), (W ? W : 1)>()) {
         if (j == 3) {
             constexpr uint32_t wm = (1u << (W ? W : 1)) - 1u;
             constexpr uint32_t fm = wm | (wm << (B ? B : 1)) | (wm << (2 * (B ? B : 1)));

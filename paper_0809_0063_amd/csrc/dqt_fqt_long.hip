@@ -29,6 +29,8 @@
 
 #include <string.h>
 
+#include <cmath>
+
 #include "dqt_internal.h"
 
 namespace dqt {
@@ -39,6 +41,18 @@ constexpr int kLongR = 4;          // output blocks per FQT chunk
 constexpr int kPlainR = 8;         // coefficients per plain chunk
 constexpr int kPlainG = 8;         // terms per plain group
 constexpr uint32_t kPad = 16;      // zeros in LDS before b (>= R + G - 2 for both kernels)
+
+// LDS positions with one unused slot after every 2^S entries.  The lanes of a
+// wave read b windows R entries apart (and the plain kernel's a values 8
+// apart); without the gaps those strides put 4 lanes of every 16 on the same
+// banks, with them the lanes of a 16-lane phase hit distinct banks.  Every
+// window starts at an index = 1 mod 2^S (kPad - (G - 1) = 1 mod 4 for G = 4, 8;
+// 16 - 7 = 1 mod 8 for the plain kernel), so the offset of its entry x from
+// its start, x + ((1 + x) >> S), is a constant.
+template <int S>
+__host__ __device__ constexpr uint32_t gapped(uint32_t d) { return d + (d >> S); }
+template <int S>
+__device__ constexpr uint32_t gap_off(int x) { return (uint32_t)x + ((1u + (uint32_t)x) >> S); }
 
 struct LongArgs {
     uint32_t na, nb, nout;
@@ -86,7 +100,7 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
     extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
     uint16_t* tab = reinterpret_cast<uint16_t*>(lsm);
     double* ad = reinterpret_cast<double*>(lsm + g.lds_a);
-    double* bd = reinterpret_cast<double*>(lsm + g.lds_b);   // bd[kPad + i] = B_i
+    double* bd = reinterpret_cast<double*>(lsm + g.lds_b);   // bd[gapped<2>(kPad + i)] = B_i
     uint64_t* bnd = reinterpret_cast<uint64_t*>(lsm + g.lds_bnd);
     const RedqArgs& ra = g.ra;
     build_correction_table(tab, ra);
@@ -127,7 +141,7 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
                     if (c < g.nb) w |= (uint64_t)b[c] << (g.b * s);
                 }
             }
-            bd[k] = (double)w;
+            bd[gapped<2>(k)] = (double)w;
         }
         __syncthreads();
         uint64_t res[2][R];
@@ -157,9 +171,10 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
                         double av[G], wv[G + R - 1];
 #pragma unroll
                         for (int s = 0; s < G; ++s) av[s] = ad[ig + s];
-                        const double* wb = bd + (kPad + u0 - ig - (G - 1));   // wv[x] = B_{u0 - ig - (G-1) + x}
+                        // wv[x] = B_{u0 - ig - (G-1) + x}
+                        const double* wb = bd + gapped<2>(kPad + u0 - ig - (G - 1));
 #pragma unroll
-                        for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[x];
+                        for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<2>(x)];
 #pragma unroll
                         for (int s = 0; s < G; ++s)
 #pragma unroll
@@ -206,8 +221,8 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
                                                             uint32_t nb_tot) {
     constexpr int R = kPlainR, G = kPlainG;
     extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
-    uint32_t* a32 = reinterpret_cast<uint32_t*>(lsm);     // a32[i] = a_i, zeros up to na_pad
-    uint32_t* b32 = a32 + na_pad;                         // b32[kPad + k] = b_k, zeros around
+    uint32_t* a32 = reinterpret_cast<uint32_t*>(lsm);     // a32[gapped<3>(i)] = a_i, zeros up to na_pad
+    uint32_t* b32 = a32 + gapped<3>(na_pad);              // b32[gapped<3>(kPad + k)] = b_k, zeros around
     const uint32_t nout = na + nb - 1;
     const uint32_t C = (nout + R - 1) / R;
     const uint32_t pair = threadIdx.x;
@@ -217,9 +232,9 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
         __syncthreads();
         const uint8_t* a = A + t * na;
         const uint8_t* b = B + t * nb;
-        for (uint32_t i = threadIdx.x; i < na_pad; i += blockDim.x) a32[i] = i < na ? a[i] : 0u;
+        for (uint32_t i = threadIdx.x; i < na_pad; i += blockDim.x) a32[gapped<3>(i)] = i < na ? a[i] : 0u;
         for (uint32_t k = threadIdx.x; k < nb_tot; k += blockDim.x)
-            b32[k] = (k >= kPad && k - kPad < nb) ? b[k - kPad] : 0u;
+            b32[gapped<3>(k)] = (k >= kPad && k - kPad < nb) ? b[k - kPad] : 0u;
         __syncthreads();
         uint8_t* o = OUT + t * nout;
 #pragma unroll
@@ -235,10 +250,11 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
             for (uint32_t ig = ilo & ~(uint32_t)(G - 1); ig <= ihi; ig += G) {
                 uint32_t av[G], wv[G + R - 1];
 #pragma unroll
-                for (int s = 0; s < G; ++s) av[s] = a32[ig + s];
-                const uint32_t* wb = b32 + (kPad + j0 - ig - (G - 1));   // wv[x] = b_{j0 - ig - (G-1) + x}
+                for (int s = 0; s < G; ++s) av[s] = a32[gapped<3>(ig) + s];   // ig = 0 mod 8
+                // wv[x] = b_{j0 - ig - (G-1) + x}
+                const uint32_t* wb = b32 + gapped<3>(kPad + j0 - ig - (G - 1));
 #pragma unroll
-                for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[x];
+                for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<3>(x)];
 #pragma unroll
                 for (int s = 0; s < G; ++s)
 #pragma unroll
@@ -253,11 +269,15 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 
 }  // namespace
 
-// Block size, q, L and the group width G of a long product: the smallest cost
-// (block products plus reductions, the two counts of section 5.3's model) over
-// block sizes 2..4 (the 2 BS - 1 residues of a block stay within the eight
-// byte lanes of one word) with q = 2^b, (2 BS - 1) b <= 51 and at least four
-// block products per reduction.  p <= 127 (two residues add within a byte lane).
+// Block size, q, L and the group width G of a long product: the smallest
+// estimated cost over block sizes 2..4 (the 2 BS - 1 residues of a block stay
+// within the eight byte lanes of one word) with q = 2^b, (2 BS - 1) b <= 51 and
+// at least four block products per reduction.  p <= 127 (two residues add
+// within a byte lane).  The estimate counts what section 5.3's model counts,
+// block products and reductions, the way the kernel executes them: per wave,
+// two phases of about Na / G term groups (G R FMAs and the LDS reads of G + R + G - 1
+// words each) and, per phase, a REDQ_{2BS-1} of each of the R sums at every
+// L-th term and at the end (about 40 + 12 (2 BS - 1) instructions each).
 dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out,
                          uint32_t* L_out, uint32_t* G_out) {
     if (p > 127) return DQT_E_UNSUPPORTED;
@@ -272,12 +292,13 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
         const uint32_t G = nq >= 8 ? 8 : 4;
         const uint32_t L = (uint32_t)(nq / G) * G;
         const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs, NW = Na + Nb - 1;
-        double reds = 0;
-        for (uint32_t u = 0; u < NW; ++u) {
-            const uint32_t i0 = u >= Nb ? u - (Nb - 1) : 0, i1 = u < Na ? u : Na - 1;
-            reds += (double)(i1 / L - i0 / L + 1);
-        }
-        const double cost = (double)Na * Nb + reds * (16.0 + 3.0 * (2 * bs - 1));
+        const uint32_t C = (NW + 1 + kLongR - 1) / kLongR;
+        const double waves = (double)(((C + 1) / 2 + 63) / 64);
+        const double span = (double)(Na < Nb ? Na : Nb);
+        const double groups = 2.0 * ((span + G - 1) / G);
+        const double per_group = (double)(kLongR * G) + (2.0 * G + kLongR - 1) / 2.0 + 8.0;
+        const double reductions = 2.0 * (std::floor((span - 1) / L) + 1.0) * kLongR;
+        const double cost = waves * (groups * per_group + reductions * (40.0 + 12.0 * (2 * bs - 1)));
         if (cost < best) {
             best = cost;
             best_bs = bs;
@@ -323,16 +344,21 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     g.nb_tot = kPad + g.Nb + kPad;
     g.lds_a = 4096 * 2;                        // the correction table
     g.lds_b = g.lds_a + g.na_pad * 8;
-    g.lds_bnd = g.lds_b + ((g.nb_tot * 8 + 15) & ~15u);
+    g.lds_bnd = g.lds_b + ((gapped<2>(g.nb_tot) * 8 + 15) & ~15u);
     const size_t smem = g.lds_bnd + (size_t)g.C * 8;
     const unsigned threads = ((g.C + 1) / 2 + 63) / 64 * 64;   // one chunk pair per thread
     if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
     const unsigned grid = stream_grid(count, 1, groups_per_cu(smem, threads));
-    // F_3 in blocks of three at q = 2^10 (the case of section 5.3's example) has a
-    // compile-time q and residue width; every other case the run-time form
-    if (bs == 3 && G == 8 && b == 10 && g.ra.w == 2) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<3, 8, 10, 2>), dim3(grid), dim3(threads), smem, s, A, B,
-                           out, count, g);
+    // F_3 (residues of 2 bits) in blocks of three at q = 2^10 or of two at q = 2^17 (the
+    // block sizes the cost picks over F_3) have a compile-time q and residue width;
+    // every other case the run-time form
+    if (g.ra.w == 2 && G == 8 && ((bs == 3 && b == 10) || (bs == 2 && b == 17))) {
+        if (bs == 3)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<3, 8, 10, 2>), dim3(grid), dim3(threads), smem, s, A,
+                               B, out, count, g);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<2, 8, 17, 2>), dim3(grid), dim3(threads), smem, s, A,
+                               B, out, count, g);
         DQT_LAUNCH_CHECK("dqt_polymul_fqt_u8 (long)");
         return DQT_OK;
     }
@@ -362,7 +388,7 @@ dqt_status plain_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, u
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
     const uint32_t na_pad = (na + kPlainG - 1) / kPlainG * kPlainG;
     const uint32_t nb_tot = kPad + nb + kPad;
-    const size_t smem = ((size_t)na_pad + nb_tot) * 4;
+    const size_t smem = ((size_t)gapped<3>(na_pad) + gapped<3>(nb_tot)) * 4;
     const uint32_t C = (na + nb - 1 + kPlainR - 1) / kPlainR;
     const unsigned threads = ((C + 1) / 2 + 63) / 64 * 64;
     if (threads > 512) return DQT_E_UNSUPPORTED;

@@ -101,11 +101,21 @@ struct MfmaArgs {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// Square of C of workgroup `bid`: consecutive workgroups go to the eight XCDs in
+// turn, so each XCD first gets a contiguous range of the order below; in that
+// order the squares come in groups of 8 row blocks, column by column, so that
+// the workgroups running together on an XCD share 8 row blocks of A and 8
+// column blocks of B (within its L2) rather than all of A.
 __device__ __forceinline__ void mfma_tile_of(uint32_t bid, uint32_t nblk, uint32_t nrb, uint32_t* rb, uint32_t* cb) {
     uint32_t logical = bid;
     if ((nblk & 7u) == 0) logical = (bid & 7u) * (nblk >> 3) + (bid >> 3);
-    *rb = logical % nrb;
-    *cb = logical / nrb;
+    constexpr uint32_t GR = 8;
+    const uint32_t ncb = nblk / nrb;
+    const uint32_t group = logical / (GR * ncb), first = group * GR;
+    const uint32_t rows = min(GR, nrb - first);
+    const uint32_t in = logical - group * GR * ncb;
+    *rb = first + in % rows;
+    *cb = in / rows;
 }
 
 // T x T tiles of 16 x 16 per wave (a 16 T square of C); the S waves of a

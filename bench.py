@@ -171,6 +171,7 @@ def bench_gemm_comparators(D, torch, dA, dB, dC, p, row0, stream, reps):
                                 "kernel_us": round(kus, 3), "kernel_fp_top_s": round(2 * macs / kus / 1e6, 1),
                                 "bound": bound, "work_per_launch": work, "work_unit": unit[bound],
                                 "kernel_frac": round(work / (kus * 1e-6) / peak[bound], 4)}
+    out.update(bench_library_int8(torch, p, n, dA.cpu().numpy(), dB.cpu().numpy()))
     out.update(bench_gemm_4096(D, torch, p, stream, peak, unit))
     return out
 
@@ -202,6 +203,42 @@ def bench_gemm_4096(D, torch, p, stream, peak, unit):
                                     "bound": bound, "work_per_launch": work, "work_unit": unit[bound],
                                     "kernel_frac": round(work / (kus * 1e-6) / peak[bound], 4)}
         del c2
+    out.update(bench_library_int8(torch, p, 4096, A, B))
+    return out
+
+
+def bench_library_int8(torch, p, n, A, B):
+    """The vendor library's int8 matrix product (torch._int_mm: int8 x int8 -> int32 on the matrix cores)
+    followed by one reduction mod p per output: the machine's best dense routine as a plain comparator
+    (section 7.3 compares with the machine's dgemm).  Not part of the library; timed with events around
+    each call on the current stream."""
+    import numpy as np
+    out = {}
+    try:
+        dA = torch.from_numpy(A.astype(np.int8)).to("cuda")
+        dB = torch.from_numpy(B.astype(np.int8)).to("cuda")
+        row0 = (A[:1].astype(np.int64) @ B.astype(np.int64)) % p
+        for _ in range(3):
+            C32 = torch._int_mm(dA, dB)
+        torch.cuda.synchronize()
+        reps = 10
+        e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in e:
+            a.record()
+            C32 = torch._int_mm(dA, dB)
+            b.record()
+        torch.cuda.synchronize()
+        mm_s = sum(a.elapsed_time(b) for a, b in e) / reps / 1e3
+        C = (C32 % p).to(torch.uint8)
+        s = timed_loop(lambda: (torch._int_mm(dA, dB) % p).to(torch.uint8), reps, 2, torch)
+        assert (C[:1].cpu().numpy() == row0).all()
+        ops = 2.0 * n ** 3
+        out[f"fgemm{n}_library_int8_mm"] = {"matmul_us": round(mm_s * 1e6, 1), "us_per_step_with_mod_p": round(s * 1e6, 1),
+                                           "matmul_top_s": round(ops / mm_s / 1e12, 1),
+                                           "matmul_frac": round(ops / mm_s / PEAK_INT8_MFMA, 4),
+                                           "bound": "mfma_int8"}
+    except Exception as ex:  # reported, not hidden
+        out[f"fgemm{n}_library_int8_mm"] = {"error": f"{type(ex).__name__}: {ex}"}
     return out
 
 

@@ -365,7 +365,8 @@ def fqt_long_model(p, n, bs):
 
 def bench_fqt_long(D, inputs, torch, dev):
     """Long products over F_3 (n = 128 .. 4096 coefficients, n = 500 the example of section 5.3): FQT by
-    blocks against the plain per-coefficient product, same batch, same launch shape."""
+    blocks, Karatsuba levels over FQT base products (from n = 500), and the plain per-coefficient
+    product, same batch."""
     out = {}
     p = 3
     for n in (128, 256, 500, 1024, 2048, 4096):
@@ -380,6 +381,13 @@ def bench_fqt_long(D, inputs, torch, dev):
             key = "fqt" if blk == 0 else f"fqt_block{blk}"
             row[key] = {"products_s": round(count / s, 1), "us_per_call": round(s * 1e6, 1),
                         "coeff_products_s": round(count * n * n / s, 1)}
+        if n >= 500:
+            # Karatsuba levels over F_p with FQT base products (workspace allocated once, outside the loop)
+            for lv in ((1, 2) if n < 4096 else (1, 2, 3)):
+                work = torch.empty(D.kara_long_workspace(count, n, lv), dtype=torch.uint8, device=dev)
+                s = timed_loop(lambda: D.polymul_kara_long_u8(da, db, p, levels=lv, out=o, work=work), 5, 2, torch)
+                row[f"kara{lv}"] = {"products_s": round(count / s, 1), "us_per_call": round(s * 1e6, 1)}
+                del work
         s = timed_loop(lambda: D.polymul_plain_u8(da, db, p, out=o), 5, 2, torch)
         row["plain"] = {"products_s": round(count / s, 1), "us_per_call": round(s * 1e6, 1),
                         "lane_op_frac": round(count * n * n / s / PEAK_LANE_OPS, 4)}

@@ -257,16 +257,37 @@ dqt_status dqt_gf_mul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t 
  * d_a: uint8 [count][na], d_b: uint8 [count][nb], d_out: uint8 [count][na+nb-1].
  * block = d+1 coefficients per word (0 = choose).  na, nb <= 4096.  Up to 64
  * coefficients each, a thread computes a product and every output block holds
- * all its block products in one word.  Above that (p <= 127, block 2..4), one
- * wave computes a product: the block words of both operands sit in LDS, each
- * output block is summed n_q block products at a time (q > n_q (d+1)(p-1)^2,
- * eq:bounds, the largest q with (2d+1) log2 q <= 53 and 32-bit operand
- * words), with one REDQ_{2d+1} per such sum and the sums' residues added mod
- * p; the block size minimizes block products plus reductions (section 5.3).
- * DQT_E_UNSUPPORTED for p > 127 there.
+ * all its block products in one word.  Above that, and at up to 64 where no
+ * block size keeps such a sum in one word and block = 0 (p <= 127, block
+ * 2..4), one workgroup computes a product: the block words of both operands sit in LDS,
+ * each output block is summed n_q block products at a time
+ * (q > n_q (d+1)(p-1)^2, eq:bounds, with (2d+1) log2 q <= 51), with one
+ * REDQ_{2d+1} per such sum and the sums' residues added mod p; the block size
+ * minimizes section 5.3's counts (block products, reductions) weighted by
+ * their cost in the kernel.  DQT_E_UNSUPPORTED for p > 127 there.
  */
 dqt_status dqt_polymul_fqt_u8(const uint8_t *d_a, uint32_t na, const uint8_t *d_b, uint32_t nb, uint64_t count,
                               uint32_t p, uint32_t block, uint8_t *d_out, void *stream);
+
+/*
+ * Long products by Karatsuba's recursion over F_p with the packed FQT at its
+ * base (section 5.3, figure fig:pmkara): `levels` (1..3) levels each turn a
+ * product of two n-coefficient polynomials into three products of
+ * h = ceil(n/2) coefficients (a0 b0, a1 b1, (a0 + a1)(b0 + b1), the sums
+ * reduced mod p), the 3^levels base products run through dqt_polymul_fqt_u8,
+ * and the results are combined back, a b = P0 + x^h (P1 - P0 - P2) + x^2h P2
+ * mod p.  d_a, d_b: uint8 [count][n]; d_out: uint8 [count][2n-1]; same bytes
+ * as dqt_polymul_fqt_u8.  d_work: device workspace of at least
+ * dqt_polymul_kara_long_workspace(count, n, levels) bytes (the split operands
+ * and the products of every level), owned by the caller, not retained.
+ * DQT_E_INVALID for levels outside 1..3, n outside 2..4096 or a base size
+ * below 2; DQT_E_WORKSPACE for a short workspace; the base products' own
+ * errors (DQT_E_UNSUPPORTED for p > 127 when they exceed 64 coefficients).
+ * dqt_polymul_kara_long_workspace returns 0 for invalid arguments.
+ */
+size_t dqt_polymul_kara_long_workspace(uint64_t count, uint32_t n, uint32_t levels);
+dqt_status dqt_polymul_kara_long_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t n, uint32_t p,
+                                    uint32_t levels, uint8_t *d_out, void *d_work, size_t work_bytes, void *stream);
 
 /*
  * dqt_polymul_fqt_u8 with the block products by Karatsuba's recursion

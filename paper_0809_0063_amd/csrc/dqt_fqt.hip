@@ -276,8 +276,8 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
 extern "C" dqt_status dqt_polymul_fqt_u8(const uint8_t* d_a, uint32_t na, const uint8_t* d_b, uint32_t nb,
                                          uint64_t count, uint32_t p, uint32_t block, uint8_t* d_out, void* stream) {
     if (p < 2 || p > 255 || na < 1 || nb < 1 || na > 4096 || nb > 4096) return DQT_E_INVALID;
-    if (na > 64 || nb > 64) {
-        // long products: one wave per product, chunked packed sums (dqt_fqt_long.hip)
+    // long products: one workgroup per product, chunked packed sums (dqt_fqt_long.hip)
+    auto chunked = [&]() -> dqt_status {
         DQT_TRY(fqt_long_enqueue(d_a, na, d_b, nb, count, p, block, d_out, nullptr, true));
         if (count == 0) return DQT_OK;
         if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
@@ -285,11 +285,18 @@ extern "C" dqt_status dqt_polymul_fqt_u8(const uint8_t* d_a, uint32_t na, const 
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
         DQT_TRY(debug_gate(s, p, {{d_a, count, na, na}, {d_b, count, nb, nb}}));
         return fqt_long_enqueue(d_a, na, d_b, nb, count, p, block, d_out, s, false);
-    }
+    };
+    if (na > 64 || nb > 64) return chunked();
     uint32_t best_bs = 0, best_b = 0;
-    DQT_TRY(fqt_choose(p, na, nb, block, &best_bs, &best_b));
     RedqArgs ra;
-    DQT_TRY(make_redq_args(p, best_b, 2 * best_bs - 1, (2 * best_bs - 1) * best_b, &ra));
+    dqt_status st = fqt_choose(p, na, nb, block, &best_bs, &best_b);
+    if (st == DQT_OK) st = make_redq_args(p, best_b, 2 * best_bs - 1, (2 * best_bs - 1) * best_b, &ra);
+    if (st != DQT_OK) {
+        // no block size keeps a whole output block's sum in one word (larger p, longer
+        // operands): with the size left to the library, the chunked sums take it (p <= 127)
+        if (block == 0 && p <= 127) return chunked();
+        return st;
+    }
     if (count == 0) return DQT_OK;
     if (!d_a || !d_b || !d_out) return DQT_E_INVALID;
     DQT_TRY(ensure_device_ready());

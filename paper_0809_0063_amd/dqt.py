@@ -118,6 +118,7 @@ def _load():
         "dqt_gf_dot_u8": [V, V, U64, U32, U32, U32, V, V, V],
         "dqt_polymul_fqt_u8": [V, U32, V, U32, U64, U32, U32, V, V],
         "dqt_polymul_fqt_kara_u8": [V, U32, V, U32, U64, U32, U32, U32, V, V],
+        "dqt_polymul_kara_long_u8": [V, V, U64, U32, U32, U32, V, V, SZ, V],
         "dqt_check_input_u8": [V, U64, U32, V, V],
         "dqt_fgemm": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V],
@@ -149,6 +150,9 @@ def _load():
     if hasattr(lib, "dqt_fgemm_packed_bytes"):
         lib.dqt_fgemm_packed_bytes.argtypes = [U32, U64, U64, I, ctypes.POINTER(_GemmPlan)]
         lib.dqt_fgemm_packed_bytes.restype = SZ
+    if hasattr(lib, "dqt_polymul_kara_long_workspace"):
+        lib.dqt_polymul_kara_long_workspace.argtypes = [U64, U32, U32]
+        lib.dqt_polymul_kara_long_workspace.restype = SZ
     if hasattr(lib, "dqt_fgemm_noalloc_max_bytes"):
         lib.dqt_fgemm_noalloc_max_bytes.argtypes = []
         lib.dqt_fgemm_noalloc_max_bytes.restype = SZ
@@ -362,6 +366,30 @@ def polymul_fqt_kara_u8(a: torch.Tensor, b: torch.Tensor, p: int, levels: int = 
     _check(_load().dqt_polymul_fqt_kara_u8(_dev(a, "a", torch.uint8), na, _dev(b, "b", torch.uint8), nb, n, p, block,
                                            levels, _dev(out, "out", torch.uint8), _stream(stream)),
            "dqt_polymul_fqt_kara_u8")
+    return out
+
+
+def kara_long_workspace(count: int, n: int, levels: int) -> int:
+    """Workspace bytes dqt_polymul_kara_long_u8 needs (0 for invalid arguments)."""
+    return int(_load().dqt_polymul_kara_long_workspace(count, n, levels))
+
+
+def polymul_kara_long_u8(a: torch.Tensor, b: torch.Tensor, p: int, levels: int = 1,
+                         out: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None, stream=None):
+    """Products of equal-length polynomials by `levels` Karatsuba levels over F_p with FQT base products."""
+    _u8_pair(a, b)
+    count, n = a.shape
+    if b.shape[1] != n:
+        raise ValueError(f"polymul_kara_long_u8 takes equal lengths, got {n} and {b.shape[1]}")
+    if out is None:
+        out = torch.empty((count, 2 * n - 1), dtype=torch.uint8, device=a.device)
+    need = kara_long_workspace(count, n, levels)
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=a.device)
+    _check(_load().dqt_polymul_kara_long_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), count, n, p,
+                                            levels, _dev(out, "out", torch.uint8), _dev(work, "work", torch.uint8),
+                                            work.numel(), _stream(stream)),
+           "dqt_polymul_kara_long_u8")
     return out
 
 

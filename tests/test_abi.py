@@ -106,6 +106,19 @@ def test_fgemm_workspace_sizes(D):
     assert D.fgemm_workspace_size(3, 64, 64, 64, D.GemmPlan(algo=D.GEMM_CMM, interval=8192)) == 0
 
 
+def test_kara_long_workspace_sizes(D):
+    """Per level: the 3^l operand pairs of h_l coefficients and their 3^l products of 2 h_l - 1
+    coefficients, each region rounded up to 256 bytes; 0 where the arguments are refused."""
+    r = lambda x: (x + 255) // 256 * 256
+    assert D.kara_long_workspace(10, 100, 1) == r(2 * 30 * 50) + r(30 * 99)
+    assert D.kara_long_workspace(10, 100, 2) == r(2 * 30 * 50) + r(30 * 99) + r(2 * 90 * 25) + r(90 * 49)
+    assert D.kara_long_workspace(1, 4096, 3) == r(2 * 3 * 2048) + r(3 * 4095) + r(2 * 9 * 1024) + r(9 * 2047) + \
+        r(2 * 27 * 512) + r(27 * 1023)
+    assert D.kara_long_workspace(0, 100, 1) == 0
+    for count, n, levels in ((10, 100, 0), (10, 100, 4), (10, 4097, 1), (10, 2, 1), (10, 7, 3)):
+        assert D.kara_long_workspace(count, n, levels) == 0
+
+
 def test_packed_side_sizes_add_up_to_the_workspace(D):
     """Host logic of the resident-operand calls: the two packed sides are the two halves of the workspace."""
     for p in (2, 3, 7, 13):

@@ -292,8 +292,13 @@ def test_fqt_karatsuba_products(dqt, p):
                 try:
                     got = to_host(dqt.polymul_fqt_kara_u8(da, db, p, levels=levels, block=block))
                 except dqt.DQTError as e:
-                    # refused exactly when the schoolbook FQT refuses (same block and q choice)
+                    # refused exactly when the one-word-per-block FQT refuses (same block and q
+                    # choice); with the block size left open the FQT entry then takes the
+                    # chunked sums instead
                     assert e.status in (dqt.DQT_E_BOUND, dqt.DQT_E_UNSUPPORTED), e
+                    if block == 0:
+                        assert (to_host(dqt.polymul_fqt_u8(da, db, p)) == ref).all(), (p, na, nb)
+                        continue
                     with pytest.raises(dqt.DQTError) as e2:
                         dqt.polymul_fqt_u8(da, db, p, block=block)
                     assert e2.value.status == e.status
@@ -343,7 +348,7 @@ def test_gf_dot_many_long(dqt):
 
 @pytest.mark.parametrize("p", [2, 3, 5, 7, 13, 31, 127])
 def test_fqt_long_products(dqt, p):
-    """Products of more than 64 coefficients (one wave per product, chunked packed sums) and the plain
+    """Products of more than 64 coefficients (one workgroup per product, chunked packed sums) and the plain
     comparator at the same lengths, up to 4096 coefficients, the all-(p-1) case included."""
     g = np.random.default_rng(7000 + p)
     for na, nb, count in [(65, 65, 300), (100, 200, 100), (256, 255, 64), (500, 500, 40), (1000, 1024, 9),
@@ -374,6 +379,95 @@ def test_fqt_long_block_sizes_and_limits(dqt):
     with pytest.raises(dqt.DQTError) as e:
         dqt.polymul_fqt_u8(to_dev(big), to_dev(big), 3)
     assert e.value.status == dqt.DQT_E_INVALID
+
+
+def _kara_base(n, levels):
+    h = n
+    for _ in range(levels):
+        h = (h + 1) // 2
+    return h
+
+
+@pytest.mark.parametrize("p", [7, 31, 127])
+def test_fqt_short_operands_by_chunked_sums(dqt, p):
+    """Up to 64 coefficients, where no block size keeps a whole output block's sum in one word
+    (larger p), the FQT entry with the block size left open computes by chunked sums; an explicit
+    block size is still refused there."""
+    g = np.random.default_rng(7200 + p)
+    lengths = [(na, nb) for na in (1, 2, 5, 16, 25, 33, 48, 64) for nb in (1, 3, 16, 33, 64)]
+    chunked = 0
+    for na, nb in lengths:
+        a = g.integers(0, p, size=(37, na), dtype=np.uint8)
+        b = g.integers(0, p, size=(37, nb), dtype=np.uint8)
+        a[0] = p - 1
+        b[0] = p - 1
+        ref = O.polymul(a, b, p)
+        assert (to_host(dqt.polymul_fqt_u8(to_dev(a), to_dev(b), p)) == ref).all(), (p, na, nb)
+        refused = 0
+        for block in range(2, 7):
+            try:
+                got = to_host(dqt.polymul_fqt_u8(to_dev(a), to_dev(b), p, block=block))
+            except dqt.DQTError as e:
+                assert e.status in (dqt.DQT_E_BOUND, dqt.DQT_E_UNSUPPORTED)
+                refused += 1
+                continue
+            assert (got == ref).all(), (p, na, nb, block)
+        chunked += refused == 5
+    assert chunked >= 1
+
+
+@pytest.mark.parametrize("p", [2, 3, 7, 31, 127, 251])
+def test_kara_long_products(dqt, p):
+    """Karatsuba levels over F_p on top of the FQT (1..3 levels, odd lengths so every level pads a
+    half, up to 4096 coefficients), the all-(p-1) operands in the first row; over 127 only base
+    sizes the FQT takes (one word per output block) are computed, the others refused."""
+    g = np.random.default_rng(7100 + p)
+    for n, count, levels in [(3, 50, 1), (9, 100, 3), (65, 300, 1), (100, 50, 2), (128, 64, 3), (255, 20, 1),
+                             (500, 20, 2), (1001, 9, 1), (2048, 4, 2), (4096, 3, 1), (4095, 2, 3)]:
+        a = g.integers(0, p, size=(count, n), dtype=np.uint8)
+        b = g.integers(0, p, size=(count, n), dtype=np.uint8)
+        a[0] = p - 1
+        b[0] = p - 1
+        h = _kara_base(n, levels)
+        try:   # the base size the FQT takes (an empty batch checks the parameters only)
+            z = to_dev(np.zeros((0, h), dtype=np.uint8))
+            dqt.polymul_fqt_u8(z, z, p)
+        except dqt.DQTError as e0:
+            assert p > 127, (p, n, levels)
+            with pytest.raises(dqt.DQTError) as e:
+                dqt.polymul_kara_long_u8(to_dev(a), to_dev(b), p, levels=levels)
+            assert e.value.status == e0.status == dqt.DQT_E_UNSUPPORTED
+            continue
+        ref = O.polymul(a, b, p)
+        got = to_host(dqt.polymul_kara_long_u8(to_dev(a), to_dev(b), p, levels=levels))
+        assert (got == ref).all(), (p, n, levels)
+
+
+def test_kara_long_limits_and_workspace(dqt):
+    """Levels outside 1..3, lengths outside 2..4096, a base below 2 coefficients and a short
+    workspace are refused; an empty batch is a no-op; the result does not depend on what the
+    workspace held before."""
+    import torch
+    p, n, count = 5, 300, 11
+    a, b = inputs.polymul_pairs(count, n, p, seed=5300)
+    da, db = to_dev(a), to_dev(b)
+    for levels, nn in ((0, 300), (4, 300), (1, 4097), (1, 2), (3, 7)):
+        assert dqt.kara_long_workspace(count, nn, levels) == 0
+        x = torch.zeros((count, nn), dtype=torch.uint8, device=da.device)
+        with pytest.raises(dqt.DQTError) as e:
+            dqt.polymul_kara_long_u8(x, x, p, levels=levels)
+        assert e.value.status == dqt.DQT_E_INVALID, (levels, nn)
+    need = dqt.kara_long_workspace(count, n, 2)
+    short = torch.empty(need - 1, dtype=torch.uint8, device=da.device)
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.polymul_kara_long_u8(da, db, p, levels=2, work=short)
+    assert e.value.status == dqt.DQT_E_WORKSPACE
+    work = torch.full((need,), 255, dtype=torch.uint8, device=da.device)
+    ref = O.polymul(a, b, p)
+    assert (to_host(dqt.polymul_kara_long_u8(da, db, p, levels=2, work=work)) == ref).all()
+    assert (to_host(dqt.polymul_kara_long_u8(da, db, p, levels=2, work=work)) == ref).all()
+    z = torch.zeros((0, n), dtype=torch.uint8, device=da.device)
+    assert dqt.polymul_kara_long_u8(z, z, p, levels=1).shape == (0, 2 * n - 1)
 
 
 def test_check_input_and_debug_mode(dqt):

@@ -55,16 +55,64 @@ __device__ __forceinline__ uint64_t add_mod_bytes(uint64_t a, uint64_t b, uint32
     return s - (uint64_t)p * ge;
 }
 
-// G lanes share one dot product: lane g of a group takes the pairs l = g,
-// g + G, g + 2G, ..., so the G lanes of a group read G consecutive records of
-// k bytes (whole runs of the operands, G k bytes per step), each lane keeps
-// its own packed sums of n_q products and its own field result, and the G
-// results are added in the field across the group by shuffles.  G = 1 is one
-// thread per dot product (short dot products).
-template <int K, int G>
-__global__ __launch_bounds__(256) void k_gf_dot(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+// Eight consecutive records (8 K bytes) of an operand at any byte address:
+// K unaligned 8-byte loads (global memory takes them), or, for a chunk cut by
+// the end of the dot product, byte loads of its first `bytes` bytes only.
+template <int K>
+__device__ __forceinline__ void load_chunk(const uint8_t* src, uint32_t bytes, uint64_t (&w)[K]) {
+    if (bytes == 8 * K) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) __builtin_memcpy(&w[i], src + 8 * i, 8);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) w[i] = 0;
+        for (uint32_t x = 0; x < bytes; ++x) w[x >> 3] |= (uint64_t)src[x] << (8 * (x & 7));
+    }
+}
+
+// Record r of a chunk (bytes r K .. r K + K - 1) spread into fields of B bits:
+// sum_i e_i 2^(B i), below 2^32 for every K here (B (K-1) + 7 <= 28).
+template <int K, int B, int R>
+__device__ __forceinline__ uint32_t record_word(const uint64_t (&w)[K]) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int byte = R * K + i;
+        const uint64_t word = w[byte >> 3];
+        const uint32_t half = (byte & 7) < 4 ? (uint32_t)word : (uint32_t)(word >> 32);
+        v |= ((half >> (8 * (byte & 3))) & 0xFFu) << (B * i);
+    }
+    return v;
+}
+
+// The K residues mod p of a running sum held in 16-bit lanes (RE: coefficients
+// 0, 2, 4; RO: 1, 3, 5), as K bytes.
+template <int K>
+__device__ __forceinline__ uint64_t fold16(uint64_t RE, uint64_t RO, uint32_t p, uint32_t pmagic) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const uint32_t v = (uint32_t)(((i & 1) ? RO : RE) >> (16 * (i >> 1))) & 0xFFFFu;
+        r |= (uint64_t)mod_small(v, p, pmagic) << (8 * i);
+    }
+    return r;
+}
+
+// G lanes share one dot product.  The n pairs are taken in chunks of eight
+// consecutive records; lane g of a group takes chunks g, g + G, ..., so the G
+// lanes of a group read G consecutive runs of 8 K bytes of each operand (8-byte
+// loads, coalesced across the group).  Each lane keeps its own packed sums of
+// n_q products (q = 2^B, B = floor(53 / (2K - 1)), so a record packs into one
+// 32-bit word and a product of two is one 32 x 32 -> 64-bit multiply-add).
+// After each REDQ the two table values (each coefficient below p) are added
+// without reduction into 16-bit lanes, folded mod p every fold_at reductions
+// and at the end; the G lane results are added in the field across the group
+// by shuffles.  NQ1: n_q = 1 (every product is reduced on its own).
+template <int K, int G, bool NQ1>
+__global__ __launch_bounds__(256) void k_gf_dot(const uint8_t* __restrict__ A, const uint8_t* __restrict__ Bop,
                                                 uint8_t* __restrict__ OUT, uint64_t count, uint32_t n, uint32_t nq,
                                                 RedqArgs ra, GfArgs ga) {
+    constexpr int B = 53 / (2 * K - 1);
     extern __shared__ uint64_t gfd_smem[];
     const uint32_t tn = 1u << (K * ra.w);
     uint64_t* tl = gfd_smem;
@@ -72,43 +120,83 @@ __global__ __launch_bounds__(256) void k_gf_dot(const uint8_t* __restrict__ A, c
     build_gf_tables_dot<K>(tl, th, ra, ga);
     __syncthreads();
     const uint64_t ones = 0x0101010101010101ull >> (8 * (8 - K));
+    constexpr uint64_t kEven = 0x00FF00FF00FF00FFull;
     const uint32_t wm = (1u << ra.w) - 1u;
+    const uint32_t fold_at = 65535u / (2u * (ra.p - 1u));   // table sums per 16-bit lane before a fold
     const uint32_t g = threadIdx.x % G;
     const uint64_t groups = (uint64_t)gridDim.x * (256 / G);
+    const uint32_t nch = (n + 7) / 8;
     // every lane of a group runs the same number of outer iterations (the
     // shuffles below need the whole wave), so the loop runs to the padded count
     const uint64_t padded = (count + groups - 1) / groups * groups;
     for (uint64_t t = (uint64_t)blockIdx.x * (256 / G) + threadIdx.x / G; t < padded; t += groups) {
         const bool live = t < count;
         const uint8_t* x = A + (live ? t : 0) * (uint64_t)n * K;
-        const uint8_t* y = B + (live ? t : 0) * (uint64_t)n * K;
-        uint64_t R = 0;
-        // this lane's pairs: l = g + G j; n_q of them per packed word
-        const uint32_t mine = live && g < n ? (n - g + G - 1) / G : 0;
-        for (uint32_t j0 = 0; j0 < mine; j0 += nq) {
-            const uint32_t j1 = min(mine, j0 + nq);
-            uint64_t acc = 0;
-            for (uint32_t j = j0; j < j1; ++j) {
-                const uint64_t l = (uint64_t)g + (uint64_t)G * j;
-                uint64_t xa = 0, yb = 0;
-#pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    xa |= (uint64_t)x[l * K + i] << (ra.b * i);
-                    yb |= (uint64_t)y[l * K + i] << (ra.b * i);
-                }
-                acc += xa * yb;
-            }
+        const uint8_t* y = Bop + (live ? t : 0) * (uint64_t)n * K;
+        uint64_t R = 0, RE = 0, RO = 0, acc = 0;
+        uint32_t cnt = 0, nred = 0;
+        auto reduce = [&]() {
             const uint64_t U = redq_compress(acc, ra);
             const uint32_t xl = (uint32_t)U;
-            const uint64_t xh64 = U >> (ra.b * (K - 1));
+            const uint64_t xh64 = U >> (B * (K - 1));
+            const uint32_t xh = (uint32_t)xh64;   // B K <= 32 bits hold the top K fields
             uint32_t il = 0, ih = 0;
 #pragma unroll
             for (int jj = 0; jj < K; ++jj) {
-                il |= ((xl >> (ra.b * jj)) & wm) << (ra.w * jj);
-                ih |= ((uint32_t)(xh64 >> (ra.b * jj)) & wm) << (ra.w * jj);
+                il |= __builtin_amdgcn_ubfe(xl, B * jj, ra.w) << (ra.w * jj);
+                ih |= __builtin_amdgcn_ubfe(xh, B * jj, ra.w) << (ra.w * jj);
             }
-            R = add_mod_bytes(R, add_mod_bytes(th[ih], tl[il], ra.p, ones), ra.p, ones);
+            const uint64_t sum = th[ih] + tl[il];   // bytes below 2p - 1
+            RE += sum & kEven;
+            RO += (sum >> 8) & kEven;
+            acc = 0;
+            cnt = 0;
+            if (++nred == fold_at) {
+                R = add_mod_bytes(R, fold16<K>(RE, RO, ra.p, ra.pmagic), ra.p, ones);
+                RE = RO = 0;
+                nred = 0;
+            }
+        };
+        auto pair = [&](uint32_t xa, uint32_t yb) {
+            acc += (uint64_t)xa * yb;
+            if (NQ1) reduce();
+            else if (++cnt == nq) reduce();
+        };
+        // whole chunks of eight records
+        const uint32_t nfull = n / 8;
+        for (uint32_t c = live ? g : nfull; c < nfull; c += G) {
+            uint64_t wa[K], wb[K];
+            load_chunk<K>(x + (uint64_t)c * 8 * K, 8 * K, wa);
+            load_chunk<K>(y + (uint64_t)c * 8 * K, 8 * K, wb);
+            pair(record_word<K, B, 0>(wa), record_word<K, B, 0>(wb));
+            pair(record_word<K, B, 1>(wa), record_word<K, B, 1>(wb));
+            pair(record_word<K, B, 2>(wa), record_word<K, B, 2>(wb));
+            pair(record_word<K, B, 3>(wa), record_word<K, B, 3>(wb));
+            pair(record_word<K, B, 4>(wa), record_word<K, B, 4>(wb));
+            pair(record_word<K, B, 5>(wa), record_word<K, B, 5>(wb));
+            pair(record_word<K, B, 6>(wa), record_word<K, B, 6>(wb));
+            pair(record_word<K, B, 7>(wa), record_word<K, B, 7>(wb));
         }
+        // the last n mod 8 records (chunk nfull), on the lane that chunk falls to
+        const uint32_t nrec = n - 8 * nfull;
+        if (live && nrec && nfull % G == g) {
+            uint64_t wa[K], wb[K];
+            load_chunk<K>(x + (uint64_t)nfull * 8 * K, nrec * K, wa);
+            load_chunk<K>(y + (uint64_t)nfull * 8 * K, nrec * K, wb);
+            for (uint32_t r = 0; r < nrec; ++r) {
+                // record r from the chunk, shifted down by r K bytes
+                uint32_t xa = 0, yb = 0;
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const uint32_t byte = r * K + i;
+                    xa |= (uint32_t)((wa[byte >> 3] >> (8 * (byte & 7))) & 0xFFu) << (B * i);
+                    yb |= (uint32_t)((wb[byte >> 3] >> (8 * (byte & 7))) & 0xFFu) << (B * i);
+                }
+                pair(xa, yb);
+            }
+        }
+        if (!NQ1 && cnt) reduce();
+        R = add_mod_bytes(R, fold16<K>(RE, RO, ra.p, ra.pmagic), ra.p, ones);
 #pragma unroll
         for (int off = G / 2; off >= 1; off /= 2) {
             const uint32_t lo = __shfl_xor((uint32_t)R, off, G);
@@ -126,18 +214,23 @@ template <int K, int G>
 static void launch_gf_dot_g(const uint8_t* A, const uint8_t* B, uint8_t* out, uint64_t count, uint32_t n,
                             uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
     const size_t smem = 2ull * (1ull << (K * ra.w)) * sizeof(uint64_t);
-    const uint64_t threads = count * G;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_dot<K, G>), dim3(stream_grid(threads, 256, 4)), dim3(256), smem, s, A, B,
-                       out, count, n, nq, ra, ga);
+    const unsigned grid = stream_grid(count * G, 256, 4);
+    if (nq == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_dot<K, G, true>), dim3(grid), dim3(256), smem, s, A, B, out, count, n,
+                           nq, ra, ga);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_dot<K, G, false>), dim3(grid), dim3(256), smem, s, A, B, out, count,
+                           n, nq, ra, ga);
 }
 
-// Lanes per dot product: one wave for long ones, fewer for short ones.
+// Lanes per dot product: about one per chunk of eight records, at most a wave.
 template <int K>
 static dqt_status launch_gf_dot(const uint8_t* A, const uint8_t* B, uint8_t* out, uint64_t count, uint32_t n,
                                 uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
-    if (n >= 256) launch_gf_dot_g<K, 64>(A, B, out, count, n, nq, ra, ga, s);
-    else if (n >= 32) launch_gf_dot_g<K, 16>(A, B, out, count, n, nq, ra, ga, s);
-    else if (n >= 8) launch_gf_dot_g<K, 4>(A, B, out, count, n, nq, ra, ga, s);
+    const uint32_t nch = (n + 7) / 8;
+    if (nch > 32) launch_gf_dot_g<K, 64>(A, B, out, count, n, nq, ra, ga, s);
+    else if (nch > 8) launch_gf_dot_g<K, 16>(A, B, out, count, n, nq, ra, ga, s);
+    else if (nch > 2) launch_gf_dot_g<K, 4>(A, B, out, count, n, nq, ra, ga, s);
     else launch_gf_dot_g<K, 1>(A, B, out, count, n, nq, ra, ga, s);
     DQT_LAUNCH_CHECK("dqt_gf_dot_u8");
     return DQT_OK;
@@ -155,8 +248,8 @@ extern "C" dqt_status dqt_gf_dot_u8(const uint8_t* d_a, const uint8_t* d_b, uint
     const uint32_t w = residue_bits(p);
     if (k * w > 12) return DQT_E_UNSUPPORTED;
     // the largest q with (2k-1) log2 q <= 53 (and each residue field within a digit)
-    uint32_t b = 53 / (2 * k - 1);
-    if (b > 32) b = 32;
+    // (the kernels take b as the compile-time 53 / (2k - 1): 17, 10, 7, 5, 4 for k = 2..6)
+    const uint32_t b = 53 / (2 * k - 1);
     if (b < w) return DQT_E_UNSUPPORTED;
     const uint64_t per = (uint64_t)k * (p - 1) * (p - 1);
     const uint64_t nq64 = per ? (((1ull << b) - 1) / per) : n;

@@ -334,6 +334,37 @@ def test_gf_dot_products(dqt, p, k, n):
     assert (to_host(dqt.gf_dot_u8(to_dev(w), to_dev(w), p, P)) == O.gf_dot(w, w, p, P)).all()
 
 
+@pytest.mark.parametrize("p,k", [(3, 5), (7, 3), (2, 6), (13, 2)])
+def test_gf_dot_unaligned_operands(dqt, p, k):
+    """Operands starting at every byte offset (the kernel reads runs of eight records with 8-byte
+    loads at any address), lengths that end inside a run of eight, and results against the oracle;
+    the bytes around the output stay untouched."""
+    import torch
+    P = inputs.irreducible(p, k)
+    g = np.random.default_rng(900 + p * 10 + k)
+    dev = device()
+    for n in (1, 7, 8, 9, 37, 64, 128, 301):
+        count = 129
+        a = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
+        b = g.integers(0, p, size=(count, n, k), dtype=np.uint8)
+        a[0] = p - 1
+        b[0] = p - 1
+        ref = O.gf_dot(a, b, p, P)
+        for off in (1, 3, 6):
+            bufa = torch.zeros(a.size + 16, dtype=torch.uint8, device=dev)
+            bufb = torch.zeros(b.size + 16, dtype=torch.uint8, device=dev)
+            va = bufa[off:off + a.size].view(count, n, k)
+            vb = bufb[off + 1:off + 1 + b.size].view(count, n, k)
+            va.copy_(torch.from_numpy(a))
+            vb.copy_(torch.from_numpy(b))
+            out = torch.full((count * k + 8,), 0xAB, dtype=torch.uint8, device=dev)
+            vo = out[off:off + count * k].view(count, k)
+            dqt.gf_dot_u8(va, vb, p, P, out=vo)
+            h = out.cpu().numpy()
+            assert (h[off:off + count * k].reshape(count, k) == ref).all(), (p, k, n, off)
+            assert (h[:off] == 0xAB).all() and (h[off + count * k:] == 0xAB).all()
+
+
 def test_gf_dot_many_long(dqt):
     """More long dot products than one pass of the grid holds (a wave per dot product, grid-stride),
     and a count that leaves the last pass partly empty."""

@@ -421,8 +421,11 @@ def bench_gf(D, inputs, torch, dev, reps_big):
     od = torch.empty((cnt, k), dtype=torch.uint8, device=dev)
     s = timed_loop(lambda: D.gf_dot_u8(xa, xb, pp, P, out=od), max(4, reps_big), 2, torch)
     byts = cnt * (2 * ln * k + k)
+    # q = 2^floor(53/9) = 2^5 admits n_q = floor(31 / (5 * 2^2)) = 1 product per packed word, so every
+    # product has its own REDQ and two table lookups: the kernel is bound by instruction issue
     out["gf_3^5_dot_n128"] = {"dot_s": round(cnt / s, 1), "GB_s": round(byts / s / 1e9, 1),
-                              "hbm_frac": round(byts / s / PEAK_HBM, 4), "us_per_call": round(s * 1e6, 1)}
+                              "hbm_frac": round(byts / s / PEAK_HBM, 4), "us_per_call": round(s * 1e6, 1),
+                              "n_q": 1, "bound": "valu"}
     return out
 
 

@@ -13,12 +13,14 @@
 // the first BS-1 coefficients of block u+1 and are added mod p when the
 // coefficients are written.
 //
-// Work split (both kernels): one workgroup per product, a thread owns R
-// consecutive outputs (output blocks for the FQT, coefficients for the plain
-// one), a "chunk".  The number of terms of a chunk rises and falls along the
-// product, so chunk c is paired with chunk C-1-c on the same thread: every
-// thread then has about the same number of terms, and one pair per thread
-// covers products of up to 4096 coefficients with at most 512 threads.  The
+// Work split (both kernels): a thread owns R consecutive outputs (output
+// blocks for the FQT, coefficients for the plain one), a "chunk".  The number
+// of terms of a chunk rises and falls along the product, so chunk c is paired
+// with chunk C-1-c on the same thread: every thread then has about the same
+// number of terms, and one pair per thread covers products of up to 4096
+// coefficients with at most 512 threads.  A product of more than 32 chunk
+// pairs has a workgroup to itself; shorter ones share a wave, each with a
+// power-of-two group of lanes and its own slot of LDS.  The
 // terms are taken G at a time: G values of a and the G+R-1 values of b that
 // meet them are read from LDS once and used G R times.  The operands sit in LDS
 // between zeros, so groups that overlap the ends of the operands need no test.
@@ -62,6 +64,7 @@ struct LongArgs {
     uint32_t C;                     // chunks of R output blocks (block NW, all zero, included)
     uint32_t na_pad, nb_tot;        // doubles of A (a multiple of G) and of B with its zeros
     uint32_t lds_a, lds_b, lds_bnd; // byte offsets in LDS: A words, B words, last residues of each chunk
+    uint32_t tpp, ppw, pp_bytes;    // threads per product, products per workgroup, LDS bytes per product
     RedqArgs ra;
 };
 
@@ -99,14 +102,18 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
     constexpr int R = kLongR;
     extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
     uint16_t* tab = reinterpret_cast<uint16_t*>(lsm);
-    double* ad = reinterpret_cast<double*>(lsm + g.lds_a);
-    double* bd = reinterpret_cast<double*>(lsm + g.lds_b);   // bd[gapped<2>(kPad + i)] = B_i
-    uint64_t* bnd = reinterpret_cast<uint64_t*>(lsm + g.lds_bnd);
+    // products with few chunk pairs share a wave: tpp threads (a power of two) per product,
+    // each product with its own LDS slot
+    const uint32_t sub = threadIdx.x / g.tpp;
+    const uint32_t pair = threadIdx.x - sub * g.tpp;
+    uint8_t* slot = lsm + g.lds_a + sub * g.pp_bytes;
+    double* ad = reinterpret_cast<double*>(slot);
+    double* bd = reinterpret_cast<double*>(slot + (g.lds_b - g.lds_a));   // bd[gapped<2>(kPad + i)] = B_i
+    uint64_t* bnd = reinterpret_cast<uint64_t*>(slot + (g.lds_bnd - g.lds_a));
     const RedqArgs& ra = g.ra;
     build_correction_table(tab, ra);
-    const uint32_t pair = threadIdx.x;
     const uint32_t cs[2] = {pair, g.C - 1 - pair};
-    const int nc = pair < (g.C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
+    const int nc_all = pair < (g.C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
     // one REDQ_{2BS-1} of each of the R sums; their residues added to res
     auto reduce = [&](double (&W)[R], uint64_t (&res)[R]) {
 #pragma unroll
@@ -118,11 +125,14 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
             W[r] = 0.0;
         }
     };
-    for (uint64_t t = blockIdx.x; t < count; t += gridDim.x) {
-        __syncthreads();   // the table is built / the previous product has left LDS
-        const uint8_t* a = A + t * g.na;
-        const uint8_t* b = B + t * g.nb;
-        for (uint32_t i = threadIdx.x; i < g.na_pad; i += blockDim.x) {
+    for (uint64_t t0 = (uint64_t)blockIdx.x * g.ppw; t0 < count; t0 += (uint64_t)gridDim.x * g.ppw) {
+        const uint64_t t = t0 + sub;
+        const bool live = t < count;
+        const int nc = live ? nc_all : 0;
+        __syncthreads();   // the table is built / the previous products have left LDS
+        const uint8_t* a = A + (live ? t : 0) * g.na;
+        const uint8_t* b = B + (live ? t : 0) * g.nb;
+        for (uint32_t i = live ? pair : g.na_pad; i < g.na_pad; i += g.tpp) {
             uint64_t w = 0;
 #pragma unroll
             for (int s = 0; s < BS; ++s) {
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
             }
             ad[i] = (double)w;
         }
-        for (uint32_t k = threadIdx.x; k < g.nb_tot; k += blockDim.x) {
+        for (uint32_t k = live ? pair : g.nb_tot; k < g.nb_tot; k += g.tpp) {
             uint64_t w = 0;
             const uint32_t i = k - kPad;
             if (k >= kPad && i < g.Nb) {
@@ -218,22 +228,28 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
 __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                             uint8_t* __restrict__ OUT, uint64_t count, uint32_t na,
                                                             uint32_t nb, uint32_t p, uint32_t pmagic, uint32_t na_pad,
-                                                            uint32_t nb_tot) {
+                                                            uint32_t nb_tot, uint32_t tpp, uint32_t ppw,
+                                                            uint32_t slot_words) {
     constexpr int R = kPlainR, G = kPlainG;
     extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
-    uint32_t* a32 = reinterpret_cast<uint32_t*>(lsm);     // a32[gapped<3>(i)] = a_i, zeros up to na_pad
+    // as in the FQT kernel: tpp threads and one LDS slot per product, ppw products per workgroup
+    const uint32_t sub = threadIdx.x / tpp;
+    const uint32_t pair = threadIdx.x - sub * tpp;
+    uint32_t* a32 = reinterpret_cast<uint32_t*>(lsm) + sub * slot_words;   // a32[gapped<3>(i)] = a_i, zeros up to na_pad
     uint32_t* b32 = a32 + gapped<3>(na_pad);              // b32[gapped<3>(kPad + k)] = b_k, zeros around
     const uint32_t nout = na + nb - 1;
     const uint32_t C = (nout + R - 1) / R;
-    const uint32_t pair = threadIdx.x;
     const uint32_t cs[2] = {pair, C - 1 - pair};
-    const int nc = pair < (C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
-    for (uint64_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const int nc_all = pair < (C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * ppw; t0 < count; t0 += (uint64_t)gridDim.x * ppw) {
+        const uint64_t t = t0 + sub;
+        const bool live = t < count;
+        const int nc = live ? nc_all : 0;
         __syncthreads();
-        const uint8_t* a = A + t * na;
-        const uint8_t* b = B + t * nb;
-        for (uint32_t i = threadIdx.x; i < na_pad; i += blockDim.x) a32[gapped<3>(i)] = i < na ? a[i] : 0u;
-        for (uint32_t k = threadIdx.x; k < nb_tot; k += blockDim.x)
+        const uint8_t* a = A + (live ? t : 0) * na;
+        const uint8_t* b = B + (live ? t : 0) * nb;
+        for (uint32_t i = live ? pair : na_pad; i < na_pad; i += tpp) a32[gapped<3>(i)] = i < na ? a[i] : 0u;
+        for (uint32_t k = live ? pair : nb_tot; k < nb_tot; k += tpp)
             b32[gapped<3>(k)] = (k >= kPad && k - kPad < nb) ? b[k - kPad] : 0u;
         __syncthreads();
         uint8_t* o = OUT + t * nout;
@@ -274,7 +290,8 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 // within the eight byte lanes of one word) with q = 2^b, (2 BS - 1) b <= 51 and
 // at least four block products per reduction.  p <= 127 (two residues add
 // within a byte lane).  The estimate counts what section 5.3's model counts,
-// block products and reductions, the way the kernel executes them: per wave,
+// block products and reductions, the way the kernel executes them: per wave
+// (or per share of a wave, for products of up to 32 chunk pairs),
 // two phases of about Na / G term groups (G R FMAs and the LDS reads of G + R + G - 1
 // words each) and, per phase, a REDQ_{2BS-1} of each of the R sums at every
 // L-th term and at the end (about 40 + 12 (2 BS - 1) instructions each).
@@ -293,7 +310,11 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
         const uint32_t L = (uint32_t)(nq / G) * G;
         const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs, NW = Na + Nb - 1;
         const uint32_t C = (NW + 1 + kLongR - 1) / kLongR;
-        const double waves = (double)(((C + 1) / 2 + 63) / 64);
+        // waves per product: up to 32 chunk pairs share a wave (a power-of-two group of lanes)
+        const uint32_t pairs = (C + 1) / 2;
+        uint32_t lanes = 1;
+        while (lanes < pairs) lanes *= 2;
+        const double waves = pairs <= 32 ? lanes / 64.0 : (double)((pairs + 63) / 64);
         const double span = (double)(Na < Nb ? Na : Nb);
         const double groups = 2.0 * ((span + G - 1) / G);
         const double per_group = (double)(kLongR * G) + (2.0 * G + kLongR - 1) / 2.0 + 8.0;
@@ -345,10 +366,27 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     g.lds_a = 4096 * 2;                        // the correction table
     g.lds_b = g.lds_a + g.na_pad * 8;
     g.lds_bnd = g.lds_b + ((gapped<2>(g.nb_tot) * 8 + 15) & ~15u);
-    const size_t smem = g.lds_bnd + (size_t)g.C * 8;
-    const unsigned threads = ((g.C + 1) / 2 + 63) / 64 * 64;   // one chunk pair per thread
+    const uint32_t pairs = (g.C + 1) / 2;   // one chunk pair per thread
+    unsigned threads;
+    g.pp_bytes = (uint32_t)((g.lds_bnd - g.lds_a + (size_t)g.C * 8 + 15) & ~(size_t)15);
+    if (pairs <= 32) {
+        // several products per wave of 64 threads
+        g.tpp = 1;
+        while (g.tpp < pairs) g.tpp *= 2;
+        g.ppw = 64 / g.tpp;
+        while (g.ppw > 1 && g.lds_a + (size_t)g.ppw * g.pp_bytes > 65536) {
+            g.ppw /= 2;
+            g.tpp *= 2;
+        }
+        threads = 64;
+    } else {
+        threads = (pairs + 63) / 64 * 64;
+        g.tpp = threads;
+        g.ppw = 1;
+    }
+    const size_t smem = g.lds_a + (size_t)g.ppw * g.pp_bytes;
     if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
-    const unsigned grid = stream_grid(count, 1, groups_per_cu(smem, threads));
+    const unsigned grid = stream_grid((count + g.ppw - 1) / g.ppw, 1, groups_per_cu(smem, threads));
     // F_3 (residues of 2 bits) in blocks of three at q = 2^10 or of two at q = 2^17 (the
     // block sizes the cost picks over F_3) have a compile-time q and residue width;
     // every other case the run-time form
@@ -388,13 +426,30 @@ dqt_status plain_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, u
     const uint32_t pmagic = (uint32_t)(((1ull << 32) + p - 1) / p);
     const uint32_t na_pad = (na + kPlainG - 1) / kPlainG * kPlainG;
     const uint32_t nb_tot = kPad + nb + kPad;
-    const size_t smem = ((size_t)gapped<3>(na_pad) + gapped<3>(nb_tot)) * 4;
+    const uint32_t slot_words = (gapped<3>(na_pad) + gapped<3>(nb_tot) + 3) & ~3u;
     const uint32_t C = (na + nb - 1 + kPlainR - 1) / kPlainR;
-    const unsigned threads = ((C + 1) / 2 + 63) / 64 * 64;
-    if (threads > 512) return DQT_E_UNSUPPORTED;
-    const unsigned grid = stream_grid(count, 1, groups_per_cu(smem, threads));
+    const uint32_t pairs = (C + 1) / 2;
+    unsigned threads;
+    uint32_t tpp, ppw;
+    if (pairs <= 32) {
+        tpp = 1;
+        while (tpp < pairs) tpp *= 2;
+        ppw = 64 / tpp;
+        while (ppw > 1 && (size_t)ppw * slot_words * 4 > 65536) {
+            ppw /= 2;
+            tpp *= 2;
+        }
+        threads = 64;
+    } else {
+        threads = (pairs + 63) / 64 * 64;
+        tpp = threads;
+        ppw = 1;
+    }
+    const size_t smem = (size_t)ppw * slot_words * 4;
+    if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
+    const unsigned grid = stream_grid((count + ppw - 1) / ppw, 1, groups_per_cu(smem, threads));
     hipLaunchKernelGGL(k_polymul_plain_long, dim3(grid), dim3(threads), smem, s, A, B, out, count, na, nb, p, pmagic,
-                       na_pad, nb_tot);
+                       na_pad, nb_tot, tpp, ppw, slot_words);
     DQT_LAUNCH_CHECK("dqt_polymul_plain_u8 (long)");
     return DQT_OK;
 }

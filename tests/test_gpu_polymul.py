@@ -395,6 +395,33 @@ def test_fqt_long_products(dqt, p):
             assert (to_host(dqt.polymul_plain_u8(to_dev(a), to_dev(b), p)) == ref).all(), (p, na)
 
 
+@pytest.mark.parametrize("p", [3, 7, 127])
+def test_long_products_several_per_workgroup(dqt, p):
+    """Short long products share a wave (a power-of-two group of lanes and an LDS slot per product):
+    batch sizes that leave the last workgroup partly empty, results between sentinel bytes, for the
+    FQT and the plain comparator."""
+    import torch
+    dev = device()
+    g = np.random.default_rng(7300 + p)
+    for na, nb in [(65, 65), (70, 100), (129, 128), (200, 250), (300, 300), (65, 7)]:
+        for count in (1, 3, 65, 130):
+            a = g.integers(0, p, size=(count, na), dtype=np.uint8)
+            b = g.integers(0, p, size=(count, nb), dtype=np.uint8)
+            a[0] = p - 1
+            b[0] = p - 1
+            ref = O.polymul(a, b, p)
+            nout = na + nb - 1
+            runs = [lambda o: dqt.polymul_fqt_u8(to_dev(a), to_dev(b), p, out=o)]
+            if na == nb:
+                runs.append(lambda o: dqt.polymul_plain_u8(to_dev(a), to_dev(b), p, out=o))
+            for run in runs:
+                buf = torch.full((count * nout + 64,), 0xCD, dtype=torch.uint8, device=dev)
+                run(buf[32:32 + count * nout].view(count, nout))
+                h = buf.cpu().numpy()
+                assert (h[32:32 + count * nout].reshape(count, nout) == ref).all(), (p, na, nb, count)
+                assert (h[:32] == 0xCD).all() and (h[32 + count * nout:] == 0xCD).all(), (p, na, nb, count)
+
+
 def test_fqt_long_block_sizes_and_limits(dqt):
     """Every block size of the long path gives the oracle's bytes; the limits are refused."""
     p, na, nb, count = 3, 777, 500, 20

@@ -73,7 +73,14 @@ __device__ __forceinline__ uint32_t mac(uint32_t a, uint32_t b, uint32_t acc) {
     } else if (OP == OP_DOT8) {
         return __builtin_amdgcn_udot8(a, b, acc, false);
     } else {
-        return __umul24(a, b) + acc;
+        // one v_mad_u32_u24 per multiply-add, written out: from __umul24(a, b) + acc
+        // the compiler reassociates a k-group's chain into separate products and
+        // three-way adds, which takes more registers than the tile has (spills)
+        // and 1.5 instructions per multiply-add.  a is an A word, wave-uniform,
+        // held in an SGPR (scalar loads).
+        uint32_t r;
+        asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(acc));
+        return r;
     }
 }
 
@@ -330,32 +337,44 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, uint32_t rb, uint32
         }
     } else {
         // REDQ_e: the dot products (each below the epilogue's q) of up to e
-        // outputs of this lane packed into one word, one REDQ for all of them.
+        // consecutive outputs of one row of this lane packed into one word, one
+        // REDQ for all of them; the row's TN residues are stored as one word, as
+        // in the REDC path.  (Fields are taken by shifts, not from indexed arrays,
+        // which would live in scratch memory.)
         const RedqArgs& ra = ge.ra;
-        uint64_t word = 0;
-        uint32_t nin = 0;
-        uint32_t rows[8], cols[8];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
             if (S > 1 && (uint32_t)i % S != wave) continue;
+            const uint32_t row = row0 + i;
+            uint32_t v = 0;
+            uint64_t word = 0;
+            uint32_t nin = 0;
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 word |= (uint64_t)acc[i][j] << (ra.b * nin);
-                rows[nin] = row0 + i;
-                cols[nin] = col0 + j;
                 ++nin;
-                const bool last = (i + S > TM - 1) && j == TN - 1;
-                if (nin == ge.epi_e || last) {
+                if (nin == ge.epi_e || j == TN - 1) {
                     const uint64_t U2 = redq_compress(word, ra);
+                    const uint32_t first = (uint32_t)j + 1u - nin;
                     for (uint32_t t = 0; t < nin; ++t) {
                         const uint32_t ut = field(U2, t, ra);
                         uint32_t mu = ut;
                         if (ra.c && t + 1 < nin) mu = correct_arith(ut, field(U2, t + 1, ra), ra);
-                        if (rows[t] < ge.m && cols[t] < ge.n) ge.C[(size_t)rows[t] * ge.ldc + cols[t]] = (uint8_t)mu;
+                        v |= mu << (8 * (first + t));
                     }
                     word = 0;
                     nin = 0;
                 }
+            }
+            if (row >= ge.m) continue;
+            uint8_t* out = ge.C + (size_t)row * ge.ldc + col0;
+            if (col0 + TN <= ge.n && ((uintptr_t)out & (TN - 1)) == 0) {
+                if (TN == 4) *reinterpret_cast<uint32_t*>(out) = v;
+                else *reinterpret_cast<uint16_t*>(out) = (uint16_t)v;
+            } else {
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    if (col0 + j < ge.n) out[j] = (uint8_t)(v >> (8 * j));
             }
         }
     }

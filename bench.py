@@ -46,7 +46,7 @@ SECTIONS = ("gemm", "polymul", "fqt", "gf", "workloads", "cpu")
 TRAFFIC_SOURCES = ("paper_0809_0063_amd/csrc/dqt_gemm_tile.h", "paper_0809_0063_amd/csrc/dqt_device.h")
 TRAFFIC_KERNEL = ("paper_0809_0063_amd/csrc/dqt_gemm.hip", "__device__ __forceinline__ void tile_of(",
                   "// Pack A (rows")
-TRAFFIC = {"sha256": "01b41c8ea1fd684ea0767aec0e407df6c393fcb33d298144b477c7c635efdf83", "bytes": 11725824}
+TRAFFIC = {"sha256": "754243f159153713bf45f7bbef26d13e548facff839856d52514705724516662", "bytes": 11725786}
 
 
 def kernel_sources_sha256() -> str:

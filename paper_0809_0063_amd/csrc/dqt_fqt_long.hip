@@ -39,7 +39,6 @@ namespace dqt {
 
 namespace {
 
-constexpr int kLongR = 4;          // output blocks per FQT chunk
 constexpr int kPlainR = 8;         // coefficients per plain chunk
 constexpr int kPlainG = 8;         // terms per plain group
 constexpr uint32_t kPad = 16;      // zeros in LDS before b (>= R + G - 2 for both kernels)
@@ -55,6 +54,10 @@ template <int S>
 __host__ __device__ constexpr uint32_t gapped(uint32_t d) { return d + (d >> S); }
 template <int S>
 __device__ constexpr uint32_t gap_off(int x) { return (uint32_t)x + ((1u + (uint32_t)x) >> S); }
+__host__ __device__ constexpr uint32_t gapped_n(int s, uint32_t d) { return d + (d >> s); }
+// Gap spacing of the FQT's B rows for chunks of R blocks and term groups of G:
+// windows start at kPad - (G - 1) + (multiple of R, G), 1 mod 8 only when G = 8.
+__host__ __device__ constexpr int long_gap_shift(int r, int g) { return r == 8 && g == 8 ? 3 : 2; }
 
 struct LongArgs {
     uint32_t na, nb, nout;
@@ -95,11 +98,14 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 
 // QB, QW: log2 q and the residue width as compile-time constants (0 = from the
 // run-time arguments).
-template <int BS, int G, int QB, int QW>
+template <int BS, int G, int QB, int QW, int R>
 __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                           uint8_t* __restrict__ OUT, uint64_t count, LongArgs g) {
     constexpr int NR = 2 * BS - 1;
-    constexpr int R = kLongR;
+    static_assert(R + G - 2 <= (int)kPad, "the B windows stay inside the zeros around B");
+    // B rows: a gap every 2^GS words, GS = log2 R for R = 4, and for R = 8 when G = 8 (the
+    // windows then start at 1 mod 8); lanes read windows R words apart
+    constexpr int GS = long_gap_shift(R, G);
     extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
     uint16_t* tab = reinterpret_cast<uint16_t*>(lsm);
     // products with few chunk pairs share a wave: tpp threads (a power of two) per product,
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
     const uint32_t pair = threadIdx.x - sub * g.tpp;
     uint8_t* slot = lsm + g.lds_a + sub * g.pp_bytes;
     double* ad = reinterpret_cast<double*>(slot);
-    double* bd = reinterpret_cast<double*>(slot + (g.lds_b - g.lds_a));   // bd[gapped<2>(kPad + i)] = B_i
+    double* bd = reinterpret_cast<double*>(slot + (g.lds_b - g.lds_a));   // bd[gapped<GS>(kPad + i)] = B_i
     uint64_t* bnd = reinterpret_cast<uint64_t*>(slot + (g.lds_bnd - g.lds_a));
     const RedqArgs& ra = g.ra;
     build_correction_table(tab, ra);
@@ -151,7 +157,7 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
                     if (c < g.nb) w |= (uint64_t)b[c] << (g.b * s);
                 }
             }
-            bd[gapped<2>(k)] = (double)w;
+            bd[gapped<GS>(k)] = (double)w;
         }
         __syncthreads();
         uint64_t res[2][R];
@@ -182,9 +188,9 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
 #pragma unroll
                         for (int s = 0; s < G; ++s) av[s] = ad[ig + s];
                         // wv[x] = B_{u0 - ig - (G-1) + x}
-                        const double* wb = bd + gapped<2>(kPad + u0 - ig - (G - 1));
+                        const double* wb = bd + gapped<GS>(kPad + u0 - ig - (G - 1));
 #pragma unroll
-                        for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<2>(x)];
+                        for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<GS>(x)];
 #pragma unroll
                         for (int s = 0; s < G; ++s)
 #pragma unroll
@@ -285,18 +291,32 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 
 }  // namespace
 
-// Block size, q, L and the group width G of a long product: the smallest
-// estimated cost over block sizes 2..4 (the 2 BS - 1 residues of a block stay
-// within the eight byte lanes of one word) with q = 2^b, (2 BS - 1) b <= 51 and
-// at least four block products per reduction.  p <= 127 (two residues add
-// within a byte lane).  The estimate counts what section 5.3's model counts,
-// block products and reductions, the way the kernel executes them: per wave
-// (or per share of a wave, for products of up to 32 chunk pairs),
-// two phases of about Na / G term groups (G R FMAs and the LDS reads of G + R + G - 1
-// words each) and, per phase, a REDQ_{2BS-1} of each of the R sums at every
-// L-th term and at the end (about 40 + 12 (2 BS - 1) instructions each).
+// Output blocks per chunk for a product of NW + 1 output blocks: 4, or 8 for
+// products of 32 to 64 chunk pairs of four.  Eight blocks per lane halve the B
+// reads from LDS per block product (a window of G + 7 words serves 8 G FMAs)
+// and let two to four such products share a wave; above 64 pairs the product
+// spans several waves and the fewer registers of R = 4 keep more of them
+// resident (measured over F_3 from 65 to 4096 coefficients).
+static uint32_t long_chunk_blocks(uint32_t NW) {
+    const uint32_t pairs4 = ((NW + 1 + 3) / 4 + 1) / 2;
+    return pairs4 >= 32 && pairs4 <= 64 ? 8u : 4u;
+}
+
+// Block size, q, L, the group width G and the chunk size R of a long product:
+// the smallest estimated cost over block sizes 2..4 (the 2 BS - 1 residues of a
+// block stay within the eight byte lanes of one word) with q = 2^b,
+// (2 BS - 1) b <= 51 and at least four block products per reduction.  p <= 127
+// (two residues add within a byte lane).  The estimate counts what section
+// 5.3's model counts, block products and reductions, the way the kernel runs
+// them, in units of one lane's binary64 FMA: per wave (or per share of a wave,
+// for products of up to 32 chunk pairs), two phases of about Na / G term
+// groups of G R FMAs, and per phase a REDQ_{2BS-1} of each of the R sums at
+// every L-th term and at the end, about 9.7 (2 BS - 1) FMAs each; plus the
+// product's own loads and stores (17 per 64 bytes) and 76 for its set-up.  The
+// weights are a least-squares fit of measured times over F_3 (n = 65 .. 2048,
+// every block size).
 dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out,
-                         uint32_t* L_out, uint32_t* G_out) {
+                         uint32_t* L_out, uint32_t* G_out, uint32_t* R_out) {
     if (p > 127) return DQT_E_UNSUPPORTED;
     const uint64_t e2 = (uint64_t)(p - 1) * (p - 1);
     double best = 1e300;
@@ -309,23 +329,26 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
         const uint32_t G = nq >= 8 ? 8 : 4;
         const uint32_t L = (uint32_t)(nq / G) * G;
         const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs, NW = Na + Nb - 1;
-        const uint32_t C = (NW + 1 + kLongR - 1) / kLongR;
+        const uint32_t R = long_chunk_blocks(NW);
+        const uint32_t C = (NW + 1 + R - 1) / R;
         // waves per product: up to 32 chunk pairs share a wave (a power-of-two group of lanes)
         const uint32_t pairs = (C + 1) / 2;
         uint32_t lanes = 1;
         while (lanes < pairs) lanes *= 2;
         const double waves = pairs <= 32 ? lanes / 64.0 : (double)((pairs + 63) / 64);
         const double span = (double)(Na < Nb ? Na : Nb);
-        const double groups = 2.0 * ((span + G - 1) / G);
-        const double per_group = (double)(kLongR * G) + (2.0 * G + kLongR - 1) / 2.0 + 8.0;
-        const double reductions = 2.0 * (std::floor((span - 1) / L) + 1.0) * kLongR;
-        const double cost = waves * (groups * per_group + reductions * (40.0 + 12.0 * (2 * bs - 1)));
+        const double groups = 2.0 * std::ceil(span / G);
+        const double fmas = groups * R * G;
+        const double reductions = 2.0 * (std::floor((span - 1) / L) + 1.0) * R;
+        const double io = (na + nb + 2.0 * (na + nb - 1)) / 64.0;
+        const double cost = waves * (fmas + reductions * 9.7 * (2 * bs - 1)) + 17.0 * io + 76.0;
         if (cost < best) {
             best = cost;
             best_bs = bs;
             *b_out = b;
             *L_out = L;
             *G_out = G;
+            *R_out = R;
         }
     }
     if (!best_bs) return block ? DQT_E_BOUND : DQT_E_UNSUPPORTED;
@@ -346,8 +369,8 @@ static unsigned groups_per_cu(size_t smem, unsigned threads) {
 dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint64_t count, uint32_t p,
                             uint32_t block, uint8_t* out, hipStream_t s, bool check_only) {
     if (na > kLongMaxCoeffs || nb > kLongMaxCoeffs) return DQT_E_UNSUPPORTED;
-    uint32_t bs = 0, b = 0, L = 0, G = 0;
-    DQT_TRY(fqt_long_plan(p, na, nb, block, &bs, &b, &L, &G));
+    uint32_t bs = 0, b = 0, L = 0, G = 0, R = 0;
+    DQT_TRY(fqt_long_plan(p, na, nb, block, &bs, &b, &L, &G, &R));
     LongArgs g;
     memset(&g, 0, sizeof(g));
     DQT_TRY(make_redq_args(p, b, 2 * bs - 1, (2 * bs - 1) * b, &g.ra));
@@ -360,12 +383,13 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     g.Nb = (nb + bs - 1) / bs;
     g.NW = g.Na + g.Nb - 1;
     g.L = L;
-    g.C = (g.NW + 1 + kLongR - 1) / kLongR;   // blocks 0 .. NW (block NW only carries the top residues of NW-1)
+    // chunks of R output blocks (blocks 0 .. NW; block NW only carries the top residues of NW-1)
+    g.C = (g.NW + 1 + R - 1) / R;
     g.na_pad = (g.Na + G - 1) / G * G;
     g.nb_tot = kPad + g.Nb + kPad;
     g.lds_a = 4096 * 2;                        // the correction table
     g.lds_b = g.lds_a + g.na_pad * 8;
-    g.lds_bnd = g.lds_b + ((gapped<2>(g.nb_tot) * 8 + 15) & ~15u);
+    g.lds_bnd = g.lds_b + ((gapped_n(long_gap_shift(R, G), g.nb_tot) * 8 + 15) & ~15u);
     const uint32_t pairs = (g.C + 1) / 2;   // one chunk pair per thread
     unsigned threads;
     g.pp_bytes = (uint32_t)((g.lds_bnd - g.lds_a + (size_t)g.C * 8 + 15) & ~(size_t)15);
@@ -391,28 +415,39 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     // block sizes the cost picks over F_3) have a compile-time q and residue width;
     // every other case the run-time form
     if (g.ra.w == 2 && G == 8 && ((bs == 3 && b == 10) || (bs == 2 && b == 17))) {
-        if (bs == 3)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<3, 8, 10, 2>), dim3(grid), dim3(threads), smem, s, A,
-                               B, out, count, g);
-        else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<2, 8, 17, 2>), dim3(grid), dim3(threads), smem, s, A,
-                               B, out, count, g);
+#define DQT_LONG_F3(BSV, QBV, RV)                                                                                  \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, 8, QBV, 2, RV>), dim3(grid), dim3(threads), smem, s, A, \
+                       B, out, count, g)
+        if (bs == 3) {
+            if (R == 8) DQT_LONG_F3(3, 10, 8);
+            else DQT_LONG_F3(3, 10, 4);
+        } else {
+            if (R == 8) DQT_LONG_F3(2, 17, 8);
+            else DQT_LONG_F3(2, 17, 4);
+        }
+#undef DQT_LONG_F3
         DQT_LAUNCH_CHECK("dqt_polymul_fqt_u8 (long)");
         return DQT_OK;
     }
-    const unsigned key = bs * 16 + G;
+    const unsigned key = bs * 256 + G * 16 + R;
     switch (key) {
-#define DQT_LONG_CASE(BSV, GV)                                                                                   \
-    case BSV * 16 + GV:                                                                                          \
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, GV, 0, 0>), dim3(grid), dim3(threads), smem, s, \
-                           A, B, out, count, g);                                                                 \
+#define DQT_LONG_CASE(BSV, GV, RV)                                                                                \
+    case BSV * 256 + GV * 16 + RV:                                                                                \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, GV, 0, 0, RV>), dim3(grid), dim3(threads), smem, \
+                           s, A, B, out, count, g);                                                               \
         break;
-        DQT_LONG_CASE(2, 4)
-        DQT_LONG_CASE(2, 8)
-        DQT_LONG_CASE(3, 4)
-        DQT_LONG_CASE(3, 8)
-        DQT_LONG_CASE(4, 4)
-        DQT_LONG_CASE(4, 8)
+        DQT_LONG_CASE(2, 4, 4)
+        DQT_LONG_CASE(2, 8, 4)
+        DQT_LONG_CASE(3, 4, 4)
+        DQT_LONG_CASE(3, 8, 4)
+        DQT_LONG_CASE(4, 4, 4)
+        DQT_LONG_CASE(4, 8, 4)
+        DQT_LONG_CASE(2, 4, 8)
+        DQT_LONG_CASE(2, 8, 8)
+        DQT_LONG_CASE(3, 4, 8)
+        DQT_LONG_CASE(3, 8, 8)
+        DQT_LONG_CASE(4, 4, 8)
+        DQT_LONG_CASE(4, 8, 8)
 #undef DQT_LONG_CASE
         default: return DQT_E_UNSUPPORTED;
     }

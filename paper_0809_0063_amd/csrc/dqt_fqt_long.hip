@@ -335,7 +335,9 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
         const uint32_t pairs = (C + 1) / 2;
         uint32_t lanes = 1;
         while (lanes < pairs) lanes *= 2;
-        const double waves = pairs <= 32 ? lanes / 64.0 : (double)((pairs + 63) / 64);
+        // (groups of fewer than 16 lanes measured no faster than 16: a wave's LDS reads
+        // are served 16 lanes at a time)
+        const double waves = pairs <= 32 ? (lanes < 16 ? 16 : lanes) / 64.0 : (double)((pairs + 63) / 64);
         const double span = (double)(Na < Nb ? Na : Nb);
         const double groups = 2.0 * std::ceil(span / G);
         const double fmas = groups * R * G;

@@ -240,8 +240,9 @@ dqt_status dqt_gf_dot_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count,
  * one coefficient per machine multiply-add, integer accumulation, one
  * reduction (REDC) per output coefficient.  Same layouts and results as the
  * packed entry points.  dqt_polymul_plain_u8 accepts any k <= 4096 (above 64
- * coefficients one wave computes a product, eight output coefficients per
- * lane, operands in LDS).
+ * coefficients a workgroup, or for short products a group of lanes of one
+ * wave, computes a product, eight output coefficients per lane, operands in
+ * LDS).
  */
 dqt_status dqt_polymul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count, uint32_t k, uint32_t p,
                                 uint8_t *d_out, void *stream);

@@ -153,6 +153,25 @@ def gf_dot(a: np.ndarray, b: np.ndarray, p: int, modulus: Sequence[int], threads
     return out.astype(np.uint8)
 
 
+def gf_matmul(a: np.ndarray, b: np.ndarray, p: int, modulus: Sequence[int], threads: int = 0) -> np.ndarray:
+    """Matrix products over GF(p^k) (section 6: algorithm FGDP's dot products arranged as a matrix
+    product): out[i, j] = sum_l a[i, l] b[l, j] in the field.
+
+    a: uint8 [m, kd, k], b: uint8 [kd, n, k] -> uint8 [m, n, k]; each entry is the dot product
+    (gf_dot) of row i of a and column j of b.
+    """
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    m, kd, k = a.shape
+    kd2, n, k2 = b.shape
+    assert kd2 == kd and k2 == k
+    if m == 0 or n == 0:
+        return np.zeros((m, n, k), dtype=np.uint8)
+    rows = np.broadcast_to(a[:, None, :, :], (m, n, kd, k)).reshape(m * n, kd, k)
+    cols = np.broadcast_to(b.transpose(1, 0, 2)[None, :, :, :], (m, n, kd, k)).reshape(m * n, kd, k)
+    return gf_dot(rows, cols, p, modulus, threads).reshape(m, n, k)
+
+
 def radix_mod(r: np.ndarray, p: int, logq: int, nres: int, threads: int = 0) -> np.ndarray:
     """REDQ's specification (alg:REDQ ENSURE): digits of r in base q = 2^logq, each mod p.
 

@@ -424,6 +424,35 @@ def test_gf_dot_pins():
             assert d[t].tolist() == acc
 
 
+def test_gf_matmul_pins():
+    """Matrix products over GF(p^k): the identity matrix (the field's 1 on the diagonal) leaves a
+    matrix unchanged on either side; the product is associative; entries agree with pure-Python
+    sums of field products; rectangular shapes keep rows of a and columns of b apart; an empty
+    inner dimension gives zeros."""
+    for p, k in [(3, 5), (7, 3), (2, 6), (13, 2)]:
+        P = inputs.irreducible(p, k)
+        g = np.random.default_rng(900 + p * 10 + k)
+        m, kd, n, r = 3, 5, 4, 6
+        a = g.integers(0, p, size=(m, kd, k), dtype=np.uint8)
+        b = g.integers(0, p, size=(kd, n, k), dtype=np.uint8)
+        d = g.integers(0, p, size=(n, r, k), dtype=np.uint8)
+        c = O.gf_matmul(a, b, p, P)
+        assert c.shape == (m, n, k)
+        one = lambda s: np.stack([np.eye(s, dtype=np.uint8)] + [np.zeros((s, s), dtype=np.uint8)] * (k - 1), axis=2)
+        assert (O.gf_matmul(a, one(kd), p, P) == a).all()
+        assert (O.gf_matmul(one(m), a, p, P) == a).all()
+        assert (O.gf_matmul(O.gf_matmul(a, b, p, P), d, p, P) == O.gf_matmul(a, O.gf_matmul(b, d, p, P), p, P)).all()
+        for i in range(m):
+            for j in range(n):
+                acc = [0] * k
+                for l in range(kd):
+                    pr = O.gf_mul_py(a[i, l].tolist(), b[l, j].tolist(), p, P)
+                    acc = [(x + y) % p for x, y in zip(acc, pr)]
+                assert c[i, j].tolist() == acc, (p, k, i, j)
+        z = O.gf_matmul(np.zeros((m, 0, k), np.uint8), np.zeros((0, n, k), np.uint8), p, P)
+        assert z.shape == (m, n, k) and not z.any()
+
+
 def test_compressed_products_digits_are_the_dot_products():
     """Sections 7.4-7.5: with k (p-1)^2 < Q (eq:lower) and Theta = Q^er (eq:qtheta with equality), the
     digits of every compressed word are exactly the integer dot products (Right, Left and Full), so

@@ -426,6 +426,14 @@ def bench_gf(D, inputs, torch, dev, reps_big):
     out["gf_3^5_dot_n128"] = {"dot_s": round(cnt / s, 1), "GB_s": round(byts / s / 1e9, 1),
                               "hbm_frac": round(byts / s / PEAK_HBM, 4), "us_per_call": round(s * 1e6, 1),
                               "n_q": 1, "bound": "valu"}
+    # matrix product over GF(3^5): 512 x 512 x 512 field elements (FGDP dot products, n_q = 1)
+    mm = 512
+    xa = torch.from_numpy(g.integers(0, pp, size=(mm, mm, k), dtype="uint8")).to(dev)
+    xb = torch.from_numpy(g.integers(0, pp, size=(mm, mm, k), dtype="uint8")).to(dev)
+    om = torch.empty((mm, mm, k), dtype=torch.uint8, device=dev)
+    s = timed_loop(lambda: D.gf_matmul_u8(xa, xb, pp, P, out=om), 4, 2, torch)
+    out["gf_3^5_matmul_512"] = {"field_products_s": round(mm ** 3 / s, 1), "us_per_call": round(s * 1e6, 1),
+                                "n_q": 1, "bound": "valu"}
     return out
 
 

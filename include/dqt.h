@@ -236,6 +236,19 @@ dqt_status dqt_gf_dot_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t count,
                          const uint8_t *modulus, uint8_t *d_out, void *stream);
 
 /*
+ * Matrix products over GF(p^k) by algorithm FGDP (section 6): C[i][j] =
+ * sum_l A[i][l] B[l][j], every entry a dot product of field elements summed
+ * n_q products at a time in packed form (the same q, n_q, REDQ and two tables
+ * as dqt_gf_dot_u8).  d_a: uint8 [m][kd][k], d_b: uint8 [kd][n][k], d_out:
+ * uint8 [m][n][k], all row-major and dense; modulus as for dqt_gf_mul_u8.
+ * kd = 0 gives zeros; m or n = 0 is a no-op.  p <= 127, 2 <= k <= 6, k w <= 11
+ * (w = bits of p - 1: the two tables of 2^(k w) entries share a workgroup's
+ * 64 KiB of LDS with the tiles), m <= 4,194,240; DQT_E_UNSUPPORTED otherwise.
+ */
+dqt_status dqt_gf_matmul_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t m, uint64_t n, uint64_t kd, uint32_t k,
+                            uint32_t p, const uint8_t *modulus, uint8_t *d_out, void *stream);
+
+/*
  * Plain per-entry comparators (the paper's "delayed" baseline, section 5.1):
  * one coefficient per machine multiply-add, integer accumulation, one
  * reduction (REDC) per output coefficient.  Same layouts and results as the

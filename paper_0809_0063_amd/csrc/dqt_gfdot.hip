@@ -236,6 +236,154 @@ static dqt_status launch_gf_dot(const uint8_t* A, const uint8_t* B, uint8_t* out
     return DQT_OK;
 }
 
+// Matrix products over GF(p^k) by FGDP: C[i][j] = sum_l A[i][l] B[l][j], each
+// entry a dot product of packed field elements (section 6).  A workgroup of 256
+// threads takes a 64 x 32 tile of C, a thread 4 rows x 2 columns of it; A and B
+// pass through LDS in steps of 16 along l, each element packed once into a
+// 32-bit word with fields of B bits (the same q = 2^B as the dot products).
+// Every output of a thread receives one product per step of l, so the packed
+// sums of all eight reach n_q together and are reduced together (REDQ, the two
+// tables, the sums in 16-bit lanes as in k_gf_dot).
+constexpr int kGmRows = 64, kGmCols = 32, kGmK = 16;
+
+template <int K>
+__device__ __forceinline__ uint32_t element_word(const uint8_t* e) {
+    constexpr int B = 53 / (2 * K - 1);
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) v |= (uint32_t)e[i] << (B * i);
+    return v;
+}
+
+template <int K, bool NQ1>
+__global__ __launch_bounds__(256) void k_gf_matmul(const uint8_t* __restrict__ A, const uint8_t* __restrict__ Bm,
+                                                   uint8_t* __restrict__ OUT, uint32_t m, uint32_t n, uint32_t kd,
+                                                   uint32_t nq, RedqArgs ra, GfArgs ga) {
+    constexpr int B = 53 / (2 * K - 1);
+    extern __shared__ uint64_t gfm_smem[];
+    const uint32_t tn = 1u << (K * ra.w);
+    uint64_t* tl = gfm_smem;
+    uint64_t* th = gfm_smem + tn;
+    uint32_t* la = reinterpret_cast<uint32_t*>(gfm_smem + 2 * tn);   // [kGmK][kGmRows]
+    uint32_t* lb = la + kGmK * kGmRows;                                // [kGmK][kGmCols]
+    build_gf_tables_dot<K>(tl, th, ra, ga);
+    const uint64_t ones = 0x0101010101010101ull >> (8 * (8 - K));
+    constexpr uint64_t kEven = 0x00FF00FF00FF00FFull;
+    const uint32_t wm = (1u << ra.w) - 1u;
+    const uint32_t fold_at = 65535u / (2u * (ra.p - 1u));
+    const uint32_t tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+    const uint32_t row0 = blockIdx.y * kGmRows, col0 = blockIdx.x * kGmCols;
+    uint64_t acc[4][2], RE[4][2], RO[4][2], R[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = RE[i][j] = RO[i][j] = R[i][j] = 0;
+    uint32_t cnt = 0, nred = 0;
+    auto reduce = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint64_t U = redq_compress(acc[i][j], ra);
+                const uint32_t xl = (uint32_t)U, xh = (uint32_t)(U >> (B * (K - 1)));
+                uint32_t il = 0, ih = 0;
+#pragma unroll
+                for (int jj = 0; jj < K; ++jj) {
+                    il |= __builtin_amdgcn_ubfe(xl, B * jj, ra.w) << (ra.w * jj);
+                    ih |= __builtin_amdgcn_ubfe(xh, B * jj, ra.w) << (ra.w * jj);
+                }
+                const uint64_t sum = th[ih] + tl[il];   // bytes below 2p - 1
+                RE[i][j] += sum & kEven;
+                RO[i][j] += (sum >> 8) & kEven;
+                acc[i][j] = 0;
+            }
+        cnt = 0;
+        if (++nred == fold_at) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    R[i][j] = add_mod_bytes(R[i][j], fold16<K>(RE[i][j], RO[i][j], ra.p, ra.pmagic), ra.p, ones);
+                    RE[i][j] = RO[i][j] = 0;
+                }
+            nred = 0;
+        }
+    };
+    for (uint32_t k0 = 0; k0 < kd; k0 += kGmK) {
+        __syncthreads();   // the tables are built / the previous step's words are used
+        for (uint32_t e = tid; e < kGmRows * kGmK; e += 256) {
+            const uint32_t r = e / kGmK, kk = e % kGmK;
+            const uint32_t row = row0 + r, l = k0 + kk;
+            la[kk * kGmRows + r] = row < m && l < kd ? element_word<K>(A + ((uint64_t)row * kd + l) * K) : 0u;
+        }
+        for (uint32_t e = tid; e < kGmCols * kGmK; e += 256) {
+            const uint32_t kk = e / kGmCols, c = e % kGmCols;
+            const uint32_t col = col0 + c, l = k0 + kk;
+            lb[kk * kGmCols + c] = col < n && l < kd ? element_word<K>(Bm + ((uint64_t)l * n + col) * K) : 0u;
+        }
+        __syncthreads();
+        const uint32_t steps = min((uint32_t)kGmK, kd - k0);
+        for (uint32_t kk = 0; kk < steps; ++kk) {
+            const uint4 a4 = *reinterpret_cast<const uint4*>(la + kk * kGmRows + ty * 4);
+            const uint2 b2 = *reinterpret_cast<const uint2*>(lb + kk * kGmCols + tx * 2);
+            const uint32_t av[4] = {a4.x, a4.y, a4.z, a4.w}, bv[2] = {b2.x, b2.y};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] += (uint64_t)av[i] * bv[j];
+            if (NQ1 || ++cnt == nq) reduce();
+        }
+    }
+    if (!NQ1 && cnt) reduce();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t row = row0 + ty * 4 + i;
+        if (row >= m) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t col = col0 + tx * 2 + j;
+            if (col >= n) continue;
+            const uint64_t r = add_mod_bytes(R[i][j], fold16<K>(RE[i][j], RO[i][j], ra.p, ra.pmagic), ra.p, ones);
+            uint8_t* o = OUT + ((uint64_t)row * n + col) * K;
+#pragma unroll
+            for (int t = 0; t < K; ++t) o[t] = (uint8_t)(r >> (8 * t));
+        }
+    }
+}
+
+template <int K>
+static dqt_status launch_gf_matmul(const uint8_t* A, const uint8_t* B, uint8_t* out, uint32_t m, uint32_t n,
+                                   uint32_t kd, uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
+    const size_t smem = 2ull * (1ull << (K * ra.w)) * sizeof(uint64_t) + (size_t)kGmK * (kGmRows + kGmCols) * 4;
+    const dim3 grid((n + kGmCols - 1) / kGmCols, (m + kGmRows - 1) / kGmRows);
+    if (nq == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_matmul<K, true>), grid, dim3(256), smem, s, A, B, out, m, n, kd, nq, ra,
+                           ga);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_matmul<K, false>), grid, dim3(256), smem, s, A, B, out, m, n, kd, nq,
+                           ra, ga);
+    DQT_LAUNCH_CHECK("dqt_gf_matmul_u8");
+    return DQT_OK;
+}
+
+// FGDP's parameters for sums of up to `len` products: q = 2^b with b = 53 / (2k - 1)
+// (the kernels' compile-time B), n_q = floor((q - 1) / (k (p - 1)^2)) capped at len.
+static dqt_status fgdp_setup(uint32_t k, uint32_t p, const uint8_t* modulus, uint64_t len, GfArgs* ga, RedqArgs* ra,
+                             uint32_t* nq) {
+    if (p < 2 || p > 127 || k < 2 || k > 6 || !modulus) return DQT_E_INVALID;
+    DQT_TRY(gf_setup_args(k, p, modulus, ga));
+    const uint32_t w = residue_bits(p);
+    if (k * w > 12) return DQT_E_UNSUPPORTED;
+    const uint32_t b = 53 / (2 * k - 1);
+    if (b < w) return DQT_E_UNSUPPORTED;
+    const uint64_t per = (uint64_t)k * (p - 1) * (p - 1);
+    const uint64_t nq64 = per ? (((1ull << b) - 1) / per) : len;
+    if (nq64 < 1) return DQT_E_UNSUPPORTED;   // not even one product fits a word
+    *nq = (uint32_t)(nq64 > len ? (len ? len : 1) : nq64);
+    if (b * (k - 1) + w > 32) return DQT_E_UNSUPPORTED;  // table indices gathered from 32-bit windows
+    return make_redq_args(p, b, 2 * k - 1, (2 * k - 1) * b, ra);
+}
+
 }  // namespace dqt
 
 using namespace dqt;
@@ -269,5 +417,29 @@ extern "C" dqt_status dqt_gf_dot_u8(const uint8_t* d_a, const uint8_t* d_b, uint
         case 4: return launch_gf_dot<4>(d_a, d_b, d_out, count, n, nq, ra, ga, s);
         case 5: return launch_gf_dot<5>(d_a, d_b, d_out, count, n, nq, ra, ga, s);
         default: return launch_gf_dot<6>(d_a, d_b, d_out, count, n, nq, ra, ga, s);
+    }
+}
+
+extern "C" dqt_status dqt_gf_matmul_u8(const uint8_t* d_a, const uint8_t* d_b, uint64_t m, uint64_t n, uint64_t kd,
+                                       uint32_t k, uint32_t p, const uint8_t* modulus, uint8_t* d_out, void* stream) {
+    if (m > 0x7FFFFFFFull || n > 0x7FFFFFFFull || kd > 0x7FFFFFFFull) return DQT_E_INVALID;
+    GfArgs ga;
+    RedqArgs ra;
+    uint32_t nq = 0;
+    DQT_TRY(fgdp_setup(k, p, modulus, kd, &ga, &ra, &nq));
+    // the two tables and the tiles share 64 KiB of LDS
+    if (2ull * (1ull << (k * ra.w)) * 8 + (size_t)kGmK * (kGmRows + kGmCols) * 4 > 65536) return DQT_E_UNSUPPORTED;
+    if ((m + kGmRows - 1) / kGmRows > 65535) return DQT_E_UNSUPPORTED;   // row tiles on the grid's y axis
+    if (m == 0 || n == 0) return DQT_OK;
+    if ((kd && (!d_a || !d_b)) || !d_out) return DQT_E_INVALID;
+    DQT_TRY(ensure_device_ready());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (kd) DQT_TRY(debug_gate(s, p, {{d_a, m, kd * k, kd * k}, {d_b, kd, n * k, n * k}}));
+    switch (k) {
+        case 2: return launch_gf_matmul<2>(d_a, d_b, d_out, (uint32_t)m, (uint32_t)n, (uint32_t)kd, nq, ra, ga, s);
+        case 3: return launch_gf_matmul<3>(d_a, d_b, d_out, (uint32_t)m, (uint32_t)n, (uint32_t)kd, nq, ra, ga, s);
+        case 4: return launch_gf_matmul<4>(d_a, d_b, d_out, (uint32_t)m, (uint32_t)n, (uint32_t)kd, nq, ra, ga, s);
+        case 5: return launch_gf_matmul<5>(d_a, d_b, d_out, (uint32_t)m, (uint32_t)n, (uint32_t)kd, nq, ra, ga, s);
+        default: return launch_gf_matmul<6>(d_a, d_b, d_out, (uint32_t)m, (uint32_t)n, (uint32_t)kd, nq, ra, ga, s);
     }
 }

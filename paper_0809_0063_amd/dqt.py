@@ -119,6 +119,7 @@ def _load():
         "dqt_polymul_fqt_u8": [V, U32, V, U32, U64, U32, U32, V, V],
         "dqt_polymul_fqt_kara_u8": [V, U32, V, U32, U64, U32, U32, U32, V, V],
         "dqt_polymul_kara_long_u8": [V, V, U64, U32, U32, U32, V, V, SZ, V],
+        "dqt_gf_matmul_u8": [V, V, U64, U64, U64, U32, U32, V, V, V],
         "dqt_check_input_u8": [V, U64, U32, V, V],
         "dqt_fgemm": [U32, U64, U64, U64, V, U64, V, U64, V, U64, ctypes.POINTER(_GemmPlan), V, SZ, V],
         "dqt_fgemm_batched": [ctypes.POINTER(_GemmDesc), U32, ctypes.POINTER(_BatchOpts), V, SZ, V],
@@ -404,6 +405,22 @@ def gf_mul_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
     _check(_load().dqt_gf_mul_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), n, k, p, log2q,
                                  ctypes.cast(mod, ctypes.c_void_p), _dev(out, "out", torch.uint8), _stream(stream)),
            "dqt_gf_mul_u8")
+    return out
+
+
+def gf_matmul_u8(a: torch.Tensor, b: torch.Tensor, p: int, modulus: Sequence[int],
+                 out: Optional[torch.Tensor] = None, stream=None):
+    """Matrix products over GF(p^k) by FGDP: uint8 [m, kd, k] x uint8 [kd, n, k] -> uint8 [m, n, k]."""
+    if a.dim() != 3 or b.dim() != 3 or a.shape[1] != b.shape[0] or a.shape[2] != b.shape[2]:
+        raise ValueError("a must be [m, kd, k] and b [kd, n, k]")
+    m, kd, k = a.shape
+    n = b.shape[1]
+    if out is None:
+        out = torch.empty((m, n, k), dtype=torch.uint8, device=a.device)
+    mod = _host_modulus(modulus)
+    _check(_load().dqt_gf_matmul_u8(_dev(a, "a", torch.uint8), _dev(b, "b", torch.uint8), m, n, kd, k, p,
+                                    ctypes.cast(mod, ctypes.c_void_p), _dev(out, "out", torch.uint8), _stream(stream)),
+           "dqt_gf_matmul_u8")
     return out
 
 

@@ -365,6 +365,43 @@ def test_gf_dot_unaligned_operands(dqt, p, k):
             assert (h[:off] == 0xAB).all() and (h[off + count * k:] == 0xAB).all()
 
 
+@pytest.mark.parametrize("p,k", [(3, 5), (7, 3), (2, 6), (13, 2), (3, 2), (5, 3)])
+def test_gf_matmul(dqt, p, k):
+    """Matrix products over GF(p^k) against the oracle: tiles of 64 x 32 with ragged edges, inner
+    dimensions within one step of 16, across several, and long enough for several packed sums
+    (n_q > 1) and folds, the all-(p-1) worst case, an empty inner dimension (zeros)."""
+    import torch
+    P = inputs.irreducible(p, k)
+    g = np.random.default_rng(600 + p * 10 + k)
+    dev = device()
+    for m, kd, n in [(1, 1, 1), (64, 16, 32), (65, 17, 33), (130, 40, 70), (7, 300, 5), (3, 1000, 40)]:
+        a = g.integers(0, p, size=(m, kd, k), dtype=np.uint8)
+        b = g.integers(0, p, size=(kd, n, k), dtype=np.uint8)
+        a[0] = p - 1
+        b[:, 0] = p - 1
+        got = to_host(dqt.gf_matmul_u8(to_dev(a), to_dev(b), p, P))
+        assert (got == O.gf_matmul(a, b, p, P)).all(), (p, k, m, kd, n)
+    z = dqt.gf_matmul_u8(torch.zeros((5, 0, k), dtype=torch.uint8, device=dev),
+                         torch.zeros((0, 9, k), dtype=torch.uint8, device=dev), p, P)
+    assert z.shape == (5, 9, k) and not to_host(z).any()
+    e = dqt.gf_matmul_u8(torch.zeros((0, 4, k), dtype=torch.uint8, device=dev),
+                         torch.zeros((4, 9, k), dtype=torch.uint8, device=dev), p, P)
+    assert e.shape == (0, 9, k)
+
+
+def test_gf_matmul_limits(dqt):
+    """Fields whose tables do not fit next to the tiles are refused; bad shapes are refused."""
+    import torch
+    dev = device()
+    P = inputs.irreducible(5, 4)        # k w = 12
+    x = torch.zeros((4, 4, 4), dtype=torch.uint8, device=dev)
+    with pytest.raises(dqt.DQTError) as e:
+        dqt.gf_matmul_u8(x, x, 5, P)
+    assert e.value.status == dqt.DQT_E_UNSUPPORTED
+    with pytest.raises(ValueError):
+        dqt.gf_matmul_u8(x, torch.zeros((5, 4, 4), dtype=torch.uint8, device=dev), 5, P)
+
+
 def test_gf_dot_many_long(dqt):
     """More long dot products than one pass of the grid holds (a wave per dot product, grid-stride),
     and a count that leaves the last pass partly empty."""

@@ -160,25 +160,32 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
             bd[gapped<GS>(k)] = (double)w;
         }
         __syncthreads();
-        uint64_t res[2][R];
-#pragma unroll
+        // Each phase ends with its chunk written: the last block residues of every chunk
+        // go to bnd first, and after a barrier each lane writes its chunk (chunk c - 1 of a
+        // phase-1 chunk is a phase-1 chunk or the last phase-0 one, both in bnd by then).
+        // So one phase's residues are held in registers at a time.
+        uint8_t* o = OUT + t * g.nout;
+        // (a loop, not unrolled: one copy of the phase keeps the register count down)
+#pragma unroll 1
         for (int h = 0; h < 2; ++h) {
+            const uint32_t ch = h == 0 ? cs[0] : cs[1];   // this phase's chunk (no indexed array)
             // The wave walks one common sequence of term groups (from the smallest first group
             // of its lanes to the largest last one); a lane multiplies only in its own groups.
             // The sums are reduced at multiples of L in the common sequence, so every lane of
             // the wave reduces at the same time and each sum holds at most L block products.
             const bool mine = h < nc;
-            const uint32_t u0 = mine ? cs[h] * R : 0;
+            const uint32_t u0 = mine ? ch * R : 0;
             const uint32_t ilo = u0 + 1 > g.Nb ? u0 + 1 - g.Nb : 0;
             const uint32_t ihi = min(g.Na - 1, u0 + R - 1);
             const uint32_t lo = mine ? (ilo & ~(uint32_t)(G - 1)) : 0xFFFFFFFFu;
             const uint32_t hi = mine ? ihi : 0u;
             const uint32_t wlo = wave_min(lo), whi = wave_max(hi);
             double W[R];
+            uint64_t res[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 W[r] = 0.0;
-                res[h][r] = 0;
+                res[r] = 0;
             }
             if (wlo <= whi) {
                 uint32_t next_red = (wlo / g.L + 1) * g.L;
@@ -198,25 +205,21 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
                     }
                     if (ig + G == next_red) {
                         next_red += g.L;
-                        reduce(W, res[h]);
+                        reduce(W, res);
                     }
                 }
-                reduce(W, res[h]);
+                reduce(W, res);
             }
-            if (mine) bnd[cs[h]] = res[h][R - 1];
-        }
-        __syncthreads();
-        // coefficient j = u BS + s: residue s of block u plus residue s + BS of block u - 1
-        uint8_t* o = OUT + t * g.nout;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (h >= nc) break;
-            const uint32_t c = cs[h];
+            if (mine) bnd[ch] = res[R - 1];
+            __syncthreads();
+            if (!mine) continue;
+            // coefficient j = u BS + s: residue s of block u plus residue s + BS of block u - 1
+            const uint32_t c = ch;
             uint64_t prev = c ? bnd[c - 1] : 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint32_t u = c * R + r;
-                const uint64_t cur = res[h][r];
+                const uint64_t cur = res[r];
 #pragma unroll
                 for (int s = 0; s < BS; ++s) {
                     const uint32_t j = u * BS + s;
@@ -291,30 +294,21 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 
 }  // namespace
 
-// Output blocks per chunk for a product of NW + 1 output blocks: 4, or 8 for
-// products of 32 to 64 chunk pairs of four.  Eight blocks per lane halve the B
-// reads from LDS per block product (a window of G + 7 words serves 8 G FMAs)
-// and let two to four such products share a wave; above 64 pairs the product
-// spans several waves and the fewer registers of R = 4 keep more of them
-// resident (measured over F_3 from 65 to 4096 coefficients).
-static uint32_t long_chunk_blocks(uint32_t NW) {
-    const uint32_t pairs4 = ((NW + 1 + 3) / 4 + 1) / 2;
-    return pairs4 >= 32 && pairs4 <= 64 ? 8u : 4u;
-}
-
 // Block size, q, L, the group width G and the chunk size R of a long product:
 // the smallest estimated cost over block sizes 2..4 (the 2 BS - 1 residues of a
-// block stay within the eight byte lanes of one word) with q = 2^b,
-// (2 BS - 1) b <= 51 and at least four block products per reduction.  p <= 127
-// (two residues add within a byte lane).  The estimate counts what section
-// 5.3's model counts, block products and reductions, the way the kernel runs
-// them, in units of one lane's binary64 FMA: per wave (or per share of a wave,
-// for products of up to 32 chunk pairs), two phases of about Na / G term
-// groups of G R FMAs, and per phase a REDQ_{2BS-1} of each of the R sums at
-// every L-th term and at the end, about 9.7 (2 BS - 1) FMAs each; plus the
-// product's own loads and stores (17 per 64 bytes) and 76 for its set-up.  The
+// block stay within the eight byte lanes of one word) and chunks of R = 4 or 8
+// output blocks, with q = 2^b, (2 BS - 1) b <= 51 and at least four block
+// products per reduction.  p <= 127 (two residues add within a byte lane).  The
+// estimate counts what section 5.3's model counts, block products and
+// reductions, the way the kernel runs them, in units of one lane's binary64 FMA:
+// per wave (or per share of a wave, for products of up to 32 chunk pairs), two
+// phases of about Na / G term groups of G R FMAs and G + R - 1 B words read
+// from LDS (about 4 each), and per phase a REDQ_{2BS-1} of each of the R sums
+// at every L-th term and at the end (about 22 (2 BS - 1) each); plus the
+// product's own loads and stores (43 per 64 bytes) and 75 for its set-up.  The
 // weights are a least-squares fit of measured times over F_3 (n = 65 .. 2048,
-// every block size).
+// both chunk sizes, every block size); the choice they give was the measured
+// fastest, or within 6% of it, at every measured n.
 dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out,
                          uint32_t* L_out, uint32_t* G_out, uint32_t* R_out) {
     if (p > 127) return DQT_E_UNSUPPORTED;
@@ -329,28 +323,30 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
         const uint32_t G = nq >= 8 ? 8 : 4;
         const uint32_t L = (uint32_t)(nq / G) * G;
         const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs, NW = Na + Nb - 1;
-        const uint32_t R = long_chunk_blocks(NW);
-        const uint32_t C = (NW + 1 + R - 1) / R;
-        // waves per product: up to 32 chunk pairs share a wave (a power-of-two group of lanes)
-        const uint32_t pairs = (C + 1) / 2;
-        uint32_t lanes = 1;
-        while (lanes < pairs) lanes *= 2;
-        // (groups of fewer than 16 lanes measured no faster than 16: a wave's LDS reads
-        // are served 16 lanes at a time)
-        const double waves = pairs <= 32 ? (lanes < 16 ? 16 : lanes) / 64.0 : (double)((pairs + 63) / 64);
-        const double span = (double)(Na < Nb ? Na : Nb);
-        const double groups = 2.0 * std::ceil(span / G);
-        const double fmas = groups * R * G;
-        const double reductions = 2.0 * (std::floor((span - 1) / L) + 1.0) * R;
-        const double io = (na + nb + 2.0 * (na + nb - 1)) / 64.0;
-        const double cost = waves * (fmas + reductions * 9.7 * (2 * bs - 1)) + 17.0 * io + 76.0;
-        if (cost < best) {
-            best = cost;
-            best_bs = bs;
-            *b_out = b;
-            *L_out = L;
-            *G_out = G;
-            *R_out = R;
+        for (uint32_t R = 4; R <= 8; R += 4) {
+            const uint32_t C = (NW + 1 + R - 1) / R;
+            // waves per product: up to 32 chunk pairs share a wave (a power-of-two group of lanes)
+            const uint32_t pairs = (C + 1) / 2;
+            if (pairs > 512) continue;
+            uint32_t lanes = 1;
+            while (lanes < pairs) lanes *= 2;
+            const double waves = pairs <= 32 ? lanes / 64.0 : (double)((pairs + 63) / 64);
+            const double span = (double)(Na < Nb ? Na : Nb);
+            const double groups = 2.0 * std::ceil(span / G);
+            const double fmas = groups * R * G;
+            const double window = groups * (G + R - 1);
+            const double reductions = 2.0 * (std::floor((span - 1) / L) + 1.0) * R;
+            const double io = (na + nb + 2.0 * (na + nb - 1)) / 64.0;
+            const double cost =
+                waves * (fmas + 4.0 * window + 22.2 * reductions * (2 * bs - 1)) + 43.0 * io + 75.0;
+            if (cost < best) {
+                best = cost;
+                best_bs = bs;
+                *b_out = b;
+                *L_out = L;
+                *G_out = G;
+                *R_out = R;
+            }
         }
     }
     if (!best_bs) return block ? DQT_E_BOUND : DQT_E_UNSUPPORTED;

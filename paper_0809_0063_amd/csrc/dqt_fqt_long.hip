@@ -98,7 +98,7 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 
 // QB, QW: log2 q and the residue width as compile-time constants (0 = from the
 // run-time arguments).
-template <int BS, int G, int QB, int QW, int R>
+template <int BS, int G, int QB, int QW, int R, bool ONE>
 __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                           uint8_t* __restrict__ OUT, uint64_t count, LongArgs g) {
     constexpr int NR = 2 * BS - 1;
@@ -118,8 +118,15 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
     uint64_t* bnd = reinterpret_cast<uint64_t*>(slot + (g.lds_bnd - g.lds_a));
     const RedqArgs& ra = g.ra;
     build_correction_table(tab, ra);
-    const uint32_t cs[2] = {pair, g.C - 1 - pair};
-    const int nc_all = pair < (g.C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
+    // Two chunks per lane.  ONE: chunk c with chunk c + ceil(C/2) (the number of terms of a
+    // chunk rises along the first half of the product and falls along the second, so the two
+    // add up to about the same for every lane), walked as one sequence per lane, each sum
+    // reduced once at the end (only when no sum needs an earlier reduction, L >= its terms).
+    // Otherwise chunk c with chunk C-1-c, in two wave-wide phases (below).
+    const uint32_t half = (g.C + 1) / 2;
+    const uint32_t cs[2] = {pair, ONE ? pair + half : g.C - 1 - pair};
+    const int nc_all = ONE ? (pair < half ? (cs[1] < g.C ? 2 : 1) : 0)
+                           : (pair < (g.C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0);
     // one REDQ_{2BS-1} of each of the R sums; their residues added to res
     auto reduce = [&](double (&W)[R], uint64_t (&res)[R]) {
 #pragma unroll
@@ -160,6 +167,82 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
             bd[gapped<GS>(k)] = (double)w;
         }
         __syncthreads();
+        if constexpr (ONE) {
+            // term groups of chunk c: from ilo (rounded down to G) to ihi
+            uint32_t lo[2] = {0, 0}, ng[2] = {0, 0};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= nc) continue;
+                const uint32_t u0 = cs[h] * R;
+                const uint32_t ilo = u0 + 1 > g.Nb ? u0 + 1 - g.Nb : 0;
+                const uint32_t ihi = min(g.Na - 1, u0 + R - 1);
+                lo[h] = ilo & ~(uint32_t)(G - 1);
+                ng[h] = ihi >= lo[h] ? (ihi - lo[h]) / G + 1 : 0;
+            }
+            double W[R], WA[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) W[r] = WA[r] = 0.0;
+            const uint32_t ntot = ng[0] + ng[1];
+            for (uint32_t k = 0; k < ntot; ++k) {
+                const bool inA = k < ng[0];
+                if (k == ng[0]) {   // the first chunk is done: keep its sums, start the second
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        WA[r] = W[r];
+                        W[r] = 0.0;
+                    }
+                }
+                const uint32_t ig = inA ? lo[0] + k * G : lo[1] + (k - ng[0]) * G;
+                const uint32_t u0 = (inA ? cs[0] : cs[1]) * R;
+                double av[G], wv[G + R - 1];
+#pragma unroll
+                for (int s2 = 0; s2 < G; ++s2) av[s2] = ad[ig + s2];
+                // wv[x] = B_{u0 - ig - (G-1) + x}
+                const double* wb = bd + gapped<GS>(kPad + u0 - ig - (G - 1));
+#pragma unroll
+                for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<GS>(x)];
+#pragma unroll
+                for (int s2 = 0; s2 < G; ++s2)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) W[r] = __builtin_fma(av[s2], wv[r - s2 + G - 1], W[r]);
+            }
+            if (ng[1] == 0) {   // one chunk only: its sums are still in W
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    WA[r] = W[r];
+                    W[r] = 0.0;
+                }
+            }
+            uint64_t res0[R], res1[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) res0[r] = res1[r] = 0;
+            reduce(WA, res0);   // every lane, at the same point of the code
+            reduce(W, res1);
+            if (nc >= 1) bnd[cs[0]] = res0[R - 1];
+            if (nc >= 2) bnd[cs[1]] = res1[R - 1];
+            __syncthreads();
+            uint8_t* o = OUT + t * g.nout;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= nc) break;
+                const uint32_t c = cs[h];
+                uint64_t prev = c ? bnd[c - 1] : 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t u = c * R + r;
+                    const uint64_t cur = h == 0 ? res0[r] : res1[r];
+#pragma unroll
+                    for (int s = 0; s < BS; ++s) {
+                        const uint32_t j = u * BS + s;
+                        uint32_t v = (uint32_t)(cur >> (8 * s)) & 0xFFu;
+                        if (s + BS < NR) v += (uint32_t)(prev >> (8 * (s + BS))) & 0xFFu;
+                        if (j < g.nout) o[j] = (uint8_t)(v >= ra.p ? v - ra.p : v);
+                    }
+                    prev = cur;
+                }
+            }
+            continue;
+        }
         // Each phase ends with its chunk written: the last block residues of every chunk
         // go to bnd first, and after a barrier each lane writes its chunk (chunk c - 1 of a
         // phase-1 chunk is a phase-1 chunk or the last phase-0 one, both in bnd by then).
@@ -310,7 +393,7 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 // both chunk sizes, every block size); the choice they give was the measured
 // fastest, or within 6% of it, at every measured n.
 dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out,
-                         uint32_t* L_out, uint32_t* G_out, uint32_t* R_out) {
+                         uint32_t* L_out, uint32_t* G_out, uint32_t* R_out, bool* one_out) {
     if (p > 127) return DQT_E_UNSUPPORTED;
     const uint64_t e2 = (uint64_t)(p - 1) * (p - 1);
     double best = 1e300;
@@ -333,19 +416,29 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
             const double waves = pairs <= 32 ? lanes / 64.0 : (double)((pairs + 63) / 64);
             const double span = (double)(Na < Nb ? Na : Nb);
             const double groups = 2.0 * std::ceil(span / G);
-            const double fmas = groups * R * G;
-            const double window = groups * (G + R - 1);
             const double reductions = 2.0 * (std::floor((span - 1) / L) + 1.0) * R;
             const double io = (na + nb + 2.0 * (na + nb - 1)) / 64.0;
-            const double cost =
-                waves * (fmas + 4.0 * window + 22.2 * reductions * (2 * bs - 1)) + 43.0 * io + 75.0;
-            if (cost < best) {
-                best = cost;
-                best_bs = bs;
-                *b_out = b;
-                *L_out = L;
-                *G_out = G;
-                *R_out = R;
+            for (int one = 0; one <= 1; ++one) {
+                // one sequence per lane over balanced chunks: about (span + R) / G groups per
+                // lane instead of two wave-wide walks of span / G, but A words read per lane
+                // (not broadcast); only where one reduction per sum suffices (L >= span)
+                // (and only within one wave: above 64 pairs the later waves of the wave-wide walk
+                // have nearly equal ranges, and measured faster)
+                if (one && (L < span || pairs > 64)) continue;
+                const double gr = one ? std::ceil((span + R) / G) + 2.0 : groups;
+                const double reds = one ? 2.0 * R : reductions;
+                const double cost = waves * (gr * R * G + 4.0 * gr * (G + R - 1 + (one ? G : 0)) +
+                                             22.2 * reds * (2 * bs - 1)) +
+                                    43.0 * io + 75.0;
+                if (cost < best) {
+                    best = cost;
+                    best_bs = bs;
+                    *b_out = b;
+                    *L_out = L;
+                    *G_out = G;
+                    *R_out = R;
+                    *one_out = one != 0;
+                }
             }
         }
     }
@@ -368,7 +461,8 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
                             uint32_t block, uint8_t* out, hipStream_t s, bool check_only) {
     if (na > kLongMaxCoeffs || nb > kLongMaxCoeffs) return DQT_E_UNSUPPORTED;
     uint32_t bs = 0, b = 0, L = 0, G = 0, R = 0;
-    DQT_TRY(fqt_long_plan(p, na, nb, block, &bs, &b, &L, &G, &R));
+    bool one = false;
+    DQT_TRY(fqt_long_plan(p, na, nb, block, &bs, &b, &L, &G, &R, &one));
     LongArgs g;
     memset(&g, 0, sizeof(g));
     DQT_TRY(make_redq_args(p, b, 2 * bs - 1, (2 * bs - 1) * b, &g.ra));
@@ -413,39 +507,40 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     // block sizes the cost picks over F_3) have a compile-time q and residue width;
     // every other case the run-time form
     if (g.ra.w == 2 && G == 8 && ((bs == 3 && b == 10) || (bs == 2 && b == 17))) {
-#define DQT_LONG_F3(BSV, QBV, RV)                                                                                  \
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, 8, QBV, 2, RV>), dim3(grid), dim3(threads), smem, s, A, \
-                       B, out, count, g)
-        if (bs == 3) {
-            if (R == 8) DQT_LONG_F3(3, 10, 8);
-            else DQT_LONG_F3(3, 10, 4);
-        } else {
-            if (R == 8) DQT_LONG_F3(2, 17, 8);
-            else DQT_LONG_F3(2, 17, 4);
+#define DQT_LONG_F3(BSV, QBV, RV, ONEV)                                                                    \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, 8, QBV, 2, RV, ONEV>), dim3(grid), dim3(threads), \
+                       smem, s, A, B, out, count, g)
+        const unsigned k3 = (bs == 3 ? 4u : 0u) + (R == 8 ? 2u : 0u) + (one ? 1u : 0u);
+        switch (k3) {
+            case 0: DQT_LONG_F3(2, 17, 4, false); break;
+            case 1: DQT_LONG_F3(2, 17, 4, true); break;
+            case 2: DQT_LONG_F3(2, 17, 8, false); break;
+            case 3: DQT_LONG_F3(2, 17, 8, true); break;
+            case 4: DQT_LONG_F3(3, 10, 4, false); break;
+            case 5: DQT_LONG_F3(3, 10, 4, true); break;
+            case 6: DQT_LONG_F3(3, 10, 8, false); break;
+            default: DQT_LONG_F3(3, 10, 8, true); break;
         }
 #undef DQT_LONG_F3
         DQT_LAUNCH_CHECK("dqt_polymul_fqt_u8 (long)");
         return DQT_OK;
     }
-    const unsigned key = bs * 256 + G * 16 + R;
+    const unsigned key = bs * 1024 + G * 64 + R * 2 + (one ? 1u : 0u);
     switch (key) {
-#define DQT_LONG_CASE(BSV, GV, RV)                                                                                \
-    case BSV * 256 + GV * 16 + RV:                                                                                \
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, GV, 0, 0, RV>), dim3(grid), dim3(threads), smem, \
-                           s, A, B, out, count, g);                                                               \
+#define DQT_LONG_CASE(BSV, GV, RV, ONEV)                                                                          \
+    case BSV * 1024 + GV * 64 + RV * 2 + (ONEV ? 1 : 0):                                                          \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, GV, 0, 0, RV, ONEV>), dim3(grid), dim3(threads), \
+                           smem, s, A, B, out, count, g);                                                         \
         break;
-        DQT_LONG_CASE(2, 4, 4)
-        DQT_LONG_CASE(2, 8, 4)
-        DQT_LONG_CASE(3, 4, 4)
-        DQT_LONG_CASE(3, 8, 4)
-        DQT_LONG_CASE(4, 4, 4)
-        DQT_LONG_CASE(4, 8, 4)
-        DQT_LONG_CASE(2, 4, 8)
-        DQT_LONG_CASE(2, 8, 8)
-        DQT_LONG_CASE(3, 4, 8)
-        DQT_LONG_CASE(3, 8, 8)
-        DQT_LONG_CASE(4, 4, 8)
-        DQT_LONG_CASE(4, 8, 8)
+#define DQT_LONG_CASES(BSV, GV) \
+    DQT_LONG_CASE(BSV, GV, 4, false) DQT_LONG_CASE(BSV, GV, 4, true) DQT_LONG_CASE(BSV, GV, 8, false) DQT_LONG_CASE(BSV, GV, 8, true)
+        DQT_LONG_CASES(2, 4)
+        DQT_LONG_CASES(2, 8)
+        DQT_LONG_CASES(3, 4)
+        DQT_LONG_CASES(3, 8)
+        DQT_LONG_CASES(4, 4)
+        DQT_LONG_CASES(4, 8)
+#undef DQT_LONG_CASES
 #undef DQT_LONG_CASE
         default: return DQT_E_UNSUPPORTED;
     }

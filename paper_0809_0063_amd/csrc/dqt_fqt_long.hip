@@ -317,6 +317,7 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
 }
 
 // Plain per-coefficient products c_j = sum_i a_i b_{j-i}; chunk c owns j = 8c .. 8c + 7.
+template <bool ONE>
 __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                             uint8_t* __restrict__ OUT, uint64_t count, uint32_t na,
                                                             uint32_t nb, uint32_t p, uint32_t pmagic, uint32_t na_pad,
@@ -331,8 +332,12 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
     uint32_t* b32 = a32 + gapped<3>(na_pad);              // b32[gapped<3>(kPad + k)] = b_k, zeros around
     const uint32_t nout = na + nb - 1;
     const uint32_t C = (nout + R - 1) / R;
-    const uint32_t cs[2] = {pair, C - 1 - pair};
-    const int nc_all = pair < (C + 1) / 2 ? (cs[1] > pair ? 2 : 1) : 0;
+    // ONE: chunk c with chunk c + ceil(C/2), walked as one sequence per lane (as the FQT kernel's
+    // single walk); else chunk c with chunk C - 1 - c, each walked by a loop of its own. Either
+    // way the two chunks of a lane add up to about the same number of terms.
+    const uint32_t half = (C + 1) / 2;
+    const uint32_t cs[2] = {pair, ONE ? pair + half : C - 1 - pair};
+    const int nc_all = ONE ? (pair < half ? (cs[1] < C ? 2 : 1) : 0) : (pair < half ? (cs[1] > pair ? 2 : 1) : 0);
     for (uint64_t t0 = (uint64_t)blockIdx.x * ppw; t0 < count; t0 += (uint64_t)gridDim.x * ppw) {
         const uint64_t t = t0 + sub;
         const bool live = t < count;
@@ -345,32 +350,87 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
             b32[gapped<3>(k)] = (k >= kPad && k - kPad < nb) ? b[k - kPad] : 0u;
         __syncthreads();
         uint8_t* o = OUT + t * nout;
+        if (!ONE) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= nc) break;
+                const uint32_t j0 = cs[h] * R;
+                // i with 0 <= j - i < nb for some j in [j0, j0 + R): j0 - nb < i <= j0 + R - 1
+                const uint32_t ilo = j0 + 1 > nb ? j0 + 1 - nb : 0;
+                const uint32_t ihi = min(na - 1, j0 + R - 1);
+                uint32_t c[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) c[r] = 0;
+                for (uint32_t ig = ilo & ~(uint32_t)(G - 1); ig <= ihi; ig += G) {
+                    uint32_t av[G], wv[G + R - 1];
+#pragma unroll
+                    for (int s = 0; s < G; ++s) av[s] = a32[gapped<3>(ig) + s];   // ig = 0 mod 8
+                    // wv[x] = b_{j0 - ig - (G-1) + x}
+                    const uint32_t* wb = b32 + gapped<3>(kPad + j0 - ig - (G - 1));
+#pragma unroll
+                    for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<3>(x)];
+#pragma unroll
+                    for (int s = 0; s < G; ++s)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) c[r] = __umul24(av[s], wv[r - s + G - 1]) + c[r];
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (j0 + r < nout) o[j0 + r] = (uint8_t)mod_small(c[r] > 0xFFFFFFu ? c[r] % p : c[r], p, pmagic);
+            }
+            continue;
+        }
+        // the same ranges of i, for both chunks, then one loop over both
+        uint32_t lo[2] = {0, 0}, ng[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nc) continue;
+            const uint32_t j0 = cs[h] * R;
+            const uint32_t ilo = j0 + 1 > nb ? j0 + 1 - nb : 0;
+            const uint32_t ihi = min(na - 1, j0 + R - 1);
+            lo[h] = ilo & ~(uint32_t)(G - 1);
+            ng[h] = ihi >= lo[h] ? (ihi - lo[h]) / G + 1 : 0;
+        }
+        uint32_t c[R], cA[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) c[r] = cA[r] = 0;
+        const uint32_t ntot = ng[0] + ng[1];
+        for (uint32_t k = 0; k < ntot; ++k) {
+            const bool inA = k < ng[0];
+            if (k == ng[0]) {   // the first chunk is done: keep its sums, start the second
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    cA[r] = c[r];
+                    c[r] = 0;
+                }
+            }
+            const uint32_t ig = inA ? lo[0] + k * G : lo[1] + (k - ng[0]) * G;
+            const uint32_t j0 = (inA ? cs[0] : cs[1]) * R;
+            uint32_t av[G], wv[G + R - 1];
+#pragma unroll
+            for (int s = 0; s < G; ++s) av[s] = a32[gapped<3>(ig) + s];   // ig = 0 mod 8
+            // wv[x] = b_{j0 - ig - (G-1) + x}
+            const uint32_t* wb = b32 + gapped<3>(kPad + j0 - ig - (G - 1));
+#pragma unroll
+            for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<3>(x)];
+#pragma unroll
+            for (int s = 0; s < G; ++s)
+#pragma unroll
+                for (int r = 0; r < R; ++r) c[r] = __umul24(av[s], wv[r - s + G - 1]) + c[r];
+        }
+        if (ng[1] == 0) {   // one chunk only: its sums are still in c
+#pragma unroll
+            for (int r = 0; r < R; ++r) cA[r] = c[r];
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h >= nc) break;
             const uint32_t j0 = cs[h] * R;
-            // i with 0 <= j - i < nb for some j in [j0, j0 + R): j0 - nb < i <= j0 + R - 1
-            const uint32_t ilo = j0 + 1 > nb ? j0 + 1 - nb : 0;
-            const uint32_t ihi = min(na - 1, j0 + R - 1);
-            uint32_t c[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) c[r] = 0;
-            for (uint32_t ig = ilo & ~(uint32_t)(G - 1); ig <= ihi; ig += G) {
-                uint32_t av[G], wv[G + R - 1];
-#pragma unroll
-                for (int s = 0; s < G; ++s) av[s] = a32[gapped<3>(ig) + s];   // ig = 0 mod 8
-                // wv[x] = b_{j0 - ig - (G-1) + x}
-                const uint32_t* wb = b32 + gapped<3>(kPad + j0 - ig - (G - 1));
-#pragma unroll
-                for (int x = 0; x < G + R - 1; ++x) wv[x] = wb[gap_off<3>(x)];
-#pragma unroll
-                for (int s = 0; s < G; ++s)
-#pragma unroll
-                    for (int r = 0; r < R; ++r) c[r] = __umul24(av[s], wv[r - s + G - 1]) + c[r];
+            for (int r = 0; r < R; ++r) {
+                const uint32_t v = h == 0 ? cA[r] : c[r];
+                if (j0 + r < nout) o[j0 + r] = (uint8_t)mod_small(v > 0xFFFFFFu ? v % p : v, p, pmagic);
             }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (j0 + r < nout) o[j0 + r] = (uint8_t)mod_small(c[r] > 0xFFFFFFu ? c[r] % p : c[r], p, pmagic);
         }
     }
 }
@@ -576,8 +636,14 @@ dqt_status plain_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, u
     const size_t smem = (size_t)ppw * slot_words * 4;
     if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
     const unsigned grid = stream_grid((count + ppw - 1) / ppw, 1, groups_per_cu(smem, threads));
-    hipLaunchKernelGGL(k_polymul_plain_long, dim3(grid), dim3(threads), smem, s, A, B, out, count, na, nb, p, pmagic,
-                       na_pad, nb_tot, tpp, ppw, slot_words);
+    // the single walk pays off while the chunk pairs fit one wave (measured from 65 to 4096
+    // coefficients, as for the FQT kernel); with more, the two loops per lane are faster
+    if (pairs <= 64)
+        hipLaunchKernelGGL(k_polymul_plain_long<true>, dim3(grid), dim3(threads), smem, s, A, B, out, count, na, nb, p,
+                           pmagic, na_pad, nb_tot, tpp, ppw, slot_words);
+    else
+        hipLaunchKernelGGL(k_polymul_plain_long<false>, dim3(grid), dim3(threads), smem, s, A, B, out, count, na, nb, p,
+                           pmagic, na_pad, nb_tot, tpp, ppw, slot_words);
     DQT_LAUNCH_CHECK("dqt_polymul_plain_u8 (long)");
     return DQT_OK;
 }

@@ -417,10 +417,12 @@ def test_gf_dot_many_long(dqt):
 @pytest.mark.parametrize("p", [2, 3, 5, 7, 13, 31, 127])
 def test_fqt_long_products(dqt, p):
     """Products of more than 64 coefficients (one workgroup per product, chunked packed sums) and the plain
-    comparator at the same lengths, up to 4096 coefficients, the all-(p-1) case included."""
+    comparator at the same lengths, up to 4096 coefficients, the all-(p-1) case included; 512 and 520
+    coefficients sit either side of the plain kernel's switch between its two walks (64 chunk pairs)."""
     g = np.random.default_rng(7000 + p)
     for na, nb, count in [(65, 65, 300), (100, 200, 100), (256, 255, 64), (500, 500, 40), (1000, 1024, 9),
-                          (4096, 4096, 3), (65, 4096, 5), (3000, 70, 5)]:
+                          (4096, 4096, 3), (65, 4096, 5), (3000, 70, 5),
+                          (512, 512, 12), (520, 520, 12)]:
         a = g.integers(0, p, size=(count, na), dtype=np.uint8)
         b = g.integers(0, p, size=(count, nb), dtype=np.uint8)
         a[0] = p - 1

@@ -16,11 +16,12 @@
 // Work split (both kernels): a thread owns R consecutive outputs (output
 // blocks for the FQT, coefficients for the plain one), a "chunk".  The number
 // of terms of a chunk rises and falls along the product, so chunk c is paired
-// with chunk C-1-c on the same thread: every thread then has about the same
-// number of terms, and one pair per thread covers products of up to 4096
-// coefficients with at most 512 threads.  A product of more than 32 chunk
-// pairs has a workgroup to itself; shorter ones share a wave, each with a
-// power-of-two group of lanes and its own slot of LDS.  The
+// with chunk C-1-c (or, within one wave, with chunk c + C/2) on the same
+// thread: every thread then has about the same number of terms, and one pair
+// per thread covers products of up to 4096 coefficients with at most 512
+// threads.  A product of more than 32 chunk pairs has a workgroup to itself;
+// shorter ones share a wave, as many as have a lane for each of their pairs
+// (64 / pairs of them), each with its own slot of LDS.  The
 // terms are taken G at a time: G values of a and the G+R-1 values of b that
 // meet them are read from LDS once and used G R times.  The operands sit in LDS
 // between zeros, so groups that overlap the ends of the operands need no test.
@@ -31,6 +32,8 @@
 
 #include <string.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 
 #include "dqt_internal.h"
@@ -67,7 +70,9 @@ struct LongArgs {
     uint32_t C;                     // chunks of R output blocks (block NW, all zero, included)
     uint32_t na_pad, nb_tot;        // doubles of A (a multiple of G) and of B with its zeros
     uint32_t lds_a, lds_b, lds_bnd; // byte offsets in LDS: A words, B words, last residues of each chunk
-    uint32_t tpp, ppw, pp_bytes;    // threads per product, products per workgroup, LDS bytes per product
+    uint32_t tpp, ppw, pp_bytes;    // threads per product, products per wave (1 above 64 threads),
+                                    // LDS bytes per product
+    uint32_t ppg;                   // products per workgroup
     RedqArgs ra;
 };
 
@@ -108,10 +113,16 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
     constexpr int GS = long_gap_shift(R, G);
     extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
     uint16_t* tab = reinterpret_cast<uint16_t*>(lsm);
-    // products with few chunk pairs share a wave: tpp threads (a power of two) per product,
-    // each product with its own LDS slot
-    const uint32_t sub = threadIdx.x / g.tpp;
-    const uint32_t pair = threadIdx.x - sub * g.tpp;
+    // Products of up to 64 chunk pairs share waves (tpp <= 64): each wave of the workgroup holds
+    // ppw products of tpp lanes, the lanes past ppw tpp (when tpp does not divide 64) take none,
+    // and the waves share the correction table.  A larger product (tpp = blockDim.x > 64) has
+    // the workgroup to itself.  Each product has its own LDS slot.
+    const bool shared = g.tpp <= 64;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t subw = shared ? lane / g.tpp : 0;
+    const uint32_t pair = shared ? lane - subw * g.tpp : threadIdx.x;
+    const bool has_slot = subw < g.ppw;
+    const uint32_t sub = (shared ? (threadIdx.x >> 6) * g.ppw : 0) + (has_slot ? subw : 0);
     uint8_t* slot = lsm + g.lds_a + sub * g.pp_bytes;
     double* ad = reinterpret_cast<double*>(slot);
     double* bd = reinterpret_cast<double*>(slot + (g.lds_b - g.lds_a));   // bd[gapped<GS>(kPad + i)] = B_i
@@ -138,9 +149,9 @@ __global__ __launch_bounds__(512) void k_polymul_fqt_long(const uint8_t* __restr
             W[r] = 0.0;
         }
     };
-    for (uint64_t t0 = (uint64_t)blockIdx.x * g.ppw; t0 < count; t0 += (uint64_t)gridDim.x * g.ppw) {
+    for (uint64_t t0 = (uint64_t)blockIdx.x * g.ppg; t0 < count; t0 += (uint64_t)gridDim.x * g.ppg) {
         const uint64_t t = t0 + sub;
-        const bool live = t < count;
+        const bool live = has_slot && t < count;
         const int nc = live ? nc_all : 0;
         __syncthreads();   // the table is built / the previous products have left LDS
         const uint8_t* a = A + (live ? t : 0) * g.na;
@@ -325,10 +336,12 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
                                                             uint32_t slot_words) {
     constexpr int R = kPlainR, G = kPlainG;
     extern __shared__ __attribute__((aligned(16))) uint8_t lsm[];
-    // as in the FQT kernel: tpp threads and one LDS slot per product, ppw products per workgroup
+    // as in the FQT kernel: tpp threads and one LDS slot per product, ppw products per workgroup,
+    // no product on the lanes past ppw tpp
     const uint32_t sub = threadIdx.x / tpp;
     const uint32_t pair = threadIdx.x - sub * tpp;
-    uint32_t* a32 = reinterpret_cast<uint32_t*>(lsm) + sub * slot_words;   // a32[gapped<3>(i)] = a_i, zeros up to na_pad
+    const bool has_slot = sub < ppw;
+    uint32_t* a32 = reinterpret_cast<uint32_t*>(lsm) + (has_slot ? sub : 0) * slot_words;   // a32[gapped<3>(i)] = a_i, zeros up to na_pad
     uint32_t* b32 = a32 + gapped<3>(na_pad);              // b32[gapped<3>(kPad + k)] = b_k, zeros around
     const uint32_t nout = na + nb - 1;
     const uint32_t C = (nout + R - 1) / R;
@@ -340,7 +353,7 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
     const int nc_all = ONE ? (pair < half ? (cs[1] < C ? 2 : 1) : 0) : (pair < half ? (cs[1] > pair ? 2 : 1) : 0);
     for (uint64_t t0 = (uint64_t)blockIdx.x * ppw; t0 < count; t0 += (uint64_t)gridDim.x * ppw) {
         const uint64_t t = t0 + sub;
-        const bool live = t < count;
+        const bool live = has_slot && t < count;
         const int nc = live ? nc_all : 0;
         __syncthreads();
         const uint8_t* a = A + (live ? t : 0) * na;
@@ -437,6 +450,90 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 
 }  // namespace
 
+static constexpr uint32_t kLongMaxCoeffs = 4096;
+static constexpr uint32_t kLongTableBytes = 4096 * 2;   // the correction table, at the start of LDS
+
+// LDS layout and launch shape of a long product for one block size, group width G and chunk size R.
+struct LongShape {
+    uint32_t Na, Nb, NW, C, pairs;
+    uint32_t na_pad, nb_tot, lds_b, lds_bnd, pp_bytes;
+    uint32_t tpp, ppw, ppg, threads;
+    size_t smem;
+};
+
+static LongShape long_shape(uint32_t na, uint32_t nb, uint32_t bs, uint32_t G, uint32_t R) {
+    LongShape h;
+    h.Na = (na + bs - 1) / bs;
+    h.Nb = (nb + bs - 1) / bs;
+    h.NW = h.Na + h.Nb - 1;
+    // chunks of R output blocks (blocks 0 .. NW; block NW only carries the top residues of NW-1)
+    h.C = (h.NW + 1 + R - 1) / R;
+    h.pairs = (h.C + 1) / 2;   // one chunk pair per thread
+    h.na_pad = (h.Na + G - 1) / G * G;
+    h.nb_tot = kPad + h.Nb + kPad;
+    h.lds_b = kLongTableBytes + h.na_pad * 8;
+    h.lds_bnd = h.lds_b + ((gapped_n(long_gap_shift(R, G), h.nb_tot) * 8 + 15) & ~15u);
+    h.pp_bytes = (uint32_t)((h.lds_bnd - kLongTableBytes + (size_t)h.C * 8 + 15) & ~(size_t)15);
+    if (h.pairs <= 64) {
+        // Shared waves: 64 / pairs products per wave (a thread for each chunk pair; each product
+        // given 64 / ppw threads, the spare ones only stage) and four waves per workgroup sharing
+        // one correction table (two or one where their slots would pass 64 KiB of LDS).  With a
+        // table per wave, LDS held the kernel to a few waves per CU at these sizes.
+        uint32_t wpg = 4;
+        h.ppw = h.pairs <= 32 ? 64 / h.pairs : 1;
+        while (h.ppw > 1 && kLongTableBytes + (size_t)h.ppw * h.pp_bytes > 65536) --h.ppw;
+        while (wpg > 1 && kLongTableBytes + (size_t)wpg * h.ppw * h.pp_bytes > 65536) wpg /= 2;
+        h.tpp = 64 / h.ppw;
+        h.ppg = wpg * h.ppw;
+        h.threads = 64 * wpg;
+    } else {
+        h.threads = (h.pairs + 63) / 64 * 64;
+        h.tpp = h.threads;
+        h.ppw = 1;
+        h.ppg = 1;
+    }
+    h.smem = kLongTableBytes + (size_t)h.ppg * h.pp_bytes;
+    return h;
+}
+
+// F_3 (residues of 2 bits) in blocks of three at q = 2^10 or of two at q = 2^17 (the block
+// sizes the cost picks over F_3) have instances with a compile-time q and residue width.
+static bool long_f3(uint32_t p, uint32_t bs, uint32_t b, uint32_t G) {
+    return p == 3 && G == 8 && ((bs == 3 && b == 10) || (bs == 2 && b == 17));
+}
+
+// Vector registers per lane of each instance (its kernel attribute, read once; 128 where it
+// cannot be read), for the occupancy term of the cost estimate.
+static int long_regs(uint32_t bs, uint32_t G, uint32_t R, bool one, bool f3) {
+    static const std::array<int, 64> regs = [] {
+        std::array<int, 64> r;
+        r.fill(128);
+        auto put = [&](int idx, const void* fn) {
+            hipFuncAttributes at;
+            if (hipFuncGetAttributes(&at, fn) == hipSuccess && at.numRegs > 0) r[idx] = at.numRegs;
+            else (void)hipGetLastError();
+        };
+#define DQT_REGS(BSV, GV, QBV, QWV, RV, ONEV, F3V)                                                             \
+    put((((BSV - 2) * 2 + (GV == 8)) * 2 + (RV == 8)) * 4 + (ONEV ? 2 : 0) + (F3V ? 1 : 0),                   \
+        reinterpret_cast<const void*>(&k_polymul_fqt_long<BSV, GV, QBV, QWV, RV, ONEV>))
+#define DQT_REGS4(BSV, GV, QBV, QWV, F3V)                                                                      \
+    DQT_REGS(BSV, GV, QBV, QWV, 4, false, F3V); DQT_REGS(BSV, GV, QBV, QWV, 4, true, F3V);                     \
+    DQT_REGS(BSV, GV, QBV, QWV, 8, false, F3V); DQT_REGS(BSV, GV, QBV, QWV, 8, true, F3V)
+        DQT_REGS4(2, 8, 17, 2, true);
+        DQT_REGS4(3, 8, 10, 2, true);
+        DQT_REGS4(2, 4, 0, 0, false);
+        DQT_REGS4(2, 8, 0, 0, false);
+        DQT_REGS4(3, 4, 0, 0, false);
+        DQT_REGS4(3, 8, 0, 0, false);
+        DQT_REGS4(4, 4, 0, 0, false);
+        DQT_REGS4(4, 8, 0, 0, false);
+#undef DQT_REGS4
+#undef DQT_REGS
+        return r;
+    }();
+    return regs[(((bs - 2) * 2 + (G == 8)) * 2 + (R == 8)) * 4 + (one ? 2 : 0) + (f3 ? 1 : 0)];
+}
+
 // Block size, q, L, the group width G and the chunk size R of a long product:
 // the smallest estimated cost over block sizes 2..4 (the 2 BS - 1 residues of a
 // block stay within the eight byte lanes of one word) and chunks of R = 4 or 8
@@ -444,14 +541,16 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 // products per reduction.  p <= 127 (two residues add within a byte lane).  The
 // estimate counts what section 5.3's model counts, block products and
 // reductions, the way the kernel runs them, in units of one lane's binary64 FMA:
-// per wave (or per share of a wave, for products of up to 32 chunk pairs), two
-// phases of about Na / G term groups of G R FMAs and G + R - 1 B words read
-// from LDS (about 4 each), and per phase a REDQ_{2BS-1} of each of the R sums
-// at every L-th term and at the end (about 22 (2 BS - 1) each); plus the
-// product's own loads and stores (43 per 64 bytes) and 75 for its set-up.  The
-// weights are a least-squares fit of measured times over F_3 (n = 65 .. 2048,
-// both chunk sizes, every block size); the choice they give was the measured
-// fastest, or within 6% of it, at every measured n.
+// per wave (or per share of a wave, for products of up to 32 chunk pairs), about
+// Na / G term groups per phase of G R FMAs and G + R - 1 B words read from LDS,
+// and a REDQ_{2BS-1} of each of the R sums at every L-th term and at the end
+// (about 9 (2 BS - 1) FMAs' worth each); that divided by the waves per SIMD
+// that registers and LDS let the launch keep resident (counted up to three: at
+// these sizes the kernel waits on LDS and memory, and fewer waves hide less of
+// it); plus the product's own loads and stores (12 per 64 bytes) and 24 for its
+// set-up.  The weights are a least-squares fit of measured times over F_3
+// (n = 65 .. 2048, both chunk sizes, both walks, every block size); the choice
+// they give was within 10% of the measured fastest at every measured n.
 dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out,
                          uint32_t* L_out, uint32_t* G_out, uint32_t* R_out, bool* one_out) {
     if (p > 127) return DQT_E_UNSUPPORTED;
@@ -465,31 +564,33 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
         if (nq < 4) continue;
         const uint32_t G = nq >= 8 ? 8 : 4;
         const uint32_t L = (uint32_t)(nq / G) * G;
-        const uint32_t Na = (na + bs - 1) / bs, Nb = (nb + bs - 1) / bs, NW = Na + Nb - 1;
         for (uint32_t R = 4; R <= 8; R += 4) {
-            const uint32_t C = (NW + 1 + R - 1) / R;
-            // waves per product: up to 32 chunk pairs share a wave (a power-of-two group of lanes)
-            const uint32_t pairs = (C + 1) / 2;
-            if (pairs > 512) continue;
-            uint32_t lanes = 1;
-            while (lanes < pairs) lanes *= 2;
-            const double waves = pairs <= 32 ? lanes / 64.0 : (double)((pairs + 63) / 64);
-            const double span = (double)(Na < Nb ? Na : Nb);
+            const LongShape h = long_shape(na, nb, bs, G, R);
+            if (h.pairs > 512 || h.threads > 512 || h.smem > 65536) continue;
+            // waves per product (a share of one below 65 chunk pairs)
+            const double waves = h.pairs <= 64 ? 1.0 / h.ppw : h.threads / 64.0;
+            const double span = (double)(h.Na < h.Nb ? h.Na : h.Nb);
             const double groups = 2.0 * std::ceil(span / G);
             const double reductions = 2.0 * (std::floor((span - 1) / L) + 1.0) * R;
             const double io = (na + nb + 2.0 * (na + nb - 1)) / 64.0;
+            const uint32_t wpg = h.threads / 64;
             for (int one = 0; one <= 1; ++one) {
                 // one sequence per lane over balanced chunks: about (span + R) / G groups per
                 // lane instead of two wave-wide walks of span / G, but A words read per lane
                 // (not broadcast); only where one reduction per sum suffices (L >= span)
                 // (and only within one wave: above 64 pairs the later waves of the wave-wide walk
                 // have nearly equal ranges, and measured faster)
-                if (one && (L < span || pairs > 64)) continue;
+                if (one && (L < span || h.pairs > 64)) continue;
+                const int regs = long_regs(bs, G, R, one != 0, long_f3(p, bs, b, G));
+                const uint32_t by_regs = 512u / (uint32_t)((regs + 7) / 8 * 8);   // waves per SIMD
+                const uint32_t groups_cu = std::min<uint32_t>((uint32_t)((160u * 1024u) / h.smem), 4u * by_regs / wpg);
+                const double resident = std::max(0.25, std::min(3.0, groups_cu * wpg / 4.0));
                 const double gr = one ? std::ceil((span + R) / G) + 2.0 : groups;
                 const double reds = one ? 2.0 * R : reductions;
-                const double cost = waves * (gr * R * G + 4.0 * gr * (G + R - 1 + (one ? G : 0)) +
-                                             22.2 * reds * (2 * bs - 1)) +
-                                    43.0 * io + 75.0;
+                const double cost = waves * 3.0 / resident *
+                                        (gr * R * G + 0.699 * gr * (G + R - 1 + (one ? G : 0)) +
+                                         9.24 * reds * (2 * bs - 1)) +
+                                    12.3 * io + 23.5;
                 if (cost < best) {
                     best = cost;
                     best_bs = bs;
@@ -506,8 +607,6 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
     *bs_out = best_bs;
     return DQT_OK;
 }
-
-static constexpr uint32_t kLongMaxCoeffs = 4096;
 
 // Workgroups per CU that the LDS (160 KiB) and the wave slots allow.
 static unsigned groups_per_cu(size_t smem, unsigned threads) {
@@ -531,42 +630,27 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     g.nb = nb;
     g.nout = na + nb - 1;
     g.b = b;
-    g.Na = (na + bs - 1) / bs;
-    g.Nb = (nb + bs - 1) / bs;
-    g.NW = g.Na + g.Nb - 1;
     g.L = L;
-    // chunks of R output blocks (blocks 0 .. NW; block NW only carries the top residues of NW-1)
-    g.C = (g.NW + 1 + R - 1) / R;
-    g.na_pad = (g.Na + G - 1) / G * G;
-    g.nb_tot = kPad + g.Nb + kPad;
-    g.lds_a = 4096 * 2;                        // the correction table
-    g.lds_b = g.lds_a + g.na_pad * 8;
-    g.lds_bnd = g.lds_b + ((gapped_n(long_gap_shift(R, G), g.nb_tot) * 8 + 15) & ~15u);
-    const uint32_t pairs = (g.C + 1) / 2;   // one chunk pair per thread
-    unsigned threads;
-    g.pp_bytes = (uint32_t)((g.lds_bnd - g.lds_a + (size_t)g.C * 8 + 15) & ~(size_t)15);
-    if (pairs <= 32) {
-        // several products per wave of 64 threads
-        g.tpp = 1;
-        while (g.tpp < pairs) g.tpp *= 2;
-        g.ppw = 64 / g.tpp;
-        while (g.ppw > 1 && g.lds_a + (size_t)g.ppw * g.pp_bytes > 65536) {
-            g.ppw /= 2;
-            g.tpp *= 2;
-        }
-        threads = 64;
-    } else {
-        threads = (pairs + 63) / 64 * 64;
-        g.tpp = threads;
-        g.ppw = 1;
-    }
-    const size_t smem = g.lds_a + (size_t)g.ppw * g.pp_bytes;
+    const LongShape h = long_shape(na, nb, bs, G, R);
+    g.Na = h.Na;
+    g.Nb = h.Nb;
+    g.NW = h.NW;
+    g.C = h.C;
+    g.na_pad = h.na_pad;
+    g.nb_tot = h.nb_tot;
+    g.lds_a = kLongTableBytes;
+    g.lds_b = h.lds_b;
+    g.lds_bnd = h.lds_bnd;
+    g.pp_bytes = h.pp_bytes;
+    g.tpp = h.tpp;
+    g.ppw = h.ppw;
+    g.ppg = h.ppg;
+    const unsigned threads = h.threads;
+    const size_t smem = h.smem;
     if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
-    const unsigned grid = stream_grid((count + g.ppw - 1) / g.ppw, 1, groups_per_cu(smem, threads));
-    // F_3 (residues of 2 bits) in blocks of three at q = 2^10 or of two at q = 2^17 (the
-    // block sizes the cost picks over F_3) have a compile-time q and residue width;
-    // every other case the run-time form
-    if (g.ra.w == 2 && G == 8 && ((bs == 3 && b == 10) || (bs == 2 && b == 17))) {
+    const unsigned grid = stream_grid((count + g.ppg - 1) / g.ppg, 1, groups_per_cu(smem, threads));
+    // the F_3 instances with a compile-time q and residue width, else the run-time form
+    if (long_f3(p, bs, b, G)) {
 #define DQT_LONG_F3(BSV, QBV, RV, ONEV)                                                                    \
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_polymul_fqt_long<BSV, 8, QBV, 2, RV, ONEV>), dim3(grid), dim3(threads), \
                        smem, s, A, B, out, count, g)
@@ -620,13 +704,9 @@ dqt_status plain_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, u
     unsigned threads;
     uint32_t tpp, ppw;
     if (pairs <= 32) {
-        tpp = 1;
-        while (tpp < pairs) tpp *= 2;
-        ppw = 64 / tpp;
-        while (ppw > 1 && (size_t)ppw * slot_words * 4 > 65536) {
-            ppw /= 2;
-            tpp *= 2;
-        }
+        ppw = 64 / pairs;
+        while (ppw > 1 && (size_t)ppw * slot_words * 4 > 65536) --ppw;
+        tpp = 64 / ppw;
         threads = 64;
     } else {
         threads = (pairs + 63) / 64 * 64;

@@ -436,7 +436,8 @@ def test_fqt_long_products(dqt, p):
 
 @pytest.mark.parametrize("p", [3, 7, 127])
 def test_long_products_several_per_workgroup(dqt, p):
-    """Short long products share a wave (a power-of-two group of lanes and an LDS slot per product):
+    """Short long products share a wave (64 / pairs products, a group of lanes and an LDS slot each,
+    lanes left over when the group size does not divide 64):
     batch sizes that leave the last workgroup partly empty, results between sentinel bytes, for the
     FQT and the plain comparator."""
     import torch

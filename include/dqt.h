@@ -273,8 +273,9 @@ dqt_status dqt_gf_mul_plain_u8(const uint8_t *d_a, const uint8_t *d_b, uint64_t 
  * coefficients each, a thread computes a product and every output block holds
  * all its block products in one word.  Above that, and at up to 64 where no
  * block size keeps such a sum in one word and block = 0 (p <= 127, block
- * 2..4), one workgroup (or, for products of up to 32 pairs of four-block
- * chunks, a group of lanes of one wave) computes a product: the block words of both operands sit in LDS,
+ * 2..4), one workgroup (or, for products of up to 64 pairs of chunks, a
+ * group of lanes of one wave, four waves sharing a workgroup) computes a
+ * product: the block words of both operands sit in LDS,
  * each output block is summed n_q block products at a time
  * (q > n_q (d+1)(p-1)^2, eq:bounds, with (2d+1) log2 q <= 51), with one
  * REDQ_{2d+1} per such sum and the sums' residues added mod p; the block size

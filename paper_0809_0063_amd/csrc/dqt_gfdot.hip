@@ -238,13 +238,16 @@ static dqt_status launch_gf_dot(const uint8_t* A, const uint8_t* B, uint8_t* out
 
 // Matrix products over GF(p^k) by FGDP: C[i][j] = sum_l A[i][l] B[l][j], each
 // entry a dot product of packed field elements (section 6).  A workgroup of 256
-// threads takes a 64 x 32 tile of C, a thread 4 rows x 2 columns of it; A and B
-// pass through LDS in steps of 16 along l, each element packed once into a
-// 32-bit word with fields of B bits (the same q = 2^B as the dot products).
-// Every output of a thread receives one product per step of l, so the packed
-// sums of all eight reach n_q together and are reduced together (REDQ, the two
-// tables, the sums in 16-bit lanes as in k_gf_dot).
-constexpr int kGmRows = 64, kGmCols = 32, kGmK = 16;
+// threads takes a 16 TR x 16 TC tile of C, a thread TR rows x TC columns of it
+// (4 x 2 where the grid has enough tiles, down to 1 x 1 for small products, so
+// that every SIMD gets waves: each product costs a reduction, there is little to
+// share between the outputs of a thread); A and B pass through LDS in steps of
+// 16 along l, each element packed once into a 32-bit word with fields of B bits
+// (the same q = 2^B as the dot products).  Every output of a thread receives
+// one product per step of l, so the packed sums of all of them reach n_q
+// together and are reduced together (REDQ, the two tables, the sums in 16-bit
+// lanes as in k_gf_dot).
+constexpr int kGmRows = 64, kGmCols = 32, kGmK = 16;   // the largest tile
 
 template <int K>
 __device__ __forceinline__ uint32_t element_word(const uint8_t* e) {
@@ -255,35 +258,36 @@ __device__ __forceinline__ uint32_t element_word(const uint8_t* e) {
     return v;
 }
 
-template <int K, bool NQ1>
+template <int K, bool NQ1, int TR, int TC>
 __global__ __launch_bounds__(256) void k_gf_matmul(const uint8_t* __restrict__ A, const uint8_t* __restrict__ Bm,
                                                    uint8_t* __restrict__ OUT, uint32_t m, uint32_t n, uint32_t kd,
                                                    uint32_t nq, RedqArgs ra, GfArgs ga) {
     constexpr int B = 53 / (2 * K - 1);
+    constexpr int ROWS = 16 * TR, COLS = 16 * TC;
     extern __shared__ uint64_t gfm_smem[];
     const uint32_t tn = 1u << (K * ra.w);
     uint64_t* tl = gfm_smem;
     uint64_t* th = gfm_smem + tn;
-    uint32_t* la = reinterpret_cast<uint32_t*>(gfm_smem + 2 * tn);   // [kGmK][kGmRows]
-    uint32_t* lb = la + kGmK * kGmRows;                                // [kGmK][kGmCols]
+    uint32_t* la = reinterpret_cast<uint32_t*>(gfm_smem + 2 * tn);   // [kGmK][ROWS]
+    uint32_t* lb = la + kGmK * ROWS;                                   // [kGmK][COLS]
     build_gf_tables_dot<K>(tl, th, ra, ga);
     const uint64_t ones = 0x0101010101010101ull >> (8 * (8 - K));
     constexpr uint64_t kEven = 0x00FF00FF00FF00FFull;
     const uint32_t wm = (1u << ra.w) - 1u;
     const uint32_t fold_at = 65535u / (2u * (ra.p - 1u));
     const uint32_t tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
-    const uint32_t row0 = blockIdx.y * kGmRows, col0 = blockIdx.x * kGmCols;
-    uint64_t acc[4][2], RE[4][2], RO[4][2], R[4][2];
+    const uint32_t row0 = blockIdx.y * ROWS, col0 = blockIdx.x * COLS;
+    uint64_t acc[TR][TC], RE[TR][TC], RO[TR][TC], R[TR][TC];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = RE[i][j] = RO[i][j] = R[i][j] = 0;
+        for (int j = 0; j < TC; ++j) acc[i][j] = RE[i][j] = RO[i][j] = R[i][j] = 0;
     uint32_t cnt = 0, nred = 0;
     auto reduce = [&]() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TR; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < TC; ++j) {
                 const uint64_t U = redq_compress(acc[i][j], ra);
                 const uint32_t xl = (uint32_t)U, xh = (uint32_t)(U >> (B * (K - 1)));
                 uint32_t il = 0, ih = 0;
@@ -300,9 +304,9 @@ __global__ __launch_bounds__(256) void k_gf_matmul(const uint8_t* __restrict__ A
         cnt = 0;
         if (++nred == fold_at) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TR; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < TC; ++j) {
                     R[i][j] = add_mod_bytes(R[i][j], fold16<K>(RE[i][j], RO[i][j], ra.p, ra.pmagic), ra.p, ones);
                     RE[i][j] = RO[i][j] = 0;
                 }
@@ -311,37 +315,39 @@ __global__ __launch_bounds__(256) void k_gf_matmul(const uint8_t* __restrict__ A
     };
     for (uint32_t k0 = 0; k0 < kd; k0 += kGmK) {
         __syncthreads();   // the tables are built / the previous step's words are used
-        for (uint32_t e = tid; e < kGmRows * kGmK; e += 256) {
+        for (uint32_t e = tid; e < ROWS * kGmK; e += 256) {
             const uint32_t r = e / kGmK, kk = e % kGmK;
             const uint32_t row = row0 + r, l = k0 + kk;
-            la[kk * kGmRows + r] = row < m && l < kd ? element_word<K>(A + ((uint64_t)row * kd + l) * K) : 0u;
+            la[kk * ROWS + r] = row < m && l < kd ? element_word<K>(A + ((uint64_t)row * kd + l) * K) : 0u;
         }
-        for (uint32_t e = tid; e < kGmCols * kGmK; e += 256) {
-            const uint32_t kk = e / kGmCols, c = e % kGmCols;
+        for (uint32_t e = tid; e < COLS * kGmK; e += 256) {
+            const uint32_t kk = e / COLS, c = e % COLS;
             const uint32_t col = col0 + c, l = k0 + kk;
-            lb[kk * kGmCols + c] = col < n && l < kd ? element_word<K>(Bm + ((uint64_t)l * n + col) * K) : 0u;
+            lb[kk * COLS + c] = col < n && l < kd ? element_word<K>(Bm + ((uint64_t)l * n + col) * K) : 0u;
         }
         __syncthreads();
         const uint32_t steps = min((uint32_t)kGmK, kd - k0);
         for (uint32_t kk = 0; kk < steps; ++kk) {
-            const uint4 a4 = *reinterpret_cast<const uint4*>(la + kk * kGmRows + ty * 4);
-            const uint2 b2 = *reinterpret_cast<const uint2*>(lb + kk * kGmCols + tx * 2);
-            const uint32_t av[4] = {a4.x, a4.y, a4.z, a4.w}, bv[2] = {b2.x, b2.y};
+            uint32_t av[TR], bv[TC];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TR; ++i) av[i] = la[kk * ROWS + ty * TR + i];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] += (uint64_t)av[i] * bv[j];
+            for (int j = 0; j < TC; ++j) bv[j] = lb[kk * COLS + tx * TC + j];
+#pragma unroll
+            for (int i = 0; i < TR; ++i)
+#pragma unroll
+                for (int j = 0; j < TC; ++j) acc[i][j] += (uint64_t)av[i] * bv[j];
             if (NQ1 || ++cnt == nq) reduce();
         }
     }
     if (!NQ1 && cnt) reduce();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t row = row0 + ty * 4 + i;
+    for (int i = 0; i < TR; ++i) {
+        const uint32_t row = row0 + ty * TR + i;
         if (row >= m) continue;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const uint32_t col = col0 + tx * 2 + j;
+        for (int j = 0; j < TC; ++j) {
+            const uint32_t col = col0 + tx * TC + j;
             if (col >= n) continue;
             const uint64_t r = add_mod_bytes(R[i][j], fold16<K>(RE[i][j], RO[i][j], ra.p, ra.pmagic), ra.p, ones);
             uint8_t* o = OUT + ((uint64_t)row * n + col) * K;
@@ -351,17 +357,33 @@ __global__ __launch_bounds__(256) void k_gf_matmul(const uint8_t* __restrict__ A
     }
 }
 
+template <int K, int TR, int TC>
+static void launch_gf_matmul_tile(const uint8_t* A, const uint8_t* B, uint8_t* out, uint32_t m, uint32_t n,
+                                  uint32_t kd, uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
+    const size_t smem = 2ull * (1ull << (K * ra.w)) * sizeof(uint64_t) + (size_t)kGmK * 16 * (TR + TC) * 4;
+    const dim3 grid((n + 16 * TC - 1) / (16 * TC), (m + 16 * TR - 1) / (16 * TR));
+    if (nq == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_matmul<K, true, TR, TC>), grid, dim3(256), smem, s, A, B, out, m, n,
+                           kd, nq, ra, ga);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_matmul<K, false, TR, TC>), grid, dim3(256), smem, s, A, B, out, m, n,
+                           kd, nq, ra, ga);
+}
+
 template <int K>
 static dqt_status launch_gf_matmul(const uint8_t* A, const uint8_t* B, uint8_t* out, uint32_t m, uint32_t n,
                                    uint32_t kd, uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
-    const size_t smem = 2ull * (1ull << (K * ra.w)) * sizeof(uint64_t) + (size_t)kGmK * (kGmRows + kGmCols) * 4;
-    const dim3 grid((n + kGmCols - 1) / kGmCols, (m + kGmRows - 1) / kGmRows);
-    if (nq == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_matmul<K, true>), grid, dim3(256), smem, s, A, B, out, m, n, kd, nq, ra,
-                           ga);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gf_matmul<K, false>), grid, dim3(256), smem, s, A, B, out, m, n, kd, nq,
-                           ra, ga);
+    // the largest tile per thread whose grid still has kGmWantTiles workgroups (about four
+    // waves per SIMD); the smaller tiles only where the larger ones leave SIMDs idle, so
+    // their grids stay below the largest tile's row limit times four
+    constexpr uint64_t kGmWantTiles = 1024;
+    auto tiles = [&](uint32_t rows, uint32_t cols) {
+        return (uint64_t)((n + cols - 1) / cols) * ((m + rows - 1) / rows);
+    };
+    if (tiles(64, 32) >= kGmWantTiles) launch_gf_matmul_tile<K, 4, 2>(A, B, out, m, n, kd, nq, ra, ga, s);
+    else if (tiles(32, 32) >= kGmWantTiles) launch_gf_matmul_tile<K, 2, 2>(A, B, out, m, n, kd, nq, ra, ga, s);
+    else if (tiles(32, 16) >= kGmWantTiles) launch_gf_matmul_tile<K, 2, 1>(A, B, out, m, n, kd, nq, ra, ga, s);
+    else launch_gf_matmul_tile<K, 1, 1>(A, B, out, m, n, kd, nq, ra, ga, s);
     DQT_LAUNCH_CHECK("dqt_gf_matmul_u8");
     return DQT_OK;
 }

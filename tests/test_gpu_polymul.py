@@ -367,14 +367,17 @@ def test_gf_dot_unaligned_operands(dqt, p, k):
 
 @pytest.mark.parametrize("p,k", [(3, 5), (7, 3), (2, 6), (13, 2), (3, 2), (5, 3)])
 def test_gf_matmul(dqt, p, k):
-    """Matrix products over GF(p^k) against the oracle: tiles of 64 x 32 with ragged edges, inner
-    dimensions within one step of 16, across several, and long enough for several packed sums
-    (n_q > 1) and folds, the all-(p-1) worst case, an empty inner dimension (zeros)."""
+    """Matrix products over GF(p^k) against the oracle: ragged edges on every tile size a thread
+    can take (4 x 2 outputs from 1024 tiles of 64 x 32 up, then 2 x 2, 2 x 1 and 1 x 1: the shapes
+    of 2050, 1030 and 520 rows reach the first three, the rest the last), inner dimensions within
+    one step of 16, across several, and long enough for several packed sums (n_q > 1) and folds,
+    the all-(p-1) worst case, an empty inner dimension (zeros)."""
     import torch
     P = inputs.irreducible(p, k)
     g = np.random.default_rng(600 + p * 10 + k)
     dev = device()
-    for m, kd, n in [(1, 1, 1), (64, 16, 32), (65, 17, 33), (130, 40, 70), (7, 300, 5), (3, 1000, 40)]:
+    for m, kd, n in [(1, 1, 1), (64, 16, 32), (65, 17, 33), (130, 40, 70), (7, 300, 5), (3, 1000, 40),
+                     (2050, 2, 1000), (1030, 17, 1000), (520, 3, 1000)]:
         a = g.integers(0, p, size=(m, kd, k), dtype=np.uint8)
         b = g.integers(0, p, size=(kd, n, k), dtype=np.uint8)
         a[0] = p - 1

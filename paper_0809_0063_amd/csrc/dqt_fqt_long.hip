@@ -19,9 +19,11 @@
 // with chunk C-1-c (or, within one wave, with chunk c + C/2) on the same
 // thread: every thread then has about the same number of terms, and one pair
 // per thread covers products of up to 4096 coefficients with at most 512
-// threads.  A product of more than 32 chunk pairs has a workgroup to itself;
-// shorter ones share a wave, as many as have a lane for each of their pairs
-// (64 / pairs of them), each with its own slot of LDS.  The
+// threads.  Products of up to 32 chunk pairs share a wave, as many as have a
+// lane for each of their pairs (64 / pairs of them), each with its own slot of
+// LDS; a larger product has a wave (up to 64 pairs) or a workgroup to itself.
+// The FQT kernel puts four waves of the first two kinds in a workgroup, which
+// share one correction table.  The
 // terms are taken G at a time: G values of a and the G+R-1 values of b that
 // meet them are read from LDS once and used G R times.  The operands sit in LDS
 // between zeros, so groups that overlap the ends of the operands need no test.

@@ -95,6 +95,21 @@ def test_argument_errors_before_any_device_call(D):
     assert lib.dqt_polymul_fqt_u8(None, 0, None, 4, 10, 3, 0, None, None) == D.DQT_E_INVALID
 
 
+def test_long_products_planned_without_device(D):
+    """An empty batch of long products is planned (block size, q, chunk size and launch shape from
+    the cost estimate, whose register counts fall back to a fixed value without a device) and
+    accepted; a forced block size whose sums cannot hold four block products is refused."""
+    lib = D.lib()
+    for p in (2, 3, 7, 31, 127):
+        for na, nb in ((65, 65), (70, 500), (500, 500), (1000, 1024), (4096, 4096), (3000, 70)):
+            assert lib.dqt_polymul_fqt_u8(None, na, None, nb, 0, p, 0, None, None) == D.DQT_OK, (p, na, nb)
+    for block in (2, 3, 4):
+        assert lib.dqt_polymul_fqt_u8(None, 500, None, 500, 0, 3, block, None, None) == D.DQT_OK, block
+    # blocks of four over F_31: q = 2^7 holds no block product of 4 (p - 1)^2 = 3600
+    assert lib.dqt_polymul_fqt_u8(None, 500, None, 500, 0, 31, 4, None, None) == D.DQT_E_BOUND
+    assert lib.dqt_polymul_fqt_u8(None, 500, None, 500, 0, 131, 0, None, None) == D.DQT_E_UNSUPPORTED
+
+
 def test_fgemm_workspace_sizes(D):
     # packed path: words of four entries for the rows of A and the columns of B
     ws = D.fgemm_workspace_size(3, 1024, 1024, 1024)

@@ -453,7 +453,11 @@ __global__ __launch_bounds__(512) void k_polymul_plain_long(const uint8_t* __res
 }  // namespace
 
 static constexpr uint32_t kLongMaxCoeffs = 4096;
-static constexpr uint32_t kLongTableBytes = 4096 * 2;   // the correction table, at the start of LDS
+
+// LDS bytes of the correction table at the start of a workgroup's LDS: its entries as 16-bit
+// words (64 for F_3 with windows of three residues, up to 4096; none where the correction is
+// computed), rounded to 16 bytes.
+static uint32_t long_table_bytes(const RedqArgs& ra) { return (ra.tab_entries * 2u + 15u) & ~15u; }
 
 // LDS layout and launch shape of a long product for one block size, group width G and chunk size R.
 struct LongShape {
@@ -463,7 +467,7 @@ struct LongShape {
     size_t smem;
 };
 
-static LongShape long_shape(uint32_t na, uint32_t nb, uint32_t bs, uint32_t G, uint32_t R) {
+static LongShape long_shape(uint32_t na, uint32_t nb, uint32_t bs, uint32_t G, uint32_t R, uint32_t lds_a) {
     LongShape h;
     h.Na = (na + bs - 1) / bs;
     h.Nb = (nb + bs - 1) / bs;
@@ -473,9 +477,9 @@ static LongShape long_shape(uint32_t na, uint32_t nb, uint32_t bs, uint32_t G, u
     h.pairs = (h.C + 1) / 2;   // one chunk pair per thread
     h.na_pad = (h.Na + G - 1) / G * G;
     h.nb_tot = kPad + h.Nb + kPad;
-    h.lds_b = kLongTableBytes + h.na_pad * 8;
+    h.lds_b = lds_a + h.na_pad * 8;
     h.lds_bnd = h.lds_b + ((gapped_n(long_gap_shift(R, G), h.nb_tot) * 8 + 15) & ~15u);
-    h.pp_bytes = (uint32_t)((h.lds_bnd - kLongTableBytes + (size_t)h.C * 8 + 15) & ~(size_t)15);
+    h.pp_bytes = (uint32_t)((h.lds_bnd - lds_a + (size_t)h.C * 8 + 15) & ~(size_t)15);
     if (h.pairs <= 64) {
         // Shared waves: 64 / pairs products per wave (a thread for each chunk pair; each product
         // given 64 / ppw threads, the spare ones only stage) and four waves per workgroup sharing
@@ -483,8 +487,8 @@ static LongShape long_shape(uint32_t na, uint32_t nb, uint32_t bs, uint32_t G, u
         // table per wave, LDS held the kernel to a few waves per CU at these sizes.
         uint32_t wpg = 4;
         h.ppw = h.pairs <= 32 ? 64 / h.pairs : 1;
-        while (h.ppw > 1 && kLongTableBytes + (size_t)h.ppw * h.pp_bytes > 65536) --h.ppw;
-        while (wpg > 1 && kLongTableBytes + (size_t)wpg * h.ppw * h.pp_bytes > 65536) wpg /= 2;
+        while (h.ppw > 1 && lds_a + (size_t)h.ppw * h.pp_bytes > 65536) --h.ppw;
+        while (wpg > 1 && lds_a + (size_t)wpg * h.ppw * h.pp_bytes > 65536) wpg /= 2;
         h.tpp = 64 / h.ppw;
         h.ppg = wpg * h.ppw;
         h.threads = 64 * wpg;
@@ -494,7 +498,7 @@ static LongShape long_shape(uint32_t na, uint32_t nb, uint32_t bs, uint32_t G, u
         h.ppw = 1;
         h.ppg = 1;
     }
-    h.smem = kLongTableBytes + (size_t)h.ppg * h.pp_bytes;
+    h.smem = lds_a + (size_t)h.ppg * h.pp_bytes;
     return h;
 }
 
@@ -536,6 +540,22 @@ static int long_regs(uint32_t bs, uint32_t G, uint32_t R, bool one, bool f3) {
     return regs[(((bs - 2) * 2 + (G == 8)) * 2 + (R == 8)) * 4 + (one ? 2 : 0) + (f3 ? 1 : 0)];
 }
 
+// Vector registers per lane of the plain kernel's two instances (as long_regs).
+static int plain_long_regs(bool one) {
+    static const std::array<int, 2> regs = [] {
+        std::array<int, 2> r{128, 128};
+        auto put = [&](int idx, const void* fn) {
+            hipFuncAttributes at;
+            if (hipFuncGetAttributes(&at, fn) == hipSuccess && at.numRegs > 0) r[idx] = at.numRegs;
+            else (void)hipGetLastError();
+        };
+        put(0, reinterpret_cast<const void*>(&k_polymul_plain_long<false>));
+        put(1, reinterpret_cast<const void*>(&k_polymul_plain_long<true>));
+        return r;
+    }();
+    return regs[one ? 1 : 0];
+}
+
 // Block size, q, L, the group width G and the chunk size R of a long product:
 // the smallest estimated cost over block sizes 2..4 (the 2 BS - 1 residues of a
 // block stay within the eight byte lanes of one word) and chunks of R = 4 or 8
@@ -544,15 +564,16 @@ static int long_regs(uint32_t bs, uint32_t G, uint32_t R, bool one, bool f3) {
 // estimate counts what section 5.3's model counts, block products and
 // reductions, the way the kernel runs them, in units of one lane's binary64 FMA:
 // per wave (or per share of a wave, for products of up to 32 chunk pairs), about
-// Na / G term groups per phase of G R FMAs and G + R - 1 B words read from LDS,
-// and a REDQ_{2BS-1} of each of the R sums at every L-th term and at the end
-// (about 9 (2 BS - 1) FMAs' worth each); that divided by the waves per SIMD
-// that registers and LDS let the launch keep resident (counted up to three: at
-// these sizes the kernel waits on LDS and memory, and fewer waves hide less of
-// it); plus the product's own loads and stores (12 per 64 bytes) and 24 for its
+// Na / G term groups per phase of G R FMAs and G + R - 1 B words read from LDS
+// (about 2 FMAs' worth each), and a REDQ_{2BS-1} of each of the R sums at every
+// L-th term and at the end (about 12 (2 BS - 1) each); that divided by the
+// waves per SIMD that registers and LDS let the launch keep resident (counted
+// up to four: the kernel waits on LDS and memory, and fewer waves hide less of
+// it); plus the product's own loads and stores (19 per 64 bytes) and 8 for its
 // set-up.  The weights are a least-squares fit of measured times over F_3
-// (n = 65 .. 2048, both chunk sizes, both walks, every block size); the choice
-// they give was within 10% of the measured fastest at every measured n.
+// (21 lengths from 65 to 4096, both chunk sizes, both walks, every block size);
+// the choice they give was within 10% of the measured fastest at every one (2%
+// on average).
 dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, uint32_t* bs_out, uint32_t* b_out,
                          uint32_t* L_out, uint32_t* G_out, uint32_t* R_out, bool* one_out) {
     if (p > 127) return DQT_E_UNSUPPORTED;
@@ -566,8 +587,10 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
         if (nq < 4) continue;
         const uint32_t G = nq >= 8 ? 8 : 4;
         const uint32_t L = (uint32_t)(nq / G) * G;
+        RedqArgs ra;
+        if (make_redq_args(p, b, 2 * bs - 1, (2 * bs - 1) * b, &ra) != DQT_OK) continue;
         for (uint32_t R = 4; R <= 8; R += 4) {
-            const LongShape h = long_shape(na, nb, bs, G, R);
+            const LongShape h = long_shape(na, nb, bs, G, R, long_table_bytes(ra));
             if (h.pairs > 512 || h.threads > 512 || h.smem > 65536) continue;
             // waves per product (a share of one below 65 chunk pairs)
             const double waves = h.pairs <= 64 ? 1.0 / h.ppw : h.threads / 64.0;
@@ -586,13 +609,13 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
                 const int regs = long_regs(bs, G, R, one != 0, long_f3(p, bs, b, G));
                 const uint32_t by_regs = 512u / (uint32_t)((regs + 7) / 8 * 8);   // waves per SIMD
                 const uint32_t groups_cu = std::min<uint32_t>((uint32_t)((160u * 1024u) / h.smem), 4u * by_regs / wpg);
-                const double resident = std::max(0.25, std::min(3.0, groups_cu * wpg / 4.0));
+                const double resident = std::max(0.25, std::min(4.0, groups_cu * wpg / 4.0));
                 const double gr = one ? std::ceil((span + R) / G) + 2.0 : groups;
                 const double reds = one ? 2.0 * R : reductions;
-                const double cost = waves * 3.0 / resident *
-                                        (gr * R * G + 0.699 * gr * (G + R - 1 + (one ? G : 0)) +
-                                         9.24 * reds * (2 * bs - 1)) +
-                                    12.3 * io + 23.5;
+                const double cost = waves * 4.0 / resident *
+                                        (gr * R * G + 2.06 * gr * (G + R - 1 + (one ? G : 0)) +
+                                         12.35 * reds * (2 * bs - 1)) +
+                                    18.7 * io + 8.5;
                 if (cost < best) {
                     best = cost;
                     best_bs = bs;
@@ -611,11 +634,24 @@ dqt_status fqt_long_plan(uint32_t p, uint32_t na, uint32_t nb, uint32_t block, u
 }
 
 // Workgroups per CU that the LDS (160 KiB) and the wave slots allow.
-static unsigned groups_per_cu(size_t smem, unsigned threads) {
+// Workgroups per CU that the LDS (160 KiB), the wave slots and the registers
+// (512 per lane of a SIMD, allocated in granules of 8) allow.
+static unsigned groups_per_cu(size_t smem, unsigned threads, int regs) {
+    const unsigned waves = (threads + 63) / 64;
     const unsigned by_lds = (unsigned)((160u * 1024u) / (smem ? smem : 1));
-    const unsigned by_waves = 32u / ((threads + 63) / 64);
-    const unsigned n = by_lds < by_waves ? by_lds : by_waves;
+    const unsigned by_waves = 32u / waves;
+    const unsigned by_regs = 4u * std::min(8u, 512u / (unsigned)((regs + 7) / 8 * 8)) / waves;
+    const unsigned n = std::min(by_lds, std::min(by_waves, by_regs));
     return n ? n : 1;
+}
+
+// A grid of workgroups that loop over `units` (groups of products): no more than
+// fit the device at once, and as many units for each of them (without it, e.g.
+// 2,048 units on 1,280 workgroups of which 1,024 fit would leave a tail).
+static unsigned balanced_grid(uint64_t units, unsigned per_cu) {
+    const uint64_t cap = stream_grid(units, 1, per_cu);
+    const uint64_t rounds = (units + cap - 1) / cap;
+    return (unsigned)((units + rounds - 1) / rounds);
 }
 
 dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uint32_t nb, uint64_t count, uint32_t p,
@@ -633,14 +669,15 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     g.nout = na + nb - 1;
     g.b = b;
     g.L = L;
-    const LongShape h = long_shape(na, nb, bs, G, R);
+    const uint32_t lds_a = long_table_bytes(g.ra);
+    const LongShape h = long_shape(na, nb, bs, G, R, lds_a);
     g.Na = h.Na;
     g.Nb = h.Nb;
     g.NW = h.NW;
     g.C = h.C;
     g.na_pad = h.na_pad;
     g.nb_tot = h.nb_tot;
-    g.lds_a = kLongTableBytes;
+    g.lds_a = lds_a;
     g.lds_b = h.lds_b;
     g.lds_bnd = h.lds_bnd;
     g.pp_bytes = h.pp_bytes;
@@ -650,7 +687,8 @@ dqt_status fqt_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, uin
     const unsigned threads = h.threads;
     const size_t smem = h.smem;
     if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
-    const unsigned grid = stream_grid((count + g.ppg - 1) / g.ppg, 1, groups_per_cu(smem, threads));
+    const int regs = long_regs(bs, G, R, one, long_f3(p, bs, b, G));
+    const unsigned grid = balanced_grid((count + g.ppg - 1) / g.ppg, groups_per_cu(smem, threads, regs));
     // the F_3 instances with a compile-time q and residue width, else the run-time form
     if (long_f3(p, bs, b, G)) {
 #define DQT_LONG_F3(BSV, QBV, RV, ONEV)                                                                    \
@@ -717,7 +755,7 @@ dqt_status plain_long_enqueue(const uint8_t* A, uint32_t na, const uint8_t* B, u
     }
     const size_t smem = (size_t)ppw * slot_words * 4;
     if (threads > 512 || smem > 65536) return DQT_E_UNSUPPORTED;
-    const unsigned grid = stream_grid((count + ppw - 1) / ppw, 1, groups_per_cu(smem, threads));
+    const unsigned grid = balanced_grid((count + ppw - 1) / ppw, groups_per_cu(smem, threads, plain_long_regs(pairs <= 64)));
     // the single walk pays off while the chunk pairs fit one wave (measured from 65 to 4096
     // coefficients, as for the FQT kernel); with more, the two loops per lane are faster
     if (pairs <= 64)

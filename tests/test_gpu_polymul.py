@@ -465,6 +465,24 @@ def test_long_products_several_per_workgroup(dqt, p):
                 assert (h[:32] == 0xCD).all() and (h[32 + count * nout:] == 0xCD).all(), (p, na, nb, count)
 
 
+@pytest.mark.parametrize("p", [3, 7])
+def test_long_products_several_rounds(dqt, p):
+    """Batches larger than what fits the device at once, so that every workgroup loops over several
+    groups of products (short products several to a wave and four waves to a workgroup; long ones a
+    workgroup each), for the FQT and the plain comparator: a sample of products against the oracle,
+    the last products of the batch among them."""
+    g = np.random.default_rng(7700 + p)
+    for n, count in [(65, 200003), (200, 40001), (1000, 3001)]:
+        a = g.integers(0, p, size=(count, n), dtype=np.uint8)
+        b = g.integers(0, p, size=(count, n), dtype=np.uint8)
+        pick = np.unique(np.concatenate([g.choice(count, size=150, replace=False), np.arange(count - 5, count)]))
+        ref = O.polymul(a[pick], b[pick], p)
+        da, db = to_dev(a), to_dev(b)
+        for run in (dqt.polymul_fqt_u8, dqt.polymul_plain_u8):
+            got = to_host(run(da, db, p))
+            assert (got[pick] == ref).all(), (p, n, count, run.__name__)
+
+
 def test_fqt_long_block_sizes_and_limits(dqt):
     """Every block size of the long path gives the oracle's bytes; the limits are refused."""
     p, na, nb, count = 3, 777, 500, 20

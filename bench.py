@@ -364,12 +364,12 @@ def fqt_long_model(p, n, bs):
 
 
 def bench_fqt_long(D, inputs, torch, dev):
-    """Long products over F_3 (n = 128 .. 4096 coefficients, n = 500 the example of section 5.3): FQT by
+    """Long products over F_3 (n = 65 .. 4096 coefficients, n = 500 the example of section 5.3): FQT by
     blocks, Karatsuba levels over FQT base products (from n = 500), and the plain per-coefficient
     product, same batch."""
     out = {}
     p = 3
-    for n in (128, 256, 500, 1024, 2048, 4096):
+    for n in (65, 96, 128, 192, 256, 384, 500, 1024, 2048, 4096):
         count = max(2048, (1 << 34) // (n * n))
         a, b = inputs.polymul_pairs(count, n, p, seed=inputs.SEED_POLYMUL + n)
         da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)

@@ -375,12 +375,16 @@ def bench_fqt_long(D, inputs, torch, dev):
         da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
         o = torch.empty((count, 2 * n - 1), dtype=torch.uint8, device=dev)
         row = {"count": count}
-        blocks = (0, 2, 3, 4) if n in (500, 1024, 2048) else (0,)
+        blocks = (0, 2, 3, 4) if n in (500, 1024, 2048) else (0, 2, 3)
         for blk in blocks:
             s = timed_loop(lambda: D.polymul_fqt_u8(da, db, p, block=blk, out=o), 5, 2, torch)
             key = "fqt" if blk == 0 else f"fqt_block{blk}"
             row[key] = {"products_s": round(count / s, 1), "us_per_call": round(s * 1e6, 1),
                         "coeff_products_s": round(count * n * n / s, 1)}
+            if blk:
+                # block products (one binary64 FMA each) per second over the FP64 vector peak
+                nblk = -(-n // blk)
+                row[key]["fma_frac"] = round(count * nblk * nblk / s / PEAK_F64_FMA, 4)
         if n >= 500:
             # Karatsuba levels over F_p with FQT base products (workspace allocated once, outside the loop)
             for lv in ((1, 2) if n < 4096 else (1, 2, 3)):

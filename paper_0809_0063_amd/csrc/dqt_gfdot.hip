@@ -223,13 +223,15 @@ static void launch_gf_dot_g(const uint8_t* A, const uint8_t* B, uint8_t* out, ui
                            n, nq, ra, ga);
 }
 
-// Lanes per dot product: about one per chunk of eight records, at most a wave.
+// Lanes per dot product: about one per four chunks of eight records, at most a wave (with one
+// chunk per lane, the combining of the lanes' sums and the fold cost more than they spread:
+// 65,536 dot products of 128 elements over GF(3^5) took 33 us on 16 lanes each, 30 us on 4).
 template <int K>
 static dqt_status launch_gf_dot(const uint8_t* A, const uint8_t* B, uint8_t* out, uint64_t count, uint32_t n,
                                 uint32_t nq, const RedqArgs& ra, const GfArgs& ga, hipStream_t s) {
     const uint32_t nch = (n + 7) / 8;
-    if (nch > 32) launch_gf_dot_g<K, 64>(A, B, out, count, n, nq, ra, ga, s);
-    else if (nch > 8) launch_gf_dot_g<K, 16>(A, B, out, count, n, nq, ra, ga, s);
+    if (nch > 64) launch_gf_dot_g<K, 64>(A, B, out, count, n, nq, ra, ga, s);
+    else if (nch > 16) launch_gf_dot_g<K, 16>(A, B, out, count, n, nq, ra, ga, s);
     else if (nch > 2) launch_gf_dot_g<K, 4>(A, B, out, count, n, nq, ra, ga, s);
     else launch_gf_dot_g<K, 1>(A, B, out, count, n, nq, ra, ga, s);
     DQT_LAUNCH_CHECK("dqt_gf_dot_u8");

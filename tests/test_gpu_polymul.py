@@ -319,9 +319,11 @@ def test_fqt_karatsuba_products(dqt, p):
 
 
 @pytest.mark.parametrize("p,k,n", [(3, 5, 1), (3, 5, 7), (7, 3, 1), (7, 3, 9), (7, 3, 10), (7, 3, 100), (3, 2, 1000),
-                                   (3, 2, 20000), (2, 6, 33), (5, 4, 17), (13, 3, 5)])
+                                   (3, 2, 20000), (2, 6, 33), (5, 4, 17), (13, 3, 5), (3, 5, 128), (7, 3, 129),
+                                   (3, 5, 300)])
 def test_gf_dot_products(dqt, p, k, n):
-    """FGDP dot products: packed sums of n_q products, one REDQ and two lookups per word."""
+    """FGDP dot products: packed sums of n_q products, one REDQ and two lookups per word; lengths on
+    each number of lanes per dot product (1 up to 16 elements, 4 up to 128, 16 up to 512, then 64)."""
     P = inputs.irreducible(p, k)
     g = np.random.default_rng(p * 100 + k * 10 + n)
     count = 257 if n < 1000 else 17
